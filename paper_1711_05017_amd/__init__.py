@@ -1,0 +1,26 @@
+"""MI355X-native geometric-energy correlation (skeletal densities, 3D FFT).
+
+The compute path lives in libga.so (HIP kernels for gfx950 behind the C ABI of
+include/ga.h); ``paper_1711_05017_amd.ga`` is its ctypes binding.
+"""
+
+from . import ga  # noqa: F401
+from .ga import (  # noqa: F401
+    GA_C2R,
+    GA_FIELDS,
+    GA_R2C,
+    GA_SINGLE,
+    GaError,
+    Plan,
+    ga_correlate,
+    ga_energy_fields,
+    ga_fft3d,
+    ga_force_torque,
+    ga_splat,
+    ga_supported_n,
+)
+
+
+def lib():
+    """The loaded libga.so (raises when it has not been built)."""
+    return ga.load()

@@ -1,0 +1,231 @@
+// ga_fft.hpp -- wavefront-resident mixed-radix FFT engine for gfx950.
+//
+// One length-N complex transform is owned by L = N/E lanes of a single
+// 64-lane wavefront; each lane holds E elements per stage. Stages are
+// Stockham autosort steps (radix 2, 3, 4 or 8) computed in place in an LDS
+// region: every lane of the wave reads all its inputs, then writes all its
+// outputs, so no workgroup barrier is needed between stages (a wave executes
+// its LDS instructions in order). Twiddles depend only on the lane's position
+// in its transform, so they are loaded once per kernel into registers.
+//
+// The transform computes X(k) = sum_n x(n) exp(DIR 2 pi i k n / N) with
+// DIR = -1 (forward) or +1 (inverse, unnormalised): the discrete sums of
+// Sec. 3.2 (eq. 7a/7b), by the Cooley-Tukey factorisation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ga {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {  // a * conj(b)
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// a * w for DIR = -1, a * conj(w) for DIR = +1 (w = exp(-2 pi i m / N) from the table).
+template <int DIR>
+__device__ __forceinline__ float2 twmul(float2 a, float2 w) {
+  if constexpr (DIR < 0) return cmul(a, w);
+  else return cmulc(a, w);
+}
+// a * (DIR i)
+template <int DIR>
+__device__ __forceinline__ float2 mul_di(float2 a) {
+  if constexpr (DIR < 0) return make_float2(a.y, -a.x);
+  else return make_float2(-a.y, a.x);
+}
+
+// Compiler barrier for wave-synchronous LDS use: memory operations are not
+// moved across it; the hardware keeps a wave's LDS operations in order.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---- butterflies: in-register DFTs of size R, exp(DIR 2 pi i / R) --------
+template <int R, int DIR> struct Bfly;
+
+template <int DIR> struct Bfly<2, DIR> {
+  __device__ __forceinline__ static void run(float2* v) {
+    const float2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <int DIR> struct Bfly<3, DIR> {
+  __device__ __forceinline__ static void run(float2* v) {
+    constexpr float H3 = 0.86602540378443864676f;  // sin(2 pi / 3)
+    const float2 a0 = v[0];
+    const float2 t = cadd(v[1], v[2]);
+    const float2 d = csub(v[1], v[2]);
+    const float2 m = make_float2(a0.x - 0.5f * t.x, a0.y - 0.5f * t.y);
+    const float2 r = cscale(mul_di<DIR>(d), H3);  // DIR i sqrt(3)/2 (a1 - a2)
+    v[0] = cadd(a0, t);
+    v[1] = cadd(m, r);
+    v[2] = csub(m, r);
+  }
+};
+
+template <int DIR> struct Bfly<4, DIR> {
+  __device__ __forceinline__ static void run(float2* v) {
+    const float2 t0 = cadd(v[0], v[2]);
+    const float2 t1 = csub(v[0], v[2]);
+    const float2 t2 = cadd(v[1], v[3]);
+    const float2 t3 = mul_di<DIR>(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+  }
+};
+
+template <int DIR> struct Bfly<8, DIR> {
+  __device__ __forceinline__ static void run(float2* v) {
+    constexpr float C8 = 0.70710678118654752440f;  // cos(pi / 4)
+    float2 e[4] = {v[0], v[2], v[4], v[6]};
+    float2 o[4] = {v[1], v[3], v[5], v[7]};
+    Bfly<4, DIR>::run(e);
+    Bfly<4, DIR>::run(o);
+    // o[k] *= exp(DIR 2 pi i k / 8)
+    const float2 o1 = make_float2(C8 * (o[1].x - DIR * o[1].y), C8 * (o[1].y + DIR * o[1].x));
+    const float2 o2 = mul_di<DIR>(o[2]);
+    const float2 o3 = make_float2(C8 * (-o[3].x - DIR * o[3].y), C8 * (-o[3].y + DIR * o[3].x));
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
+  }
+};
+
+// ---- radix schedules --------------------------------------------------------
+// E elements per lane; every radix divides E; the product of radices is N.
+template <int N> struct Shape;
+#define GA_SHAPE(NN, EE, NSTAGES, ...)                       \
+  template <> struct Shape<NN> {                             \
+    static constexpr int E = EE;                             \
+    static constexpr int NST = NSTAGES;                      \
+    static constexpr int R[NSTAGES] = {__VA_ARGS__};         \
+  };
+GA_SHAPE(16, 4, 2, 4, 4)
+GA_SHAPE(24, 12, 3, 3, 2, 4)
+GA_SHAPE(32, 8, 2, 8, 4)
+GA_SHAPE(48, 12, 3, 3, 4, 4)
+GA_SHAPE(64, 8, 2, 8, 8)
+GA_SHAPE(96, 24, 3, 3, 4, 8)
+GA_SHAPE(128, 8, 3, 8, 4, 4)
+GA_SHAPE(192, 24, 3, 3, 8, 8)
+GA_SHAPE(256, 8, 3, 8, 8, 4)
+GA_SHAPE(384, 24, 4, 3, 8, 8, 2)
+GA_SHAPE(512, 8, 3, 8, 8, 8)
+#undef GA_SHAPE
+
+template <int N> constexpr int lanes_per_fft() { return N / Shape<N>::E; }
+template <int N> constexpr int ffts_per_wave() { return 64 / lanes_per_fft<N>(); }
+template <int N> constexpr int ns_before(int s) {
+  int p = 1;
+  for (int i = 0; i < s; ++i) p *= Shape<N>::R[i];
+  return p;
+}
+template <int N> constexpr int tw_off(int s) {
+  int o = 0;
+  for (int i = 1; i < s; ++i) o += (Shape<N>::E / Shape<N>::R[i]) * (Shape<N>::R[i] - 1);
+  return o;
+}
+template <int N> constexpr int tw_count() { return tw_off<N>(Shape<N>::NST); }
+
+template <int N> struct Twiddles {
+  float2 v[tw_count<N>()];
+};
+
+// Per-lane twiddles: stage s > 0, butterfly b, element r uses
+// exp(-2 pi i r k / (NS R)) with k = j mod NS, j = lane + L b.
+template <int N, int S>
+__device__ __forceinline__ void load_twiddles_stage(Twiddles<N>& tw, const float2* __restrict__ table, int lane) {
+  if constexpr (S < Shape<N>::NST) {
+    if constexpr (S > 0) {
+      constexpr int E = Shape<N>::E, L = N / E, R = Shape<N>::R[S], NS = ns_before<N>(S), NB = E / R;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int j = lane + L * b;
+        const int k = j % NS;
+#pragma unroll
+        for (int r = 1; r < R; ++r) tw.v[tw_off<N>(S) + b * (R - 1) + r - 1] = table[r * k * (N / (NS * R))];
+      }
+    }
+    load_twiddles_stage<N, S + 1>(tw, table, lane);
+  }
+}
+template <int N>
+__device__ __forceinline__ void load_twiddles(Twiddles<N>& tw, const float2* __restrict__ table, int lane) {
+  load_twiddles_stage<N, 0>(tw, table, lane);
+}
+
+// One Stockham stage, in place in buf (element stride es). Stage 0 takes its
+// inputs from ld(pos) and the last stage hands its outputs to st(pos, v);
+// positions are natural indices of the transform.
+template <int N, int S, int DIR, class Ld, class St>
+__device__ __forceinline__ void fft_stage(int lane, const Twiddles<N>& tw, float2* buf, int es, Ld& ld, St& st) {
+  constexpr int E = Shape<N>::E, L = N / E, R = Shape<N>::R[S], NS = ns_before<N>(S), NB = E / R;
+  constexpr bool first = (S == 0), last = (S == Shape<N>::NST - 1);
+  float2 v[E];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = lane + L * b;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int pos = j + r * (N / R);
+      if constexpr (first) v[b * R + r] = ld(pos);
+      else v[b * R + r] = buf[pos * es];
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    if constexpr (S > 0) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[b * R + r] = twmul<DIR>(v[b * R + r], tw.v[tw_off<N>(S) + b * (R - 1) + r - 1]);
+    }
+    Bfly<R, DIR>::run(&v[b * R]);
+  }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = lane + L * b;
+    const int k = j % NS;
+    const int base = (j - k) * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int pos = base + r * NS;
+      if constexpr (last) st(pos, v[b * R + r]);
+      else buf[pos * es] = v[b * R + r];
+    }
+  }
+  wave_sync();
+  if constexpr (!last) fft_stage<N, S + 1, DIR>(lane, tw, buf, es, ld, st);
+}
+
+// Transform of length N on the L lanes [0, L) of this transform (`lane` is
+// the index within the transform), data in buf[pos * es].
+template <int N, int DIR, class Ld, class St>
+__device__ __forceinline__ void fft_lanes(int lane, const Twiddles<N>& tw, float2* buf, int es, Ld ld, St st) {
+  fft_stage<N, 0, DIR>(lane, tw, buf, es, ld, st);
+}
+
+template <int N, int DIR>
+__device__ __forceinline__ void fft_inplace(int lane, const Twiddles<N>& tw, float2* buf, int es) {
+  auto ld = [&](int pos) { return buf[pos * es]; };
+  auto st = [&](int pos, float2 v) { buf[pos * es] = v; };
+  fft_stage<N, 0, DIR>(lane, tw, buf, es, ld, st);
+}
+
+}  // namespace ga

@@ -1,0 +1,270 @@
+"""GPU parity: every C-ABI call against the FP64 oracle on the same seeded inputs.
+
+Tolerances (relative L2 over all compared elements): 1e-5 for densities,
+spectra and energy fields, 1e-4 for forces and torques. Small grids are
+compared element by element; the full-size workloads (128^3) on sampled
+outputs that the oracle evaluates one by one.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+FIELD_TOL = 1e-5
+FORCE_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def G():
+    import paper_1711_05017_amd as pkg
+
+    pkg.lib()
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    return pkg
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _part(n, seed, npts, rlo=1.0, rhi=3.0, conf=None):
+    return synth.random_part(seed, n, npts, rlo, rhi, conf_radius=conf)
+
+
+# ---------------------------------------------------------------------------
+# splat
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,npts,rot", [(16, 30, False), (32, 200, False), (48, 333, True), (96, 700, True),
+                                        (128, 2000, True), (192, 1500, True)])
+def test_splat_matches_oracle(G, n, npts, rot):
+    p = _part(n, 1000 + n, npts, 0.5, 4.0)
+    plan = G.Plan(n)
+    if rot:
+        R = synth.shoemake_rotations(7 + n, 1)[0]
+        c = p.ref_point()
+    else:
+        R, c = None, None
+    got = G.ga_splat(plan, _dev(p.xyzr), _dev(p.w), R=R, c=c, channels=4).cpu().numpy()
+    if rot:
+        y = O.place(p.xyzr[:, :3], R, c)
+    else:
+        y = p.xyzr[:, :3].astype(np.float64)
+    u = O.splat(y, p.xyzr[:, 3], p.w, n)
+    ref = np.concatenate([u[None], O.moment_channels(u)])
+    assert O.rel_l2(got[0], ref[0]) < FIELD_TOL
+    for ch in range(1, 4):
+        assert O.rel_l2(got[ch], ref[ch]) < FIELD_TOL
+
+
+def test_splat_edge_cases(G):
+    n = 16
+    plan = G.Plan(n)
+    # empty input gives zeros
+    z = G.ga_splat(plan, torch.zeros((0, 4), device="cuda"), torch.zeros(0, device="cuda"))
+    assert float(z.abs().max()) == 0.0
+    # radius below one voxel is raised to one; a radius reaching n/2 is dropped;
+    # negative weights and coordinates outside [0, n) wrap
+    xyzr = np.array([[3.0, 4.0, 5.0, 0.3], [-1.25, 17.5, 8.0, 2.5], [8.0, 8.0, 8.0, 8.0], [15.9, 0.1, 7.7, 3.0]],
+                    np.float32)
+    w = np.array([1.0, -0.5, 1.0, 2.0], np.float32)
+    got = G.ga_splat(plan, _dev(xyzr), _dev(w)).cpu().numpy()[0]
+    keep = [0, 1, 3]
+    ref = O.splat(xyzr[keep, :3].astype(np.float64), xyzr[keep, 3], w[keep], n)
+    assert O.rel_l2(got, ref) < FIELD_TOL
+    # invalid arguments are rejected synchronously
+    with pytest.raises(G.GaError):
+        G.ga_splat(plan, _dev(xyzr), _dev(w), sigma=0.0)
+    with pytest.raises(G.GaError):
+        G.ga_splat(plan, _dev(xyzr), _dev(w), channels=2)
+    with pytest.raises(G.GaError):
+        G.ga_splat(plan, _dev(xyzr), _dev(w), R=np.diag([1.0, 1.0, -1.0]), c=[0, 0, 0])
+
+
+# ---------------------------------------------------------------------------
+# 3D FFT
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [16, 24, 32, 48, 64, 96, 128, 192])
+def test_fft3d_r2c_and_c2r_match_oracle(G, n):
+    rng = np.random.default_rng(n)
+    batch = 2
+    x = rng.standard_normal((batch, n, n, n)).astype(np.float32)
+    plan = G.Plan(n, max_batch=batch)
+    X = G.ga_fft3d(plan, G.GA_R2C, _dev(x)).cpu().numpy()
+    for b in range(batch):
+        ref = O.rfft3(x[b].astype(np.float64))
+        assert O.rel_l2(X[b], ref) < FIELD_TOL
+    # C2R of an arbitrary (not Hermitian) half spectrum
+    H = (rng.standard_normal((batch, n, n, n // 2 + 1)) + 1j * rng.standard_normal((batch, n, n, n // 2 + 1)))
+    H = H.astype(np.complex64)
+    y = G.ga_fft3d(plan, G.GA_C2R, _dev(H)).cpu().numpy()
+    for b in range(batch):
+        ref = O.irfft3(H[b].astype(np.complex128))
+        assert O.rel_l2(y[b], ref) < FIELD_TOL
+
+
+def test_fft3d_roundtrip_and_batch_limit(G):
+    n = 32
+    plan = G.Plan(n, max_batch=3)
+    x = np.random.default_rng(1).standard_normal((3, n, n, n)).astype(np.float32)
+    y = G.ga_fft3d(plan, G.GA_C2R, G.ga_fft3d(plan, G.GA_R2C, _dev(x))).cpu().numpy()
+    assert np.abs(y - x).max() < 1e-5 * np.abs(x).max()
+    with pytest.raises(G.GaError):
+        G.ga_fft3d(plan, G.GA_R2C, _dev(np.zeros((4, n, n, n), np.float32)))
+
+
+# ---------------------------------------------------------------------------
+# correlation
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [16, 32, 48, 96])
+def test_correlate_from_oracle_spectra(G, n):
+    A = _part(n, 2000 + n, 8 * n)
+    B = _part(n, 3000 + n, 8 * n)
+    d = O.pair_fields(A.xyzr, A.w, B.xyzr, B.w, np.eye(3, dtype=np.float32), B.ref_point(), n,
+                      want_torque=False)
+    h = n // 2 + 1
+    Ah = _dev(d["Ahat"][:, :, :h].astype(np.complex64))
+    Bh = _dev(np.stack([d["Bhat"][:, :, :h], np.conj(d["Bhat"][:, :, :h])]).astype(np.complex64))
+    plan = G.Plan(n, max_batch=2)
+    E = G.ga_correlate(plan, Ah, Bh).cpu().numpy()
+    assert O.rel_l2(E[0], d["E"]) < FIELD_TOL
+    # second member: conj(B) correlates with the reflected density
+    ref2 = np.real(O.ifft3(d["Ahat"] * d["Bhat"]))
+    assert O.rel_l2(E[1], ref2) < FIELD_TOL
+
+
+@pytest.mark.parametrize("n,npts,nrot", [(32, 200, 3), (48, 300, 5), (96, 900, 3), (192, 1200, 2)])
+def test_energy_fields_fused_path(G, n, npts, nrot):
+    A = _part(n, 4000 + n, npts, 1.0, 4.0)
+    B = _part(n, 5000 + n, npts, 1.0, 4.0)
+    R = synth.shoemake_rotations(6000 + n, nrot)
+    cB = B.ref_point()
+    plan = G.Plan(n, max_batch=nrot)
+    uA = G.ga_splat(plan, _dev(A.xyzr), _dev(A.w))
+    Ahat = G.ga_fft3d(plan, G.GA_R2C, uA)[0]
+    E = G.ga_energy_fields(plan, Ahat, _dev(B.xyzr), _dev(B.w), _dev(R), cB).cpu().numpy()
+    uA_ref = O.splat(A.xyzr[:, :3].astype(np.float64), A.xyzr[:, 3], A.w, n)
+    for r in range(nrot):
+        uB_ref = O.splat(O.place(B.xyzr[:, :3], R[r], cB), B.xyzr[:, 3], B.w, n)
+        assert O.rel_l2(E[r], O.energy_field(uA_ref, uB_ref)) < FIELD_TOL, r
+
+
+def test_c1_workload_end_to_end(G):
+    a = synth.config_c1()
+    n = a.n
+    plan = G.Plan(n, max_batch=4)
+    uA = G.ga_splat(plan, _dev(a.A.xyzr), _dev(a.A.w), sigma=a.sigma)
+    Ahat = G.ga_fft3d(plan, G.GA_R2C, uA)[0]
+    E = G.ga_energy_fields(plan, Ahat, _dev(a.B.xyzr), _dev(a.B.w), _dev(a.rotations), a.cB, a.sigma).cpu().numpy()
+    d = O.pair_fields(a.A.xyzr, a.A.w, a.B.xyzr, a.B.w, a.rotations[0], a.cB, n, a.sigma)
+    assert O.rel_l2(E[0], d["E"]) < FIELD_TOL
+    uB4 = G.ga_splat(plan, _dev(a.B.xyzr), _dev(a.B.w), R=a.rotations[0], c=a.cB, sigma=a.sigma, channels=4)
+    Bhat4 = G.ga_fft3d(plan, G.GA_R2C, uB4)
+    t = _dev(a.poses)
+    ref = np.concatenate([O.lattice_read(d["E"], a.poses)[:, None], O.lattice_read(d["F"], a.poses).T,
+                          O.lattice_read(d["tau"], a.poses).T], 1)
+    for mode in (G.GA_FIELDS, G.GA_SINGLE):
+        got = G.ga_force_torque(plan, Ahat, Bhat4, t, mode).cpu().numpy()
+        assert O.rel_l2(got[:, 0], ref[:, 0]) < FIELD_TOL
+        assert O.rel_l2(got[:, 1:4], ref[:, 1:4]) < FORCE_TOL
+        assert O.rel_l2(got[:, 4:7], ref[:, 4:7]) < FORCE_TOL
+
+
+# ---------------------------------------------------------------------------
+# force / torque
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,npts", [(24, 120), (48, 400), (96, 1000)])
+def test_force_torque_fields_and_single(G, n, npts):
+    A = _part(n, 7000 + n, npts, 1.0, 4.0)
+    B = _part(n, 8000 + n, npts, 1.0, 4.0, conf=n / 6)
+    R = synth.shoemake_rotations(9000 + n, 1)[0]
+    cB = B.ref_point()
+    d = O.pair_fields(A.xyzr, A.w, B.xyzr, B.w, R, cB, n)
+    plan = G.Plan(n, max_batch=4)
+    Ahat = G.ga_fft3d(plan, G.GA_R2C, G.ga_splat(plan, _dev(A.xyzr), _dev(A.w)))[0]
+    Bhat4 = G.ga_fft3d(plan, G.GA_R2C, G.ga_splat(plan, _dev(B.xyzr), _dev(B.w), R=R, c=cB, channels=4))
+    rng = np.random.default_rng(n)
+    lat = (n // 2 + rng.integers(-n // 4, n // 4, (40, 3))).astype(np.float32)
+    lat[0] = [0, 0, 0]
+    lat[1] = [n - 1, n - 1, n - 1]
+    frac = (lat[:20] + rng.random((20, 3))).astype(np.float32)
+    fields = np.concatenate([d["E"][None], d["F"], d["tau"]])
+    for mode, poses in ((G.GA_FIELDS, lat), (G.GA_FIELDS, frac), (G.GA_SINGLE, lat)):
+        got = G.ga_force_torque(plan, Ahat, Bhat4, _dev(poses), mode).cpu().numpy()
+        if np.all(poses == np.round(poses)):
+            ref = O.lattice_read(fields, poses).T
+        else:
+            ref = O.trilinear_read(fields, poses).T
+        assert O.rel_l2(got[:, 0], ref[:, 0]) < FIELD_TOL
+        assert O.rel_l2(got[:, 1:4], ref[:, 1:4]) < FORCE_TOL
+        assert O.rel_l2(got[:, 4:7], ref[:, 4:7]) < FORCE_TOL
+
+
+def test_single_pose_rounds_to_nearest_lattice_point(G):
+    n = 16
+    A = _part(n, 11, 60, 1.0, 3.0)
+    B = _part(n, 12, 60, 1.0, 3.0, conf=3.0)
+    d = O.pair_fields(A.xyzr, A.w, B.xyzr, B.w, np.eye(3, dtype=np.float32), B.ref_point(), n)
+    plan = G.Plan(n, max_batch=4)
+    Ahat = G.ga_fft3d(plan, G.GA_R2C, G.ga_splat(plan, _dev(A.xyzr), _dev(A.w)))[0]
+    Bhat4 = G.ga_fft3d(plan, G.GA_R2C, G.ga_splat(plan, _dev(B.xyzr), _dev(B.w), R=np.eye(3), c=B.ref_point(),
+                                                   channels=4))
+    poses = np.array([[7.4, 8.5, 9.6], [-0.5, 16.2, 31.49]], np.float32)
+    got = G.ga_force_torque(plan, Ahat, Bhat4, _dev(poses), G.GA_SINGLE).cpu().numpy()
+    lat = np.array([[7, 9, 10], [-1, 16, 31]], np.float32)  # round half away from zero
+    fields = np.concatenate([d["E"][None], d["F"], d["tau"]])
+    ref = O.lattice_read(fields, lat).T
+    assert O.rel_l2(got, ref) < FORCE_TOL
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads
+# ---------------------------------------------------------------------------
+
+def test_c2_peg_in_hole_1000_poses(G):
+    a = synth.config_c2()
+    n = a.n
+    plan = G.Plan(n, max_batch=4)
+    Ahat = G.ga_fft3d(plan, G.GA_R2C, G.ga_splat(plan, _dev(a.A.xyzr), _dev(a.A.w), sigma=a.sigma))[0]
+    Bhat4 = G.ga_fft3d(plan, G.GA_R2C, G.ga_splat(plan, _dev(a.B.xyzr), _dev(a.B.w), R=a.rotations[0], c=a.cB,
+                                                   sigma=a.sigma, channels=4))
+    got = G.ga_force_torque(plan, Ahat, Bhat4, _dev(a.poses), G.GA_FIELDS).cpu().numpy()
+    d = O.pair_fields(a.A.xyzr, a.A.w, a.B.xyzr, a.B.w, a.rotations[0], a.cB, n, a.sigma)
+    fields = np.concatenate([d["E"][None], d["F"], d["tau"]])
+    ref = O.lattice_read(fields, a.poses).T
+    assert np.abs(ref[:, 0]).max() > 0
+    assert O.rel_l2(got[:, 0], ref[:, 0]) < FIELD_TOL
+    assert O.rel_l2(got[:, 1:4], ref[:, 1:4]) < FORCE_TOL
+    assert O.rel_l2(got[:, 4:7], ref[:, 4:7]) < FORCE_TOL
+
+
+def test_c3_batched_rotations_full_size_sampled(G):
+    """128^3, one stationary part against 64 rotations in one call (the
+    benchmark's launch configuration); each field sampled at 16 translations
+    where the oracle evaluates E(t) = sum_p u_A(p) u_B(p - t) directly."""
+    a = synth.config_c3()
+    n = a.n
+    nrot = a.rotations.shape[0]
+    plan = G.Plan(n, max_batch=nrot)
+    Ahat = G.ga_fft3d(plan, G.GA_R2C, G.ga_splat(plan, _dev(a.A.xyzr), _dev(a.A.w), sigma=a.sigma))[0]
+    E = G.ga_energy_fields(plan, Ahat, _dev(a.B.xyzr), _dev(a.B.w), _dev(a.rotations), a.cB, a.sigma)
+    torch.cuda.synchronize()
+    uA = O.splat(a.A.xyzr[:, :3].astype(np.float64), a.A.xyzr[:, 3], a.A.w, n)
+    ts = a.poses
+    got_all, ref_all = [], []
+    for r in range(nrot):
+        uB = O.splat(O.place(a.B.xyzr[:, :3], a.rotations[r], a.cB), a.B.xyzr[:, 3], a.B.w, n)
+        ref_all.append(O.correlate_direct(uA, uB, ts))
+        got_all.append(O.lattice_read(E[r].cpu().numpy(), ts))
+    got_all, ref_all = np.array(got_all), np.array(ref_all)
+    assert np.abs(ref_all).max() > 0
+    assert O.rel_l2(got_all, ref_all) < FIELD_TOL
