@@ -29,13 +29,15 @@ HBM_PEAK_GBPS = 8000.0
 
 def algorithmic_bytes(n, batch, n_pts):
     """Bytes each kernel of the field path must move per launch:
-    pass 1 writes the plane spectra (8H per field) and reads the samples,
+    the binning pre-pass reads the samples (20 B each) and writes one placed
+    record (32 B) per sample and field, pass 1 writes the plane spectra (8H),
     pass 2 reads them and the resident spectrum and writes the product after
     the inverse x transform (24H), pass 3 reads it and writes the field
     (8H + 4 n^3). H = n^2 (n/2 + 1) complex elements."""
     H = n * n * (n // 2 + 1)
     return {
-        "plane_fwd": batch * (8 * H + 20 * n_pts),
+        "bin": batch * n_pts * (20 + 32),
+        "plane_fwd": batch * 8 * H,
         "strip": batch * 24 * H,
         "plane_inv": batch * (8 * H + 4 * n ** 3),
     }
@@ -95,7 +97,7 @@ def main():
     R = torch.from_numpy(np.ascontiguousarray(a.rotations.reshape(batch, 9))).to(dev)
     Ahat = G.ga_fft3d(plan, G.GA_R2C, G.ga_splat(plan, xa, wa, sigma=a.sigma))[0].contiguous()
     E = torch.empty((batch, n, n, n), dtype=torch.float32, device=dev)
-    work = plan.workspace(G.ga.GA_OP_ENERGY, batch, device=dev)
+    work = plan.workspace(G.ga.GA_OP_ENERGY, batch, a.B.n, device=dev)
 
     def step():
         G.ga_energy_fields(plan, Ahat, xb, wb, R, a.cB, a.sigma, out=E, work=work)
@@ -110,7 +112,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kern = {}
-    for name, kind in (("plane_fwd", G.ga.GA_K_PLANE_FWD), ("strip", G.ga.GA_K_STRIP),
+    for name, kind in (("bin", G.ga.GA_K_BIN), ("plane_fwd", G.ga.GA_K_PLANE_FWD), ("strip", G.ga.GA_K_STRIP),
                        ("plane_inv", G.ga.GA_K_PLANE_INV)):
         ms, cnt = plan.profile_read(kind)
         kern[name] = ms / max(cnt, 1)

@@ -111,9 +111,10 @@ ga_status ga_plan_create(ga_plan** plan, int32_t n, int32_t max_batch, uint32_t 
 ga_status ga_plan_destroy(ga_plan* plan);
 int32_t ga_plan_n(const ga_plan* plan);
 
-/* Workspace bytes that operation `op` needs for `batch` fields and
- * `n_poses` poses (0 when none is needed). */
-size_t ga_workspace_size(const ga_plan* plan, int32_t op, int32_t batch, int32_t n_poses);
+/* Workspace bytes that operation `op` needs for `batch` fields; n_items is
+ * the number of skeleton samples for GA_OP_ENERGY and the number of poses
+ * for GA_OP_FORCE_SINGLE (ignored otherwise). 0 for an unknown op. */
+size_t ga_workspace_size(const ga_plan* plan, int32_t op, int32_t batch, int64_t n_items);
 
 /*
  * Splat (Sec. 2.3 skeletal density, modelled; Sec. 2.4 rotation about c):
@@ -156,7 +157,7 @@ ga_status ga_correlate(const ga_plan* plan, const float* d_Ahat, int64_t a_strid
  * batch x 9 floats) about h_c, splatted, transformed, multiplied by
  * conj with the resident d_Ahat (one spectrum of the stationary part) and
  * transformed back into the energy field d_E[b] (batch x n^3 floats).
- * Workspace: GA_OP_ENERGY.
+ * Workspace: GA_OP_ENERGY with n_items = n_pts.
  */
 ga_status ga_energy_fields(const ga_plan* plan, const float* d_Ahat, const float* d_xyzr, const float* d_w,
                            int64_t n_pts, const float* d_R, const float* h_c, float sigma, int32_t batch,
@@ -193,7 +194,8 @@ ga_status ga_force_torque(const ga_plan* plan, const float* d_Ahat, const float*
 #define GA_K_STRIP 2     /* pass 2: x FFT per column strip (with products) */
 #define GA_K_PLANE_INV 3 /* pass 3: inverse y FFT and z C2R per x-plane */
 #define GA_K_READOUT 4   /* force/torque products, partial sums, readout */
-#define GA_K_COUNT 5
+#define GA_K_BIN 5       /* placement and binning of the moving part's samples */
+#define GA_K_COUNT 6
 
 ga_status ga_profile_enable(ga_plan* plan, int32_t enable);
 ga_status ga_profile_read(ga_plan* plan, int32_t kind, double* total_ms, int64_t* launches);

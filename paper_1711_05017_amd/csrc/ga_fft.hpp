@@ -108,6 +108,39 @@ template <int DIR> struct Bfly<8, DIR> {
   }
 };
 
+// exp(DIR i pi m / 8) for a compile-time m in [0, 9]
+template <int DIR>
+__device__ __forceinline__ constexpr float2 w16(int m) {
+  constexpr float C1 = 0.92387953251128675613f;  // cos(pi / 8)
+  constexpr float S1 = 0.38268343236508977173f;  // sin(pi / 8)
+  constexpr float C2 = 0.70710678118654752440f;  // cos(pi / 4)
+  const float c[10] = {1.f, C1, C2, S1, 0.f, -S1, -C2, -C1, -1.f, -C1};
+  const float s[10] = {0.f, S1, C2, C1, 1.f, C1, C2, S1, 0.f, -S1};
+  return make_float2(c[m], DIR * s[m]);
+}
+
+// 16 = 4 x 4: DFT4 over n1 for each n2, twiddle exp(DIR 2 pi i n2 k1 / 16),
+// DFT4 over n2 for each k1; output index k1 + 4 k2.
+template <int DIR> struct Bfly<16, DIR> {
+  __device__ __forceinline__ static void run(float2* v) {
+    float2 a[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      float2 t[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
+      Bfly<4, DIR>::run(t);
+#pragma unroll
+      for (int k1 = 0; k1 < 4; ++k1) a[n2][k1] = (n2 * k1 == 0) ? t[k1] : cmul(t[k1], w16<DIR>(n2 * k1));
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      float2 t[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+      Bfly<4, DIR>::run(t);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+    }
+  }
+};
+
 // ---- radix schedules --------------------------------------------------------
 // E elements per lane; every radix divides E; the product of radices is N.
 template <int N> struct Shape;
@@ -123,7 +156,7 @@ GA_SHAPE(32, 8, 2, 8, 4)
 GA_SHAPE(48, 12, 3, 3, 4, 4)
 GA_SHAPE(64, 8, 2, 8, 8)
 GA_SHAPE(96, 24, 3, 3, 4, 8)
-GA_SHAPE(128, 8, 3, 8, 4, 4)
+GA_SHAPE(128, 16, 2, 16, 8)
 GA_SHAPE(192, 24, 3, 3, 8, 8)
 GA_SHAPE(256, 8, 3, 8, 8, 4)
 GA_SHAPE(384, 24, 4, 3, 8, 8, 2)

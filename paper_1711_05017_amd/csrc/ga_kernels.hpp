@@ -2,11 +2,14 @@
 //
 // Data flow of one energy field (three HBM passes):
 //   plane_fwd  per x-plane: splat (or load) the real plane into LDS, z R2C of
-//              row pairs, y FFT of the n/2+1 columns, write the plane.
+//              row pairs, y FFT of the columns, write the plane spectrum.
 //   strip_*    per strip of G (ky, kz) columns: x FFT in LDS, fused with the
 //              conjugate product (and the spectral-gradient multipliers) and
 //              the inverse x FFT, or with the single-pose partial sum.
 //   plane_inv  per x-plane: inverse y FFT, z C2R of row pairs, write reals.
+// After the z R2C the kz = 0 and kz = n/2 columns are real, so their y
+// transforms share one complex transform (two-for-one); every y phase then
+// has n/2 transforms, the same as the z phase.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -24,11 +27,22 @@ template <int N> struct Plane {
   static constexpr int SIZE = N * H;     // float2 per plane
   static constexpr int L = lanes_per_fft<N>();
   static constexpr int TPW = ffts_per_wave<N>();
-  static constexpr int WAVES = (N >= 192) ? 8 : 4;
+  static constexpr int WAVES = (N >= 128) ? 8 : 4;
   static constexpr int THREADS = 64 * WAVES;
+  // waves per SIMD the register budget must allow: two 8-wave workgroups per
+  // CU at n = 128 (the plane's LDS admits two)
+  static constexpr int MINW = (N == 128) ? 4 : 1;
+  static_assert(SIZE % 2 == 0, "plane copies move two complex values at a time");
 };
 
-constexpr int kChunk = 256;  // samples scanned per round; bounds the LDS hit list
+constexpr int kChunk = 256;  // records examined per round; bounds the LDS hit list
+
+// One sample after placement: y = R (x - c) split into an integer voxel base
+// (mod n) and a float32 fraction in [0, 1).
+struct Placed {
+  float4 a;  // fx, fy, fz, rho
+  int4 b;    // bx, by, bz, weight (float bits)
+};
 
 struct SplatParams {
   const float4* xyzr;  // n_pts x (x, y, z, r)
@@ -40,6 +54,11 @@ struct SplatParams {
   float sig_c;    // 1 / (2 sigma^2)
   float e0;       // exp(-1 / (2 sigma^2)) = K offset (independent of rho)
   float inv1me0;  // 1 / (1 - e0)
+  // binned samples (from k_bin_samples), per batch member: records sorted by
+  // bx with bin offsets off[b*(N+1) + i]; null -> scan all samples
+  const Placed* rec;
+  const int* off;
+  const float* rmax;
 };
 
 struct Hit {
@@ -53,15 +72,23 @@ __device__ __forceinline__ int wrapn(int v, int n) {
 }
 __device__ __forceinline__ float yhat(int q, int n) { return (float)((q < n / 2) ? q : q - n); }
 
-// Placement of one sample, y = R (x - c) in float64, split into an integer
-// voxel base (mod n) and a float32 fraction in [0, 1). Returns false for a
-// sample that is not finite or whose radius reaches n/2.
+__device__ __forceinline__ void load_rotation(const SplatParams& p, int b, double* R) {
+  if (p.Rdev) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) R[i] = (double)p.Rdev[b * 9 + i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) R[i] = (double)p.Rh[i];
+  }
+}
+
+// Placement of sample s in float64. Returns false for a sample that is not
+// finite or whose radius reaches n/2 (it contributes nothing).
 template <int N>
-__device__ __forceinline__ bool place_sample(const SplatParams& p, const double* R, long long s, float& fx, float& fy,
-                                             float& fz, int& bx, int& by, int& bz, float& rho, float& w) {
+__device__ __forceinline__ bool place_sample(const SplatParams& p, const double* R, long long s, Placed& out) {
   const float4 q = p.xyzr[s];
-  w = p.w[s];
-  rho = fmaxf(q.w, 1.0f);
+  const float w = p.w[s];
+  const float rho = fmaxf(q.w, 1.0f);
   if (!(rho < 0.5f * N) || !isfinite(w)) return false;
   const double dx0 = (double)q.x - (double)p.c[0];
   const double dy0 = (double)q.y - (double)p.c[1];
@@ -71,79 +98,174 @@ __device__ __forceinline__ bool place_sample(const SplatParams& p, const double*
   const double yz = R[6] * dx0 + R[7] * dy0 + R[8] * dz0;
   if (!(fabs(yx) < 1.0e7 && fabs(yy) < 1.0e7 && fabs(yz) < 1.0e7)) return false;
   const double fbx = floor(yx), fby = floor(yy), fbz = floor(yz);
-  fx = (float)(yx - fbx);
-  fy = (float)(yy - fby);
-  fz = (float)(yz - fbz);
   long long ix = (long long)fbx % N, iy = (long long)fby % N, iz = (long long)fbz % N;
-  bx = (int)(ix < 0 ? ix + N : ix);
-  by = (int)(iy < 0 ? iy + N : iy);
-  bz = (int)(iz < 0 ? iz + N : iz);
+  out.a = make_float4((float)(yx - fbx), (float)(yy - fby), (float)(yz - fbz), rho);
+  out.b = make_int4((int)(ix < 0 ? ix + N : ix), (int)(iy < 0 ? iy + N : iy), (int)(iz < 0 ? iz + N : iz),
+                    __float_as_int(w));
   return true;
 }
 
-// Splat the samples that reach plane x into the LDS real plane Wf (voxel
-// (y, z) at Wf[idx(y, z)]), each voxel value multiplied by yhat_y (chan 2)
-// or yhat_z (chan 3).
-template <int N, class Idx>
-__device__ void splat_plane(const SplatParams& p, const double* R, int x, int chan, float* Wf, Hit* hits,
+// Per batch member: place every sample once, counting sort by bx into
+// rec[b*n_pts ...], bin offsets off[b*(N+1) + i], largest radius rmax[b].
+// grid = batch, block = 256.
+template <int N>
+__global__ void __launch_bounds__(256) k_bin_samples(SplatParams p, Placed* __restrict__ rec, int* __restrict__ off,
+                                                     float* __restrict__ rmax) {
+  __shared__ int cnt[N];
+  __shared__ int cur[N];
+  __shared__ int s_rmax;
+  const int b = blockIdx.x, tid = threadIdx.x;
+  for (int i = tid; i < N; i += 256) cnt[i] = 0;
+  if (tid == 0) s_rmax = __float_as_int(1.0f);
+  __syncthreads();
+  double R[9];
+  load_rotation(p, b, R);
+  for (long long s = tid; s < p.n_pts; s += 256) {
+    Placed q;
+    if (place_sample<N>(p, R, s, q)) {
+      atomicAdd(&cnt[q.b.x], 1);
+      atomicMax(&s_rmax, __float_as_int(q.a.w));  // positive floats order like their bits
+    }
+  }
+  __syncthreads();
+  int* ob = off + (size_t)b * (N + 1);
+  if (tid < 64) {
+    // exclusive scan of the N bin counts by one wave, 64 bins per step
+    int carry = 0;
+    for (int base = 0; base < N; base += 64) {
+      const int i = base + tid;
+      const int v = (i < N) ? cnt[i] : 0;
+      int incl = v;
+      for (int d = 1; d < 64; d <<= 1) {
+        const int o = __shfl_up(incl, d, 64);
+        if (tid >= d) incl += o;
+      }
+      if (i < N) {
+        cur[i] = carry + incl - v;
+        ob[i] = carry + incl - v;
+      }
+      carry += __shfl(incl, 63, 64);
+    }
+    if (tid == 0) {
+      ob[N] = carry;
+      rmax[b] = __int_as_float(s_rmax);
+    }
+  }
+  __syncthreads();
+  Placed* rb = rec + (size_t)b * p.n_pts;
+  for (long long s = tid; s < p.n_pts; s += 256) {
+    Placed q;
+    if (place_sample<N>(p, R, s, q)) rb[atomicAdd(&cur[q.b.x], 1)] = q;
+  }
+}
+
+// Candidate hit test of one placed sample against plane x; appends to the
+// LDS hit list.
+template <int N>
+__device__ __forceinline__ void test_hit(const Placed& q, int x, Hit* hits, int* nhits) {
+  int m = x - q.b.x;
+  m = (m >= N / 2) ? m - N : m;
+  m = (m < -N / 2) ? m + N : m;
+  float dx = (float)m - q.a.x;
+  dx = (dx < -0.5f * N) ? dx + (float)N : dx;
+  const float w = __int_as_float(q.b.w);
+  if (fabsf(dx) < q.a.w && w != 0.0f) {
+    const int slot = atomicAdd(nhits, 1);
+    Hit h;
+    h.a = make_float4(dx, q.a.y, q.a.z, q.a.w);
+    h.b = make_float2(__int_as_float(q.b.y | (q.b.z << 16)), w);
+    hits[slot] = h;
+  }
+}
+
+// Splat the hits of the list into the LDS real plane Wf (voxel (y, z) at
+// Wf[idx(y, z)]), each value multiplied by yhat_y (chan 2) or yhat_z (chan 3).
+template <int N, int WAVES, class Idx>
+__device__ __forceinline__ void splat_hits(const SplatParams& p, int chan, float* Wf, const Hit* hits, int nh,
+                                           Idx idx) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i = wave; i < nh; i += WAVES) {
+    const Hit h = hits[i];
+    const float dx = h.a.x, fy = h.a.y, fz = h.a.z, rho = h.a.w, w = h.b.y;
+    const int packed = __float_as_int(h.b.x);
+    const int by = packed & 0xffff, bz = packed >> 16;
+    const float rho2 = rho * rho;
+    const float rd = sqrtf(fmaxf(rho2 - dx * dx, 0.0f));
+    const int ylo = (int)ceilf(fy - rd), yhi = (int)floorf(fy + rd);
+    const int zlo = (int)ceilf(fz - rd), zhi = (int)floorf(fz + rd);
+    const int sz = zhi - zlo + 1;
+    const int cnt = (yhi - ylo + 1) * sz;
+    const float inv2s2 = p.sig_c / rho2;
+    for (int v = lane; v < cnt; v += 64) {
+      const int oy = ylo + v / sz, oz = zlo + v % sz;
+      const float ddy = (float)oy - fy, ddz = (float)oz - fz;
+      const float d2 = dx * dx + ddy * ddy + ddz * ddz;
+      if (d2 < rho2) {
+        const int yy = wrapn(by + oy, N), zz = wrapn(bz + oz, N);
+        float val = w * (__expf(-d2 * inv2s2) - p.e0) * p.inv1me0;
+        if (chan == 2) val *= yhat(yy, N);
+        if (chan == 3) val *= yhat(zz, N);
+        atomicAdd(&Wf[idx(yy, zz)], val);
+      }
+    }
+  }
+}
+
+// Splat every sample that reaches plane x into Wf. With binned records only
+// the bins within reach of x are examined; otherwise all samples are placed.
+template <int N, int WAVES, int THREADS, class Idx>
+__device__ void splat_plane(const SplatParams& p, const double* R, int b, int x, int chan, float* Wf, Hit* hits,
                             int* nhits, Idx idx) {
-  using P = Plane<N>;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (long long c0 = 0; c0 < p.n_pts; c0 += kChunk) {
+  const int tid = threadIdx.x;
+  long long lo1 = 0, n1 = p.n_pts, lo2 = 0, n2 = 0;
+  const Placed* rb = nullptr;
+  if (p.rec) {
+    const int* ob = p.off + (size_t)b * (N + 1);
+    rb = p.rec + (size_t)b * p.n_pts;
+    const int reach = (int)ceilf(p.rmax[b]) + 1;
+    if (2 * reach + 1 >= N) {
+      lo1 = 0;
+      n1 = ob[N];
+    } else {
+      const int blo = x - reach, bhi = x + reach;  // inclusive bin range, mod N
+      if (blo < 0) {
+        lo1 = ob[blo + N];
+        n1 = ob[N] - lo1;
+        lo2 = 0;
+        n2 = ob[bhi + 1];
+      } else if (bhi >= N) {
+        lo1 = ob[blo];
+        n1 = ob[N] - lo1;
+        lo2 = 0;
+        n2 = ob[bhi + 1 - N];
+      } else {
+        lo1 = ob[blo];
+        n1 = ob[bhi + 1] - lo1;
+      }
+    }
+  }
+  const long long total = n1 + n2;
+  for (long long c0 = 0; c0 < total; c0 += kChunk) {
     if (tid == 0) *nhits = 0;
     __syncthreads();
-    if (tid < kChunk && c0 + tid < p.n_pts) {
-      float fx, fy, fz, rho, w;
-      int bx, by, bz;
-      if (place_sample<N>(p, R, c0 + tid, fx, fy, fz, bx, by, bz, rho, w)) {
-        int m = x - bx;
-        m = (m >= N / 2) ? m - N : m;
-        m = (m < -N / 2) ? m + N : m;
-        float dx = (float)m - fx;
-        dx = (dx < -0.5f * N) ? dx + (float)N : dx;
-        if (fabsf(dx) < rho && w != 0.0f) {
-          const int slot = atomicAdd(nhits, 1);
-          Hit h;
-          h.a = make_float4(dx, fy, fz, rho);
-          h.b = make_float2(__int_as_float(by | (bz << 16)), w);
-          hits[slot] = h;
-        }
-      }
+    const long long i = c0 + tid;
+    if (tid < kChunk && i < total) {
+      Placed q;
+      bool ok = true;
+      if (rb) q = rb[(i < n1) ? lo1 + i : lo2 + (i - n1)];
+      else ok = place_sample<N>(p, R, i, q);
+      if (ok) test_hit<N>(q, x, hits, nhits);
     }
     __syncthreads();
-    const int nh = *nhits;
-    for (int i = wave; i < nh; i += P::WAVES) {
-      const Hit h = hits[i];
-      const float dx = h.a.x, fy = h.a.y, fz = h.a.z, rho = h.a.w, w = h.b.y;
-      const int packed = __float_as_int(h.b.x);
-      const int by = packed & 0xffff, bz = packed >> 16;
-      const float rho2 = rho * rho;
-      const float rd = sqrtf(fmaxf(rho2 - dx * dx, 0.0f));
-      const int ylo = (int)ceilf(fy - rd), yhi = (int)floorf(fy + rd);
-      const int zlo = (int)ceilf(fz - rd), zhi = (int)floorf(fz + rd);
-      const int sz = zhi - zlo + 1;
-      const int cnt = (yhi - ylo + 1) * sz;
-      const float inv2s2 = p.sig_c / rho2;
-      for (int v = lane; v < cnt; v += 64) {
-        const int oy = ylo + v / sz, oz = zlo + v % sz;
-        const float ddy = (float)oy - fy, ddz = (float)oz - fz;
-        const float d2 = dx * dx + ddy * ddy + ddz * ddz;
-        if (d2 < rho2) {
-          const int yy = wrapn(by + oy, N), zz = wrapn(bz + oz, N);
-          float val = w * (__expf(-d2 * inv2s2) - p.e0) * p.inv1me0;
-          if (chan == 2) val *= yhat(yy, N);
-          if (chan == 3) val *= yhat(zz, N);
-          atomicAdd(&Wf[idx(yy, zz)], val);
-        }
-      }
-    }
+    splat_hits<N, WAVES>(p, chan, Wf, hits, *nhits, idx);
     __syncthreads();
   }
 }
 
 // z R2C of every row pair and y FFT of every column, in the LDS plane W.
-// On entry W holds the pair-packed real plane; on exit the plane's 2D
-// spectrum [ky][kz] with row stride H.
+// On entry W holds the pair-packed real plane (rows 2t, 2t+1 as the real and
+// imaginary parts of region t); on exit the plane's 2D spectrum [ky][kz]
+// with row stride H.
 template <int N>
 __device__ void plane_forward_lds(float2* W, const Twiddles<N>& tw) {
   using P = Plane<N>;
@@ -156,87 +278,126 @@ __device__ void plane_forward_lds(float2* W, const Twiddles<N>& tw) {
     if (t < N / 2) {
       float2* reg = W + t * P::PAIR;
       fft_inplace<N, -1>(l, tw, reg, 1);
+      // A(k) = (Z(k) + conj Z(N-k))/2 goes to position k, which no other lane
+      // reads; B(k) = (Z(k) - conj Z(N-k))/(2i) waits in registers until every
+      // lane has read its Z(N-k), then goes to position H + k.
       constexpr int KPL = (H + L - 1) / L;
-      float2 za[KPL], zb[KPL];
+      float2 bk[KPL];
 #pragma unroll
       for (int e = 0; e < KPL; ++e) {
         const int k = l + L * e;
         if (k < H) {
-          za[e] = reg[k];
-          zb[e] = reg[(N - k) % N];
+          const float2 a = reg[k];
+          const float2 z = reg[(N - k) % N];
+          bk[e] = make_float2(0.5f * (a.y + z.y), -0.5f * (a.x - z.x));
+          reg[k] = make_float2(0.5f * (a.x + z.x), 0.5f * (a.y - z.y));
         }
       }
       wave_sync();
 #pragma unroll
       for (int e = 0; e < KPL; ++e) {
         const int k = l + L * e;
-        if (k < H) {
-          const float2 a = za[e];
-          const float2 b = make_float2(zb[e].x, -zb[e].y);  // conj Z(N-k)
-          reg[k] = make_float2(0.5f * (a.x + b.x), 0.5f * (a.y + b.y));          // (Z + conj Z')/2
-          reg[H + k] = make_float2(0.5f * (a.y - b.y), -0.5f * (a.x - b.x));     // (Z - conj Z')/(2i)
-        }
+        if (k < H) reg[H + k] = bk[e];
       }
       wave_sync();
     }
   }
   __syncthreads();
-  // y: one FFT per kz column (stride H)
-  for (int t0 = wave * TPW; t0 < H; t0 += P::WAVES * TPW) {
+  // y: columns 1 .. N/2-1 in place; column 0 carries the real columns kz = 0
+  // (real part) and kz = N/2 (imaginary part) and is split afterwards.
+  for (int t0 = wave * TPW; t0 < N / 2; t0 += P::WAVES * TPW) {
     const int t = t0 + lane / L;
-    if (t < H) fft_inplace<N, -1>(l, tw, W + t, H);
+    if (t < N / 2) {
+      float2* col = W + t;
+      auto ld = [&](int pos) -> float2 {
+        float2 v = col[pos * H];
+        if (t == 0) v.y = col[pos * H + N / 2].x;
+        return v;
+      };
+      auto st = [&](int pos, float2 v) { col[pos * H] = v; };
+      fft_lanes<N, -1>(l, tw, col, H, ld, st);
+      if (t == 0) {
+        // C = A + i B with A, B the spectra of the real columns kz = 0 and
+        // kz = N/2: B(k) = (C(k) - conj C(N-k))/(2i) to column N/2 (not read
+        // here), then A(k) = C(k) - i B(k) in place, position by position.
+        for (int k = l; k < N; k += L) {
+          const float2 a = col[k * H];
+          const float2 z = col[((N - k) % N) * H];
+          col[k * H + N / 2] = make_float2(0.5f * (a.y + z.y), -0.5f * (a.x - z.x));
+        }
+        wave_sync();
+        for (int k = l; k < N; k += L) {
+          const float2 c = col[k * H];
+          const float2 bb = col[k * H + N / 2];
+          col[k * H] = make_float2(c.x + bb.y, c.y - bb.x);
+        }
+        wave_sync();
+      }
+    }
   }
   __syncthreads();
 }
 
-// Pass 1. grid = (N planes, batch). Source: splatted samples (p.xyzr != null)
-// or real grids `grid` [batch][nch_in... = 1][N^3]. Writes nch spectra planes
-// per batch member: out[((b*nch + c)*N + x)*N*H].
-template <int N>
-__global__ void __launch_bounds__(Plane<N>::THREADS) k_plane_fwd(SplatParams p, const float* __restrict__ grid,
-                                                                 int nch, float2* __restrict__ out,
-                                                                 const float2* __restrict__ table) {
+// Two complex values at a time between global memory and LDS.
+template <int THREADS, int SIZE>
+__device__ __forceinline__ void copy_plane(float2* __restrict__ dst, const float2* __restrict__ src) {
+  const float4* s4 = reinterpret_cast<const float4*>(src);
+  float4* d4 = reinterpret_cast<float4*>(dst);
+#pragma unroll 4
+  for (int i = threadIdx.x; i < SIZE / 2; i += THREADS) d4[i] = s4[i];
+}
+
+// Pass 1. grid = (N planes, batch). GRID: real grids `grid` [batch][N^3]
+// (NCH = 1). Otherwise splat from the binned samples (p.rec) of each batch
+// member. Writes NCH spectra planes per batch member,
+// out[((b*NCH + c)*N + x)*N*H]: u, and with NCH = 4 the moment densities
+// yhat_x u, yhat_y u, yhat_z u.
+template <int N, bool GRID, int NCH>
+__global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_fwd(SplatParams p,
+                                                                               const float* __restrict__ grid,
+                                                                               float2* __restrict__ out,
+                                                                               const float2* __restrict__ table) {
   using P = Plane<N>;
-  __shared__ float2 W[P::SIZE];
-  __shared__ Hit hits[kChunk];
+  __shared__ __attribute__((aligned(16))) float2 W[P::SIZE];
+  __shared__ Hit hits[GRID ? 1 : kChunk];
   __shared__ int nhits;
   const int x = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
-  Twiddles<N> tw;
-  load_twiddles<N>(tw, table, (tid & 63) % P::L);
   float* Wf = reinterpret_cast<float*>(W);
-  double R[9];
-  if (p.Rdev) {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) R[i] = (double)p.Rdev[b * 9 + i];
-  } else {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) R[i] = (double)p.Rh[i];
-  }
   const size_t plane_sz = (size_t)N * P::H;
-  const int npass = (nch == 4) ? 3 : 1;
-  for (int pass = 0; pass < npass; ++pass) {
+  constexpr int NPASS = (NCH == 4) ? 3 : 1;
+#pragma unroll 1
+  for (int pass = 0; pass < NPASS; ++pass) {
     const int chan = (pass == 0) ? 0 : pass + 1;  // 0, 2, 3
-    if (grid) {
-      const float* src = grid + ((size_t)b * N + x) * N * N;
-      for (int i = tid; i < N * N; i += P::THREADS) {
-        const int y = i / N, z = i % N;
-        Wf[((y >> 1) * P::PAIR + z) * 2 + (y & 1)] = src[i];
+    if constexpr (GRID) {
+      const float2* src = reinterpret_cast<const float2*>(grid + ((size_t)b * N + x) * N * N);
+      // two adjacent z values of one row land in one pair-region entry each
+      for (int i = tid; i < N * N / 2; i += P::THREADS) {
+        const int y = (2 * i) / N, z = (2 * i) % N;
+        const float2 v = src[i];
+        Wf[((y >> 1) * P::PAIR + z) * 2 + (y & 1)] = v.x;
+        Wf[((y >> 1) * P::PAIR + z + 1) * 2 + (y & 1)] = v.y;
       }
-      // the padding columns of each pair region are not read before written
     } else {
-      for (int i = tid; i < P::SIZE; i += P::THREADS) W[i] = make_float2(0.f, 0.f);
+      float4* W4 = reinterpret_cast<float4*>(W);
+      for (int i = tid; i < P::SIZE / 2; i += P::THREADS) W4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
       __syncthreads();
-      splat_plane<N>(p, R, x, chan, Wf, hits, &nhits,
-                     [](int yy, int zz) { return ((yy >> 1) * P::PAIR + zz) * 2 + (yy & 1); });
+      splat_plane<N, P::WAVES, P::THREADS>(p, nullptr, b, x, chan, Wf, hits, &nhits, [](int yy, int zz) {
+        return ((yy >> 1) * P::PAIR + zz) * 2 + (yy & 1);
+      });
     }
     __syncthreads();
-    plane_forward_lds<N>(W, tw);
-    float2* dst = out + (((size_t)b * nch + chan) * N + x) * plane_sz;
-    for (int i = tid; i < P::SIZE; i += P::THREADS) dst[i] = W[i];
-    if (nch == 4 && chan == 0) {
-      const float sx = yhat(x, N);
-      float2* dx = out + (((size_t)b * nch + 1) * N + x) * plane_sz;
-      for (int i = tid; i < P::SIZE; i += P::THREADS) dx[i] = cscale(W[i], sx);
+    {
+      Twiddles<N> tw;
+      load_twiddles<N>(tw, table, (tid & 63) % P::L);
+      plane_forward_lds<N>(W, tw);
+    }
+    copy_plane<P::THREADS, P::SIZE>(out + (((size_t)b * NCH + chan) * N + x) * plane_sz, W);
+    if constexpr (NCH == 4) {
+      if (chan == 0) {
+        const float sx = yhat(x, N);
+        float2* dx = out + (((size_t)b * NCH + 1) * N + x) * plane_sz;
+        for (int i = tid; i < P::SIZE; i += P::THREADS) dx[i] = cscale(W[i], sx);
+      }
     }
     __syncthreads();
   }
@@ -252,11 +413,10 @@ __global__ void __launch_bounds__(Plane<N>::THREADS) k_splat_real(SplatParams p,
   __shared__ int nhits;
   const int x = blockIdx.x, tid = threadIdx.x;
   double R[9];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) R[i] = (double)p.Rh[i];
+  load_rotation(p, 0, R);
   for (int i = tid; i < N * N; i += P::THREADS) U[i] = 0.f;
   __syncthreads();
-  splat_plane<N>(p, R, x, 0, U, hits, &nhits, [](int yy, int zz) { return yy * N + zz; });
+  splat_plane<N, P::WAVES, P::THREADS>(p, R, 0, x, 0, U, hits, &nhits, [](int yy, int zz) { return yy * N + zz; });
   __syncthreads();
   const size_t n3 = (size_t)N * N * N;
   for (int i = tid; i < N * N; i += P::THREADS) {
@@ -274,21 +434,44 @@ __global__ void __launch_bounds__(Plane<N>::THREADS) k_splat_real(SplatParams p,
 // Pass 3. grid = (N planes, batch). in: spectra after the inverse x pass,
 // [b][x][ky][kz]; out: real grids [b][x][y][z] times `scale`.
 template <int N>
-__global__ void __launch_bounds__(Plane<N>::THREADS) k_plane_inv(const float2* __restrict__ in, float* __restrict__ out,
+__global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_inv(const float2* __restrict__ in, float* __restrict__ out,
                                                                  float scale, const float2* __restrict__ table) {
   using P = Plane<N>;
   constexpr int L = P::L, TPW = P::TPW, H = P::H;
-  __shared__ float2 W[P::SIZE];
+  __shared__ __attribute__((aligned(16))) float2 W[P::SIZE];
   const int x = blockIdx.x, b = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l = lane % L;
   Twiddles<N> tw;
   load_twiddles<N>(tw, table, l);
-  const float2* src = in + ((size_t)b * N + x) * (size_t)P::SIZE;
-  for (int i = tid; i < P::SIZE; i += P::THREADS) W[i] = src[i];
+  copy_plane<P::THREADS, P::SIZE>(W, in + ((size_t)b * N + x) * (size_t)P::SIZE);
   __syncthreads();
-  for (int t0 = wave * TPW; t0 < H; t0 += P::WAVES * TPW) {
+  // y: columns 1 .. N/2-1 in place. The z C2R below keeps only the real part
+  // of columns kz = 0 and kz = N/2, so both go through one transform of
+  // c = h(col0) + i h(colN/2), h(a)(k) = (a(k) + conj a(-k))/2, whose
+  // inverse is Re IFFT(col0) + i Re IFFT(colN/2).
+  for (int t0 = wave * TPW; t0 < N / 2; t0 += P::WAVES * TPW) {
     const int t = t0 + lane / L;
-    if (t < H) fft_inplace<N, +1>(l, tw, W + t, H);
+    if (t < N / 2) {
+      float2* col = W + t;
+      auto ld = [&](int pos) -> float2 {
+        if (t != 0) return col[pos * H];
+        const int m = (N - pos) % N;
+        const float2 a0 = col[pos * H], a1 = col[m * H];
+        const float2 b0 = col[pos * H + N / 2], b1 = col[m * H + N / 2];
+        const float2 ha = make_float2(0.5f * (a0.x + a1.x), 0.5f * (a0.y - a1.y));
+        const float2 hb = make_float2(0.5f * (b0.x + b1.x), 0.5f * (b0.y - b1.y));
+        return make_float2(ha.x - hb.y, ha.y + hb.x);
+      };
+      auto st = [&](int pos, float2 v) {
+        if (t != 0) {
+          col[pos * H] = v;
+        } else {
+          col[pos * H] = make_float2(v.x, 0.f);
+          col[pos * H + N / 2] = make_float2(v.y, 0.f);
+        }
+      };
+      fft_lanes<N, +1>(l, tw, col, H, ld, st);
+    }
   }
   __syncthreads();
   float* dst = out + ((size_t)b * N + x) * (size_t)N * N;

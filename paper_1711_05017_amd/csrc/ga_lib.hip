@@ -90,9 +90,18 @@ template <int N> struct Launch {
   static int nstrips() { return (T::C + G - 1) / G; }
   static int nsingle() { return (T::C + kSingleG - 1) / kSingleG; }
 
+  static void bin_samples(const SplatParams& sp, Placed* rec, int* off, float* rmax, int batch, hipStream_t s) {
+    hipLaunchKernelGGL(k_bin_samples<N>, dim3(batch), dim3(256), 0, s, sp, rec, off, rmax);
+  }
+  // pass 1 from real grids (nch = 1) or from binned samples (nch = 1 or 4)
   static void plane_fwd(const SplatParams& sp, const float* grid, int nch, float2* out, int batch, const float2* tw,
                         hipStream_t s) {
-    hipLaunchKernelGGL(k_plane_fwd<N>, dim3(N, batch), dim3(P::THREADS), 0, s, sp, grid, nch, out, tw);
+    if (grid)
+      hipLaunchKernelGGL((k_plane_fwd<N, true, 1>), dim3(N, batch), dim3(P::THREADS), 0, s, sp, grid, out, tw);
+    else if (nch == 4)
+      hipLaunchKernelGGL((k_plane_fwd<N, false, 4>), dim3(N, batch), dim3(P::THREADS), 0, s, sp, grid, out, tw);
+    else
+      hipLaunchKernelGGL((k_plane_fwd<N, false, 1>), dim3(N, batch), dim3(P::THREADS), 0, s, sp, grid, out, tw);
   }
   static void plane_inv(const float2* in, float* out, float scale, int batch, const float2* tw, hipStream_t s) {
     hipLaunchKernelGGL(k_plane_inv<N>, dim3(N, batch), dim3(P::THREADS), 0, s, in, out, scale, tw);
@@ -150,9 +159,21 @@ int nsingle_of(int n) {
 
 bool valid_sigma(float s) { return std::isfinite(s) && s > 0.0f; }
 
+// Workspace of the fused field path: batch spectra, then the binned samples
+// (records, bin offsets, largest radius per batch member).
+size_t bin_offset(int n, int batch) { return (size_t)batch * spectrum_elems(n) * sizeof(float2); }
+size_t bin_bytes(int n, int batch, int64_t n_pts) {
+  const size_t rec = (size_t)batch * (size_t)n_pts * sizeof(Placed);
+  const size_t off = ((size_t)batch * (n + 1) * sizeof(int) + 15) / 16 * 16;
+  return rec + off + (size_t)batch * sizeof(float);
+}
+
 SplatParams make_splat(const float* xyzr, const float* w, int64_t n_pts, const float* Rdev, const float* hR,
                        const float* hc, float sigma) {
   SplatParams p{};
+  p.rec = nullptr;
+  p.off = nullptr;
+  p.rmax = nullptr;
   p.xyzr = reinterpret_cast<const float4*>(xyzr);
   p.w = w;
   p.n_pts = n_pts;
@@ -251,17 +272,17 @@ ga_status ga_plan_destroy(ga_plan* plan) {
 
 int32_t ga_plan_n(const ga_plan* plan) { return plan ? plan->n : 0; }
 
-size_t ga_workspace_size(const ga_plan* plan, int32_t op, int32_t batch, int32_t n_poses) {
-  if (!plan || batch < 0 || n_poses < 0) return 0;
+size_t ga_workspace_size(const ga_plan* plan, int32_t op, int32_t batch, int64_t n_items) {
+  if (!plan || batch < 0 || n_items < 0) return 0;
   const int n = plan->n;
   const size_t spec = spectrum_elems(n) * sizeof(float2);
   const size_t real = (size_t)n * n * n * sizeof(float);
   switch (op) {
     case GA_OP_FFT_C2R:
-    case GA_OP_CORRELATE:
-    case GA_OP_ENERGY: return (size_t)batch * spec;
+    case GA_OP_CORRELATE: return (size_t)batch * spec;
+    case GA_OP_ENERGY: return bin_offset(n, batch) + bin_bytes(n, batch, n_items);
     case GA_OP_FORCE_FIELDS: return 7 * spec + 7 * real;
-    case GA_OP_FORCE_SINGLE: return (size_t)n_poses * nsingle_of(n) * 7 * sizeof(double);
+    case GA_OP_FORCE_SINGLE: return (size_t)n_items * nsingle_of(n) * 7 * sizeof(double);
     default: return 0;
   }
 }
@@ -347,15 +368,28 @@ ga_status ga_energy_fields(const ga_plan* plan, const float* d_Ahat, const float
       n_pts < 0 || (n_pts > 0 && (!d_xyzr || !d_w)) || !valid_sigma(sigma))
     return GA_EINVAL;
   if (!(std::isfinite(h_c[0]) && std::isfinite(h_c[1]) && std::isfinite(h_c[2]))) return GA_EINVAL;
-  if (!d_work || work_bytes < ga_workspace_size(plan, GA_OP_ENERGY, batch, 0)) return GA_ENOMEM;
+  if (!d_work || work_bytes < ga_workspace_size(plan, GA_OP_ENERGY, batch, n_pts)) return GA_ENOMEM;
   const int n = plan->n;
   float2* tmp = static_cast<float2*>(d_work);
   const float scale = (float)(1.0 / ((double)n * n * n));
   SplatParams sp = make_splat(d_xyzr, d_w, n_pts, d_R, nullptr, h_c, sigma);
+  char* bins = static_cast<char*>(d_work) + bin_offset(n, batch);
+  Placed* rec = reinterpret_cast<Placed*>(bins);
+  int* off = reinterpret_cast<int*>(bins + (size_t)batch * (size_t)n_pts * sizeof(Placed));
+  float* rmax = reinterpret_cast<float*>(reinterpret_cast<char*>(off) +
+                                         ((size_t)batch * (n + 1) * sizeof(int) + 15) / 16 * 16);
   dispatch(n, [&]<int N>() {
     {
+      {
+        ProfScope pb(plan, GA_K_BIN, stream);
+        Launch<N>::bin_samples(sp, rec, off, rmax, batch, stream);
+      }
       ProfScope ps(plan, GA_K_PLANE_FWD, stream);
-      Launch<N>::plane_fwd(sp, nullptr, 1, tmp, batch, plan->d_tw, stream);
+      SplatParams spb = sp;
+      spb.rec = rec;
+      spb.off = off;
+      spb.rmax = rmax;
+      Launch<N>::plane_fwd(spb, nullptr, 1, tmp, batch, plan->d_tw, stream);
     }
     {
       ProfScope ps(plan, GA_K_STRIP, stream);
@@ -376,7 +410,7 @@ ga_status ga_force_torque(const ga_plan* plan, const float* d_Ahat, const float*
   if (n_poses == 0) return GA_OK;
   const int n = plan->n;
   const int op = (mode == GA_FIELDS) ? GA_OP_FORCE_FIELDS : GA_OP_FORCE_SINGLE;
-  if (!d_work || work_bytes < ga_workspace_size(plan, op, 1, n_poses)) return GA_ENOMEM;
+  if (!d_work || work_bytes < ga_workspace_size(plan, op, 1, (int64_t)n_poses)) return GA_ENOMEM;
   const float2* A = reinterpret_cast<const float2*>(d_Ahat);
   const float2* B4 = reinterpret_cast<const float2*>(d_Bhat4);
   if (mode == GA_FIELDS) {

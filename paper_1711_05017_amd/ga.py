@@ -28,8 +28,8 @@ EXPORTS = [
     "ga_workspace_size", "ga_splat", "ga_fft3d", "ga_correlate", "ga_energy_fields", "ga_force_torque",
     "ga_profile_enable", "ga_profile_read",
 ]
-GA_K_SPLAT, GA_K_PLANE_FWD, GA_K_STRIP, GA_K_PLANE_INV, GA_K_READOUT = 0, 1, 2, 3, 4
-KERNEL_KINDS = {"splat": 0, "plane_fwd": 1, "strip": 2, "plane_inv": 3, "readout": 4}
+GA_K_SPLAT, GA_K_PLANE_FWD, GA_K_STRIP, GA_K_PLANE_INV, GA_K_READOUT, GA_K_BIN = 0, 1, 2, 3, 4, 5
+KERNEL_KINDS = {"splat": 0, "plane_fwd": 1, "strip": 2, "plane_inv": 3, "readout": 4, "bin": 5}
 
 _vp = ctypes.c_void_p
 _SIGS = {
@@ -39,7 +39,7 @@ _SIGS = {
     "ga_plan_create": (ctypes.c_int32, [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32]),
     "ga_plan_destroy": (ctypes.c_int32, [_vp]),
     "ga_plan_n": (ctypes.c_int32, [_vp]),
-    "ga_workspace_size": (ctypes.c_size_t, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "ga_workspace_size": (ctypes.c_size_t, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64]),
     "ga_splat": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_float, ctypes.c_int32, _vp, _vp]),
     "ga_fft3d": (ctypes.c_int32, [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32, _vp, ctypes.c_size_t, _vp]),
     "ga_correlate": (ctypes.c_int32, [_vp, _vp, ctypes.c_int64, _vp, ctypes.c_int32, _vp, _vp, ctypes.c_size_t, _vp]),
@@ -149,8 +149,8 @@ class Plan:
     def handle(self):
         return self._h
 
-    def workspace(self, op: int, batch: int = 1, n_poses: int = 0, device=None) -> torch.Tensor:
-        nbytes = load().ga_workspace_size(self._h, op, batch, n_poses)
+    def workspace(self, op: int, batch: int = 1, n_items: int = 0, device=None) -> torch.Tensor:
+        nbytes = load().ga_workspace_size(self._h, op, batch, n_items)
         return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device or "cuda")
 
     def profile(self, enable: bool = True):
@@ -245,7 +245,7 @@ def ga_energy_fields(plan: Plan, Ahat: torch.Tensor, xyzr: torch.Tensor, w: torc
         out = torch.empty((batch, n, n, n), dtype=torch.float32, device=xyzr.device)
     _need(out, torch.float32, batch * n ** 3, "out")
     if work is None:
-        work = plan.workspace(GA_OP_ENERGY, batch, device=xyzr.device)
+        work = plan.workspace(GA_OP_ENERGY, batch, m, device=xyzr.device)
     st = load().ga_energy_fields(plan.handle, _ptr(Ahat), _ptr(xyzr), _ptr(w), m, _ptr(R),
                                  _host_f32(c, 3), float(sigma), batch, _ptr(out), _ptr(work), int(work.numel()),
                                  _stream(stream))
