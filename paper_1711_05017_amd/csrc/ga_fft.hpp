@@ -2,7 +2,7 @@
 //
 // One length-N complex transform is owned by L = N/E lanes of a single
 // 64-lane wavefront; each lane holds E elements per stage. Stages are
-// Stockham autosort steps (radix 2, 3, 4 or 8) computed in place in an LDS
+// Stockham autosort steps (radix 2, 3, 4, 8 or 16) computed in place in an LDS
 // region: every lane of the wave reads all its inputs, then writes all its
 // outputs, so no workgroup barrier is needed between stages (a wave executes
 // its LDS instructions in order). Twiddles depend only on the lane's position
@@ -156,7 +156,7 @@ GA_SHAPE(32, 8, 2, 8, 4)
 GA_SHAPE(48, 12, 3, 3, 4, 4)
 GA_SHAPE(64, 8, 2, 8, 8)
 GA_SHAPE(96, 24, 3, 3, 4, 8)
-GA_SHAPE(128, 16, 2, 16, 8)
+GA_SHAPE(128, 16, 2, 8, 16)
 GA_SHAPE(192, 24, 3, 3, 8, 8)
 GA_SHAPE(256, 8, 3, 8, 8, 4)
 GA_SHAPE(384, 24, 4, 3, 8, 8, 2)

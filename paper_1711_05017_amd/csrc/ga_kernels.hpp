@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "ga_fft.hpp"
 
 namespace ga {
@@ -61,9 +63,20 @@ struct SplatParams {
   const float* rmax;
 };
 
+// A sample that reaches the current plane, with the bounding square of its
+// disk in the plane: rows ylo .. ylo + sy - 1, columns zlo .. zlo + sz - 1
+// (offsets from the voxel base), cnt = sy * sz voxels.
 struct Hit {
-  float4 a;  // dx (signed, minimum image), fy, fz, rho
-  float2 b;  // packed (by, bz) as int bits, w
+  float4 a;  // dx^2, fy, fz, w
+  int4 b;    // by | bz << 16, (ylo & 0xffff) | zlo << 16, sz, 1/(2 s^2) as float bits
+};
+
+// LDS state of the splat of one plane: hit list and the running voxel
+// offset of each hit (hstart[i] = sum of cnt over hits before i).
+struct HitList {
+  Hit hits[kChunk];
+  int hstart[kChunk + 1];
+  int nhits;
 };
 
 __device__ __forceinline__ int wrapn(int v, int n) {
@@ -159,50 +172,90 @@ __global__ void __launch_bounds__(256) k_bin_samples(SplatParams p, Placed* __re
   }
 }
 
-// Candidate hit test of one placed sample against plane x; appends to the
-// LDS hit list.
+// Candidate hit test of one placed sample against plane x; appends it and
+// its disk's voxel count to the LDS hit list.
 template <int N>
-__device__ __forceinline__ void test_hit(const Placed& q, int x, Hit* hits, int* nhits) {
+__device__ __forceinline__ void test_hit(const SplatParams& p, const Placed& q, int x, HitList& hl) {
   int m = x - q.b.x;
   m = (m >= N / 2) ? m - N : m;
   m = (m < -N / 2) ? m + N : m;
   float dx = (float)m - q.a.x;
   dx = (dx < -0.5f * N) ? dx + (float)N : dx;
   const float w = __int_as_float(q.b.w);
-  if (fabsf(dx) < q.a.w && w != 0.0f) {
-    const int slot = atomicAdd(nhits, 1);
-    Hit h;
-    h.a = make_float4(dx, q.a.y, q.a.z, q.a.w);
-    h.b = make_float2(__int_as_float(q.b.y | (q.b.z << 16)), w);
-    hits[slot] = h;
+  const float rho = q.a.w;
+  if (!(fabsf(dx) < rho) || w == 0.0f) return;
+  const float rd = sqrtf(fmaxf(rho * rho - dx * dx, 0.0f));
+  const float fy = q.a.y, fz = q.a.z;
+  const int ylo = (int)ceilf(fy - rd), yhi = (int)floorf(fy + rd);
+  const int zlo = (int)ceilf(fz - rd), zhi = (int)floorf(fz + rd);
+  const int sy = yhi - ylo + 1, sz = zhi - zlo + 1;
+  if (sy <= 0 || sz <= 0) return;
+  const int slot = atomicAdd(&hl.nhits, 1);
+  Hit h;
+  h.a = make_float4(dx * dx, fy, fz, w);
+  h.b = make_int4(q.b.y | (q.b.z << 16), (ylo & 0xffff) | (zlo << 16), sz, __float_as_int(p.sig_c / (rho * rho)));
+  hl.hits[slot] = h;
+  hl.hstart[slot] = sy * sz;  // count for now; turned into offsets by hits_scan
+}
+
+// Exclusive scan of the hit counts in place (one wave), hstart[nh] = total.
+__device__ __forceinline__ void hits_scan(HitList& hl) {
+  const int tid = threadIdx.x;
+  const int nh = hl.nhits;
+  if (tid < 64) {
+    int carry = 0;
+    for (int base = 0; base < nh; base += 64) {
+      const int i = base + tid;
+      const int v = (i < nh) ? hl.hstart[i] : 0;
+      int incl = v;
+      for (int d = 1; d < 64; d <<= 1) {
+        const int o = __shfl_up(incl, d, 64);
+        if (tid >= d) incl += o;
+      }
+      if (i < nh) hl.hstart[i] = carry + incl - v;
+      carry += __shfl(incl, 63, 64);
+    }
+    if (tid == 0) hl.hstart[nh] = carry;
   }
 }
 
-// Splat the hits of the list into the LDS real plane Wf (voxel (y, z) at
-// Wf[idx(y, z)]), each value multiplied by yhat_y (chan 2) or yhat_z (chan 3).
+// Splat the hits into the LDS real plane Wf (voxel (y, z) at Wf[idx(y, z)]),
+// each value multiplied by yhat_y (chan 2) or yhat_z (chan 3). The
+// (hit, voxel) pairs are flattened and each wave takes a contiguous range of
+// them, 64 at a time, so lanes are not left idle by small disks.
 template <int N, int WAVES, class Idx>
-__device__ __forceinline__ void splat_hits(const SplatParams& p, int chan, float* Wf, const Hit* hits, int nh,
-                                           Idx idx) {
+__device__ __forceinline__ void splat_hits(const SplatParams& p, int chan, float* Wf, const HitList& hl, Idx idx) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int i = wave; i < nh; i += WAVES) {
-    const Hit h = hits[i];
-    const float dx = h.a.x, fy = h.a.y, fz = h.a.z, rho = h.a.w, w = h.b.y;
-    const int packed = __float_as_int(h.b.x);
-    const int by = packed & 0xffff, bz = packed >> 16;
-    const float rho2 = rho * rho;
-    const float rd = sqrtf(fmaxf(rho2 - dx * dx, 0.0f));
-    const int ylo = (int)ceilf(fy - rd), yhi = (int)floorf(fy + rd);
-    const int zlo = (int)ceilf(fz - rd), zhi = (int)floorf(fz + rd);
-    const int sz = zhi - zlo + 1;
-    const int cnt = (yhi - ylo + 1) * sz;
-    const float inv2s2 = p.sig_c / rho2;
-    for (int v = lane; v < cnt; v += 64) {
-      const int oy = ylo + v / sz, oz = zlo + v % sz;
-      const float ddy = (float)oy - fy, ddz = (float)oz - fz;
-      const float d2 = dx * dx + ddy * ddy + ddz * ddz;
-      if (d2 < rho2) {
-        const int yy = wrapn(by + oy, N), zz = wrapn(bz + oz, N);
-        float val = w * (__expf(-d2 * inv2s2) - p.e0) * p.inv1me0;
+  const int nh = hl.nhits;
+  if (nh == 0) return;
+  const int V = hl.hstart[nh];
+  const int per = (((V + WAVES - 1) / WAVES) + 63) & ~63;
+  const int g0 = wave * per, g1 = min(V, g0 + per);
+  if (g0 >= g1) return;
+  int lo = 0, hi = nh - 1;  // last hit whose range starts at or before g0
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (hl.hstart[mid] <= g0) lo = mid;
+    else hi = mid - 1;
+  }
+  int h = lo;
+  for (int gb = g0; gb < g1; gb += 64) {
+    const int g = gb + lane;
+    if (g < g1) {
+      while (hl.hstart[h + 1] <= g) ++h;
+      const Hit q = hl.hits[h];
+      const int v = g - hl.hstart[h];
+      const int sz = q.b.z;
+      // v / sz for v < 2^16: the quotient of (v + 1/2)/sz is at least
+      // 1/(2 sz) away from an integer, far above the reciprocal's error
+      const int qy = (int)(((float)v + 0.5f) * __builtin_amdgcn_rcpf((float)sz));
+      const int oy = (int)(short)(q.b.y & 0xffff) + qy;
+      const int oz = (q.b.y >> 16) + (v - qy * sz);
+      const float ddy = (float)oy - q.a.y, ddz = (float)oz - q.a.z;
+      const float e = (q.a.x + ddy * ddy + ddz * ddz) * __int_as_float(q.b.w);  // d^2 / (2 s^2)
+      if (e < p.sig_c) {  // d < rho
+        const int yy = wrapn((q.b.x & 0xffff) + oy, N), zz = wrapn((q.b.x >> 16) + oz, N);
+        float val = q.a.w * (__expf(-e) - p.e0) * p.inv1me0;
         if (chan == 2) val *= yhat(yy, N);
         if (chan == 3) val *= yhat(zz, N);
         atomicAdd(&Wf[idx(yy, zz)], val);
@@ -214,8 +267,8 @@ __device__ __forceinline__ void splat_hits(const SplatParams& p, int chan, float
 // Splat every sample that reaches plane x into Wf. With binned records only
 // the bins within reach of x are examined; otherwise all samples are placed.
 template <int N, int WAVES, int THREADS, class Idx>
-__device__ void splat_plane(const SplatParams& p, const double* R, int b, int x, int chan, float* Wf, Hit* hits,
-                            int* nhits, Idx idx) {
+__device__ void splat_plane(const SplatParams& p, const double* R, int b, int x, int chan, float* Wf, HitList& hl,
+                            Idx idx) {
   const int tid = threadIdx.x;
   long long lo1 = 0, n1 = p.n_pts, lo2 = 0, n2 = 0;
   const Placed* rb = nullptr;
@@ -246,7 +299,7 @@ __device__ void splat_plane(const SplatParams& p, const double* R, int b, int x,
   }
   const long long total = n1 + n2;
   for (long long c0 = 0; c0 < total; c0 += kChunk) {
-    if (tid == 0) *nhits = 0;
+    if (tid == 0) hl.nhits = 0;
     __syncthreads();
     const long long i = c0 + tid;
     if (tid < kChunk && i < total) {
@@ -254,10 +307,12 @@ __device__ void splat_plane(const SplatParams& p, const double* R, int b, int x,
       bool ok = true;
       if (rb) q = rb[(i < n1) ? lo1 + i : lo2 + (i - n1)];
       else ok = place_sample<N>(p, R, i, q);
-      if (ok) test_hit<N>(q, x, hits, nhits);
+      if (ok) test_hit<N>(p, q, x, hl);
     }
     __syncthreads();
-    splat_hits<N, WAVES>(p, chan, Wf, hits, *nhits, idx);
+    hits_scan(hl);
+    __syncthreads();
+    splat_hits<N, WAVES>(p, chan, Wf, hl, idx);
     __syncthreads();
   }
 }
@@ -338,13 +393,35 @@ __device__ void plane_forward_lds(float2* W, const Twiddles<N>& tw) {
   __syncthreads();
 }
 
+// Copy of COUNT items by THREADS threads that issues up to 16 loads per
+// thread before the first store, so one workgroup waits for one memory
+// latency per 16 items instead of one per item.
+template <int COUNT, int THREADS, class T, class Ld, class St>
+__device__ __forceinline__ void batched_copy(Ld ld, St st) {
+  constexpr int IT = (COUNT + THREADS - 1) / THREADS;
+  constexpr int B = IT < 16 ? IT : 16;
+#pragma unroll 1
+  for (int it0 = 0; it0 < IT; it0 += B) {
+    T v[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int i = threadIdx.x + (it0 + u) * THREADS;
+      if ((COUNT % THREADS == 0 && IT % B == 0) || i < COUNT) v[u] = ld(i);
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int i = threadIdx.x + (it0 + u) * THREADS;
+      if ((COUNT % THREADS == 0 && IT % B == 0) || i < COUNT) st(i, v[u]);
+    }
+  }
+}
+
 // Two complex values at a time between global memory and LDS.
 template <int THREADS, int SIZE>
 __device__ __forceinline__ void copy_plane(float2* __restrict__ dst, const float2* __restrict__ src) {
   const float4* s4 = reinterpret_cast<const float4*>(src);
   float4* d4 = reinterpret_cast<float4*>(dst);
-#pragma unroll 4
-  for (int i = threadIdx.x; i < SIZE / 2; i += THREADS) d4[i] = s4[i];
+  batched_copy<SIZE / 2, THREADS, float4>([&](int i) { return s4[i]; }, [&](int i, float4 v) { d4[i] = v; });
 }
 
 // Pass 1. grid = (N planes, batch). GRID: real grids `grid` [batch][N^3]
@@ -359,8 +436,7 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_fwd
                                                                                const float2* __restrict__ table) {
   using P = Plane<N>;
   __shared__ __attribute__((aligned(16))) float2 W[P::SIZE];
-  __shared__ Hit hits[GRID ? 1 : kChunk];
-  __shared__ int nhits;
+  __shared__ std::conditional_t<GRID, int, HitList> hl;  // hit list only when splatting
   const int x = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
   float* Wf = reinterpret_cast<float*>(W);
   const size_t plane_sz = (size_t)N * P::H;
@@ -371,17 +447,16 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_fwd
     if constexpr (GRID) {
       const float2* src = reinterpret_cast<const float2*>(grid + ((size_t)b * N + x) * N * N);
       // two adjacent z values of one row land in one pair-region entry each
-      for (int i = tid; i < N * N / 2; i += P::THREADS) {
+      batched_copy<N * N / 2, P::THREADS, float2>([&](int i) { return src[i]; }, [&](int i, float2 v) {
         const int y = (2 * i) / N, z = (2 * i) % N;
-        const float2 v = src[i];
         Wf[((y >> 1) * P::PAIR + z) * 2 + (y & 1)] = v.x;
         Wf[((y >> 1) * P::PAIR + z + 1) * 2 + (y & 1)] = v.y;
-      }
+      });
     } else {
       float4* W4 = reinterpret_cast<float4*>(W);
       for (int i = tid; i < P::SIZE / 2; i += P::THREADS) W4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
       __syncthreads();
-      splat_plane<N, P::WAVES, P::THREADS>(p, nullptr, b, x, chan, Wf, hits, &nhits, [](int yy, int zz) {
+      splat_plane<N, P::WAVES, P::THREADS>(p, nullptr, b, x, chan, Wf, hl, [](int yy, int zz) {
         return ((yy >> 1) * P::PAIR + zz) * 2 + (yy & 1);
       });
     }
@@ -409,14 +484,13 @@ template <int N>
 __global__ void __launch_bounds__(Plane<N>::THREADS) k_splat_real(SplatParams p, int nch, float* __restrict__ out) {
   using P = Plane<N>;
   __shared__ float U[N * N];
-  __shared__ Hit hits[kChunk];
-  __shared__ int nhits;
+  __shared__ HitList hl;
   const int x = blockIdx.x, tid = threadIdx.x;
   double R[9];
   load_rotation(p, 0, R);
   for (int i = tid; i < N * N; i += P::THREADS) U[i] = 0.f;
   __syncthreads();
-  splat_plane<N, P::WAVES, P::THREADS>(p, R, 0, x, 0, U, hits, &nhits, [](int yy, int zz) { return yy * N + zz; });
+  splat_plane<N, P::WAVES, P::THREADS>(p, R, 0, x, 0, U, hl, [](int yy, int zz) { return yy * N + zz; });
   __syncthreads();
   const size_t n3 = (size_t)N * N * N;
   for (int i = tid; i < N * N; i += P::THREADS) {
@@ -441,9 +515,9 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_inv
   __shared__ __attribute__((aligned(16))) float2 W[P::SIZE];
   const int x = blockIdx.x, b = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l = lane % L;
+  copy_plane<P::THREADS, P::SIZE>(W, in + ((size_t)b * N + x) * (size_t)P::SIZE);
   Twiddles<N> tw;
   load_twiddles<N>(tw, table, l);
-  copy_plane<P::THREADS, P::SIZE>(W, in + ((size_t)b * N + x) * (size_t)P::SIZE);
   __syncthreads();
   // y: columns 1 .. N/2-1 in place. The z C2R below keeps only the real part
   // of columns kz = 0 and kz = N/2, so both go through one transform of
@@ -517,10 +591,12 @@ template <int N, int G> struct Strip {
 template <int N, int G>
 __device__ __forceinline__ void strip_load(float2* S, const float2* __restrict__ src, int c0) {
   using T = Strip<N, G>;
-  for (int i = threadIdx.x; i < N * G; i += T::THREADS) {
-    const int x = i / G, g = i % G, c = c0 + g;
-    S[x * T::LD + g] = (c < T::C) ? src[(size_t)x * T::C + c] : make_float2(0.f, 0.f);
-  }
+  batched_copy<N * G, T::THREADS, float2>(
+      [&](int i) {
+        const int x = i / G, c = c0 + i % G;
+        return (c < T::C) ? src[(size_t)x * T::C + c] : make_float2(0.f, 0.f);
+      },
+      [&](int i, float2 v) { S[(i / G) * T::LD + i % G] = v; });
 }
 template <int N, int G>
 __device__ __forceinline__ void strip_store(const float2* S, float2* __restrict__ dst, int c0) {
@@ -577,18 +653,22 @@ __global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_corr(const flo
     __syncthreads();
     strip_fft<N, G, -1>(S, tw);
     __syncthreads();
-    for (int i = threadIdx.x; i < N * G; i += T::THREADS) {
-      const int x = i / G, g = i % G, c = c0 + g;
-      const float2 a = (c < T::C) ? Ab[(size_t)x * T::C + c] : make_float2(0.f, 0.f);
-      S[x * T::LD + g] = cmulc(a, S[x * T::LD + g]);
-    }
+    batched_copy<N * G, T::THREADS, float2>(
+        [&](int i) {
+          const int x = i / G, c = c0 + i % G;
+          return (c < T::C) ? Ab[(size_t)x * T::C + c] : make_float2(0.f, 0.f);
+        },
+        [&](int i, float2 a) {
+          float2* e = &S[(i / G) * T::LD + i % G];
+          *e = cmulc(a, *e);
+        });
   } else {
-    for (int i = threadIdx.x; i < N * G; i += T::THREADS) {
-      const int x = i / G, g = i % G, c = c0 + g;
-      float2 v = make_float2(0.f, 0.f);
-      if (c < T::C) v = cmulc(Ab[(size_t)x * T::C + c], B[boff + (size_t)x * T::C + c]);
-      S[x * T::LD + g] = v;
-    }
+    batched_copy<N * G, T::THREADS, float2>(
+        [&](int i) {
+          const int x = i / G, c = c0 + i % G;
+          return (c < T::C) ? cmulc(Ab[(size_t)x * T::C + c], B[boff + (size_t)x * T::C + c]) : make_float2(0.f, 0.f);
+        },
+        [&](int i, float2 v) { S[(i / G) * T::LD + i % G] = v; });
   }
   __syncthreads();
   strip_fft<N, G, +1>(S, tw);
