@@ -33,6 +33,7 @@ from .core import (  # noqa: F401
     torque_field_moment,
     torque_field_cross,
     single_pose_sum,
+    local_pose_sum,
     lattice_read,
     trilinear_read,
     pair_fields,

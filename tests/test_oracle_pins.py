@@ -481,6 +481,21 @@ def test_single_pose_sum_equals_lattice_fields():
         assert np.abs(s - ref).max() < 1e-10 * scale
 
 
+@pytest.mark.parametrize("n", [12, 15])
+def test_local_pose_sum_equals_lattice_fields(n):
+    """The physical-space sums with the gradient on A reproduce the spectral
+    fields at every sampled lattice translation (odd and even n, rotated B)."""
+    A, B = _small_pair(n, seed=41 + n, npts=40, conf=3.0)
+    R = synth.shoemake_rotations(7, 1)[0]
+    d = _fields(A, B, n, R=R)
+    scale = max(np.abs(d["E"]).max(), np.abs(d["F"]).max(), np.abs(d["tau"]).max())
+    for t in [(0, 0, 0), (1, 5, 11), (6, 6, 6), (n - 1, 2, 9), (-3, 4, 20)]:
+        s = O.local_pose_sum(d["uA"], d["uB"], t)
+        tl = tuple(int(v) % n for v in t)
+        ref = np.concatenate([[d["E"][tl]], d["F"][(slice(None), *tl)], d["tau"][(slice(None), *tl)]])
+        assert np.abs(s - ref).max() < 1e-10 * scale
+
+
 def test_trilinear_read_is_exact_on_lattice_and_linear_between():
     n = 8
     f = np.random.default_rng(2).standard_normal((n, n, n))
