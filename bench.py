@@ -14,6 +14,7 @@ timed with HIP events on its launch stream over the timed region.
 """
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -25,6 +26,31 @@ if ROOT not in sys.path:
 
 METRIC = "3D xcorr fields/sec and HBM GB/s at 128³; p99 force-query latency"
 HBM_PEAK_GBPS = 8000.0
+
+# HBM bytes per launch of each field kernel at 128^3 x 64, from rocprofv3
+# counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, KiB -> bytes; the factors
+# make a plain 512 MiB device copy read and write 512 MiB). Valid only for the
+# kernel sources they were taken on: reported as null once those change.
+COUNTER_TRAFFIC = {
+    "sources_sha256": "89f676efa773f1d7baa3c6d62e51bcf514243d54d761b083d4750715caefb5c0",
+    "bytes": {"bin": (188.9 * 2 + 4036.0) * 1024, "plane_fwd": (18299.9 * 2 + 532480.0) * 1024,
+              "strip": (479576.0 * 2 + 532480.0) * 1024, "plane_inv": (266314.4 * 2 + 524776.6) * 1024},
+}
+KERNEL_SOURCES = ("ga_fft.hpp", "ga_kernels.hpp", "ga_launch.hpp")
+
+
+def kernel_sources_sha256():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1711_05017_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counter_traffic(kernel):
+    if COUNTER_TRAFFIC["sources_sha256"] != kernel_sources_sha256():
+        return None
+    return int(COUNTER_TRAFFIC["bytes"][kernel])
 
 
 def algorithmic_bytes(n, batch, n_pts):
@@ -67,6 +93,72 @@ def cpu_baseline(a, budget_s=12.0):
                       f"single-threaded numpy), {dt:.1f} s"}
 
 
+def serving_leg(n_queries, rate_hz, max_slots=8, mode="local"):
+    """Serving loop under Poisson load: 16 assemblies with grid edges from
+    {64, 96, 128, 192}, each query a new rotation and a lattice translation
+    near contact. Latency = the library's completion time minus its
+    acceptance time of the query (steady clock)."""
+    import numpy as np
+
+    import paper_1711_05017_amd as G
+    import synth
+
+    wl = synth.config_c5(n_queries=n_queries, rate_hz=rate_hz)
+    srv = G.Server(device=0, hbm_budget_bytes=8 << 30, max_slots=max_slots, queue_depth=1 << 16,
+                   mode=G.GA_SERVE_LOCAL if mode == "local" else G.GA_SERVE_SPECTRAL)
+    try:
+        pids = [srv.register_pair(a.A.xyzr, a.A.w, a.B.xyzr, a.B.w, a.cB, a.n, a.sigma) for a in wl.assemblies]
+        sizes = np.array([a.n for a in wl.assemblies])
+        # warm-up: one query per assembly
+        for pid in pids:
+            srv.wait(srv.submit(pid, np.eye(3), [0, 0, 0]))
+        # one loop: submit each query at its arrival time, otherwise poll the
+        # oldest outstanding one (results carry the library's own timestamps)
+        tickets = [None] * n_queries
+        results = [None] * n_queries
+        rejected = 0
+        i_sub = i_poll = 0
+        t0 = time.perf_counter()
+        while i_poll < n_queries:
+            if i_sub < n_queries and time.perf_counter() - t0 >= wl.arrival_s[i_sub]:
+                tk = srv.submit(pids[wl.pair[i_sub]], wl.rotations[i_sub], wl.poses[i_sub])
+                if tk is None:
+                    rejected += 1
+                    continue
+                tickets[i_sub] = tk
+                i_sub += 1
+                if i_sub == n_queries:
+                    t_sub = time.perf_counter() - t0
+                continue
+            if i_poll < i_sub:
+                r = srv.poll(tickets[i_poll])
+                if r is not None:
+                    results[i_poll] = r
+                    i_poll += 1
+        lat = np.array([(r.t_done_ns - r.t_submit_ns) / 1e3 for r in results])
+        qsize = sizes[wl.pair]
+        first = min(r.t_submit_ns for r in results)
+        last = max(r.t_done_ns for r in results)
+        st = srv.stats()
+
+        def pct(x):
+            return {"p50_us": round(float(np.percentile(x, 50)), 1), "p99_us": round(float(np.percentile(x, 99)), 1),
+                    "p999_us": round(float(np.percentile(x, 99.9)), 1), "n": int(x.size)}
+
+        mixed = lat[qsize <= 128]
+        return {
+            "queries": n_queries, "offered_rate_hz": rate_hz, "achieved_submit_rate_hz": round(n_queries / t_sub, 1),
+            "throughput_qps": round(n_queries / ((last - first) / 1e9), 1),
+            "all": pct(lat), "grid_64_128": pct(mixed),
+            "by_grid": {int(n): pct(lat[qsize == n]) for n in sorted(set(sizes.tolist()))},
+            "p99_target_us_64_128": 1000.0, "meets_p99_target": bool(np.percentile(mixed, 99) < 1000.0),
+            "launch_groups": int(st.launches), "rejected_full": int(st.rejected_full + rejected),
+            "max_slots": max_slots, "mode": mode,
+        }
+    finally:
+        srv.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +166,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-queries", type=int, default=100000)
+    ap.add_argument("--serving-rate", type=float, default=16000.0)
+    ap.add_argument("--serving-mode", choices=["local", "spectral"], default="local",
+                    help="how the server evaluates a query: local sums over the moving part's balls, or its "
+                         "splat + R2C + single-translation spectral sum")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB, three times (the known-size "
+                         "kernel that scales the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the field path would shard by rotation "
@@ -89,6 +190,15 @@ def main():
     G.lib()
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if args.copy_calibration_mb:
+        nbytes = args.copy_calibration_mb << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": nbytes, "bytes_written": nbytes, "launches": 3}), flush=True)
+        return
     a = synth.config_c3(args.batch)
     n, batch = a.n, a.rotations.shape[0]
     plan = G.Plan(n, max_batch=batch)
@@ -142,9 +252,11 @@ def main():
         "path_GBps_algorithmic": round(step_bytes * args.steps / wall / 1e9, 1),
         "kernel_ms": {k: round(v, 4) for k, v in kern.items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": counter_traffic(dom),
                      "algorithmic_bytes_per_launch": abytes[dom]},
     }
+    if not args.no_serving:
+        out["serving"] = serving_leg(args.serving_queries, args.serving_rate, mode=args.serving_mode)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a)
     print(json.dumps(out), flush=True)

@@ -88,6 +88,8 @@ typedef int32_t ga_status;
 #define GA_OP_ENERGY 3
 #define GA_OP_FORCE_FIELDS 4
 #define GA_OP_FORCE_SINGLE 5
+#define GA_OP_FIELD_GRAD 6
+#define GA_OP_POSE_LOCAL 7
 
 typedef struct ga_plan ga_plan;
 
@@ -111,9 +113,10 @@ ga_status ga_plan_create(ga_plan** plan, int32_t n, int32_t max_batch, uint32_t 
 ga_status ga_plan_destroy(ga_plan* plan);
 int32_t ga_plan_n(const ga_plan* plan);
 
-/* Workspace bytes that operation `op` needs for `batch` fields; n_items is
- * the number of skeleton samples for GA_OP_ENERGY and the number of poses
- * for GA_OP_FORCE_SINGLE (ignored otherwise). 0 for an unknown op. */
+/* Workspace bytes that operation `op` needs for `batch` fields (or poses for
+ * GA_OP_POSE_LOCAL); n_items is the number of skeleton samples for
+ * GA_OP_ENERGY and GA_OP_POSE_LOCAL and the number of poses for
+ * GA_OP_FORCE_SINGLE (ignored otherwise). 0 for an unknown op. */
 size_t ga_workspace_size(const ga_plan* plan, int32_t op, int32_t batch, int64_t n_items);
 
 /*
@@ -182,6 +185,33 @@ ga_status ga_force_torque(const ga_plan* plan, const float* d_Ahat, const float*
                           hipStream_t stream);
 
 /*
+ * Resident field of the stationary part for single-translation queries:
+ * d_FA4[v] = (u_A, d_x u_A, d_y u_A, d_z u_A) at voxel v (float4 per voxel,
+ * n^3 of them), the gradient being the spectral derivative of eq. 6a,
+ * Re IFFT(2 pi i omega_a Ahat). d_uA: the density (ga_splat), d_Ahat: its
+ * spectrum (ga_fft3d). Workspace: GA_OP_FIELD_GRAD.
+ */
+ga_status ga_field_grad(const ga_plan* plan, const float* d_uA, const float* d_Ahat, float* d_FA4, void* d_work,
+                        size_t work_bytes, hipStream_t stream);
+
+/*
+ * Energy, force and torque at n_poses single poses, pose b being rotation
+ * d_R[b] (9 floats) of the moving part about h_c and translation d_t[b]
+ * (rounded to the nearest lattice point like GA_SINGLE), by local sums over
+ * the moving part's balls only:
+ *   E = sum_q u_A(q + t) u_B(q),   F = -sum_q grad u_A(q + t) u_B(q),
+ *   tau = sum_q grad u_A(q + t) x yhat(q) u_B(q),
+ * which equal the partial sums of eq. 7b that GA_SINGLE computes (the
+ * spectral derivative moves from B to A by summation by parts), with
+ * O(support of B) work and no transform of the moving part. d_FA4 from
+ * ga_field_grad. d_out7: n_poses x 7 floats. Workspace: GA_OP_POSE_LOCAL
+ * with batch = n_poses and n_items = n_pts.
+ */
+ga_status ga_pose_local(const ga_plan* plan, const float* d_FA4, const float* d_xyzr, const float* d_w, int64_t n_pts,
+                        const float* d_R, const float* h_c, float sigma, const float* d_t, int32_t n_poses,
+                        float* d_out7, void* d_work, size_t work_bytes, hipStream_t stream);
+
+/*
  * Per-kernel timing. With profiling enabled, every kernel the plan launches
  * is bracketed by two HIP events recorded on its launch stream.
  * ga_profile_read waits for the recorded events and returns, for one kernel
@@ -199,6 +229,85 @@ ga_status ga_force_torque(const ga_plan* plan, const float* d_Ahat, const float*
 
 ga_status ga_profile_enable(ga_plan* plan, int32_t enable);
 ga_status ga_profile_read(ga_plan* plan, int32_t kind, double* total_ms, int64_t* launches);
+
+/*
+ * Serving loop (Sec. 4.2: the haptic loop has a budget t0 of about 1 ms per
+ * frame; Sec. 3.3: one translation per query). A server keeps, for every
+ * registered part pair, the stationary part's spectrum and the moving part's
+ * samples resident in device memory, and answers pose queries: each query is
+ * a new rotation R of the moving part about its reference point and a
+ * translation t; its answer is (E, F, tau) at round(t) for that rotation:
+ * the GA_SINGLE readout of ga_force_torque after a 4-channel splat and
+ * R2C of the rotated part (GA_SERVE_SPECTRAL), or the equal local sums of
+ * ga_pose_local (GA_SERVE_LOCAL).
+ *
+ * Continuous batching: queries wait in a queue per grid size; a scheduler
+ * thread moves up to max_slots of them into a free execution slot group
+ * (two per grid size, each with its own stream) as soon as one is free, so
+ * queries that arrive while others run are admitted as slots free up and
+ * the groups of different sizes run concurrently on the device. Every query
+ * is computed independently of the others in its group: its result does not
+ * depend on the mix, up to float32 rounding of the splat's accumulation.
+ * All device memory the server holds (spectra, samples, slot scratch) is
+ * charged to hbm_budget_bytes; registration fails with GA_ENOMEM beyond it.
+ * Calls are thread-safe. A device error is sticky: later calls return
+ * GA_EDEVICE.
+ */
+typedef struct ga_server ga_server;
+
+#define GA_SERVE_LOCAL 0u    /* queries by ga_pose_local sums (resident u_A and grad u_A) */
+#define GA_SERVE_SPECTRAL 1u /* queries by splat, R2C and the GA_SINGLE partial sum (resident Ahat) */
+
+typedef struct {
+  int32_t device;            /* HIP device ordinal */
+  uint64_t hbm_budget_bytes; /* device memory the server may hold */
+  int32_t max_slots;         /* queries per launch group (1 .. 256) */
+  int32_t queue_depth;       /* queued queries before ga_submit returns GA_EAGAIN */
+  uint32_t mode;             /* GA_SERVE_LOCAL or GA_SERVE_SPECTRAL; both give the same values */
+} ga_server_cfg;
+
+typedef struct {
+  const float* xyzr; /* host, n_pts x 4 floats (x, y, z, r) */
+  const float* w;    /* host, n_pts floats */
+  int64_t n_pts;
+} ga_part;
+
+typedef struct {
+  float E;
+  float F[3];
+  float tau[3];
+  uint64_t t_submit_ns; /* steady clock, when ga_submit accepted the query */
+  uint64_t t_start_ns;  /* when its group was launched */
+  uint64_t t_done_ns;   /* when the scheduler saw its group complete */
+} ga_result;
+
+typedef struct {
+  uint64_t submitted, completed, launches, rejected_full;
+  uint64_t bytes_in_use;
+  int32_t pairs;
+} ga_server_stats;
+
+ga_status ga_server_create(ga_server** server, const ga_server_cfg* cfg);
+ga_status ga_server_destroy(ga_server* server); /* waits for queued queries */
+
+/* Registers a part pair on an n^3 grid with thickness sigma: A (stationary,
+ * grid coordinates) and B (moving, rotated about cB). The host arrays are
+ * copied. Computes A's spectrum on the device before returning. */
+ga_status ga_pair_register(ga_server* server, const ga_part* A, const ga_part* B, const float cB[3], int32_t n,
+                           float sigma, uint32_t* pair_id);
+/* Releases a pair once its queued queries have completed. */
+ga_status ga_pair_release(ga_server* server, uint32_t pair_id);
+
+/* Queues one query. R: 9 floats row-major, proper orthogonal within 1e-4; t:
+ * 3 finite floats (voxels). Non-blocking; GA_EAGAIN when the queue is full,
+ * GA_ENOTFOUND for an unknown pair. */
+ga_status ga_submit(ga_server* server, uint32_t pair_id, const float R[9], const float t[3], uint64_t* ticket);
+
+/* GA_OK with the result (once per ticket; the ticket is then forgotten),
+ * GA_PENDING while queued or running, GA_ENOTFOUND for an unknown ticket. */
+ga_status ga_poll(ga_server* server, uint64_t ticket, ga_result* out);
+
+ga_status ga_server_get_stats(ga_server* server, ga_server_stats* out);
 
 #ifdef __cplusplus
 }

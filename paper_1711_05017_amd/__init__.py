@@ -9,13 +9,18 @@ from .ga import (  # noqa: F401
     GA_C2R,
     GA_FIELDS,
     GA_R2C,
+    GA_SERVE_LOCAL,
+    GA_SERVE_SPECTRAL,
     GA_SINGLE,
     GaError,
     Plan,
+    Server,
     ga_correlate,
     ga_energy_fields,
     ga_fft3d,
+    ga_field_grad,
     ga_force_torque,
+    ga_pose_local,
     ga_splat,
     ga_supported_n,
 )

@@ -6,7 +6,7 @@ import subprocess
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libga.so")
-SRC = os.path.join(PKG, "csrc", "ga_lib.hip")
+SRCS = [os.path.join(PKG, "csrc", f) for f in ("ga_lib.hip", "ga_server.hip")]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -28,11 +28,12 @@ def sources():
 
 
 def build_lib(verbose: bool = False) -> str:
-    """Compile csrc/ga_lib.hip into paper_1711_05017_amd/libga.so (always
-    recompiles). Returns the library path."""
+    """Compile csrc/ga_lib.hip and csrc/ga_server.hip into
+    paper_1711_05017_amd/libga.so (always recompiles). Returns the library
+    path."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-o", tmp, SRC]
+    cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-o", tmp, *SRCS, "-lpthread"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + res.stdout + res.stderr)

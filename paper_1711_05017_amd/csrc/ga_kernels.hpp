@@ -118,21 +118,19 @@ __device__ __forceinline__ bool place_sample(const SplatParams& p, const double*
   return true;
 }
 
-// Per batch member: place every sample once, counting sort by bx into
-// rec[b*n_pts ...], bin offsets off[b*(N+1) + i], largest radius rmax[b].
-// grid = batch, block = 256.
+// Places every sample of one part once and counting-sorts the records by
+// bx: records rb[0 .. count), bin offsets ob[0 .. N] (ob[N] = count), largest
+// radius *rm. One workgroup of 256 threads.
 template <int N>
-__global__ void __launch_bounds__(256) k_bin_samples(SplatParams p, Placed* __restrict__ rec, int* __restrict__ off,
-                                                     float* __restrict__ rmax) {
+__device__ void bin_block(const SplatParams& p, const double* R, Placed* __restrict__ rb, int* __restrict__ ob,
+                          float* __restrict__ rm) {
   __shared__ int cnt[N];
   __shared__ int cur[N];
   __shared__ int s_rmax;
-  const int b = blockIdx.x, tid = threadIdx.x;
+  const int tid = threadIdx.x;
   for (int i = tid; i < N; i += 256) cnt[i] = 0;
   if (tid == 0) s_rmax = __float_as_int(1.0f);
   __syncthreads();
-  double R[9];
-  load_rotation(p, b, R);
   for (long long s = tid; s < p.n_pts; s += 256) {
     Placed q;
     if (place_sample<N>(p, R, s, q)) {
@@ -141,7 +139,6 @@ __global__ void __launch_bounds__(256) k_bin_samples(SplatParams p, Placed* __re
     }
   }
   __syncthreads();
-  int* ob = off + (size_t)b * (N + 1);
   if (tid < 64) {
     // exclusive scan of the N bin counts by one wave, 64 bins per step
     int carry = 0;
@@ -161,15 +158,61 @@ __global__ void __launch_bounds__(256) k_bin_samples(SplatParams p, Placed* __re
     }
     if (tid == 0) {
       ob[N] = carry;
-      rmax[b] = __int_as_float(s_rmax);
+      *rm = __int_as_float(s_rmax);
     }
   }
   __syncthreads();
-  Placed* rb = rec + (size_t)b * p.n_pts;
   for (long long s = tid; s < p.n_pts; s += 256) {
     Placed q;
     if (place_sample<N>(p, R, s, q)) rb[atomicAdd(&cur[q.b.x], 1)] = q;
   }
+}
+
+// Per batch member b: the moving part rotated by R_b, binned into
+// rec[b*n_pts ...], off[b*(N+1) ...], rmax[b]. grid = batch, block = 256.
+template <int N>
+__global__ void __launch_bounds__(256) k_bin_samples(SplatParams p, Placed* __restrict__ rec, int* __restrict__ off,
+                                                     float* __restrict__ rmax) {
+  const int b = blockIdx.x;
+  double R[9];
+  load_rotation(p, b, R);
+  bin_block<N>(p, R, rec + (size_t)b * p.n_pts, off + (size_t)b * (N + 1), rmax + b);
+}
+
+// One query of the serving loop: a registered pair (its moving part's
+// samples and the resident stationary spectrum), a rotation about c and a
+// lattice translation (already reduced mod N).
+struct QueryItem {
+  const float4* xyzr;
+  const float* w;
+  long long n_pts;
+  const float2* Ahat;  // spectral queries: stationary spectrum
+  const float4* FA;    // local queries: (u_A, grad u_A) per voxel
+  float R[9];
+  float c[3];
+  int t[3];
+  int pad;
+};
+
+// Binning of heterogeneous queries: item b's samples, placed with its own
+// rotation, into rec[b*stride ...]. grid = batch, block = 256.
+template <int N>
+__global__ void __launch_bounds__(256) k_bin_items(const QueryItem* __restrict__ items, SplatParams base,
+                                                   long long stride, Placed* __restrict__ rec, int* __restrict__ off,
+                                                   float* __restrict__ rmax) {
+  const int b = blockIdx.x;
+  const QueryItem& it = items[b];
+  SplatParams p = base;
+  p.xyzr = it.xyzr;
+  p.w = it.w;
+  p.n_pts = it.n_pts;
+  p.c[0] = it.c[0];
+  p.c[1] = it.c[1];
+  p.c[2] = it.c[2];
+  double R[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) R[i] = (double)it.R[i];
+  bin_block<N>(p, R, rec + (size_t)b * stride, off + (size_t)b * (N + 1), rmax + b);
 }
 
 // Candidate hit test of one placed sample against plane x; appends it and
@@ -328,8 +371,8 @@ __device__ void plane_forward_lds(float2* W, const Twiddles<N>& tw) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l = lane % L;
   // z: one complex FFT per pair of real rows, then split into the two halves
-  for (int t0 = wave * TPW; t0 < N / 2; t0 += P::WAVES * TPW) {
-    const int t = t0 + lane / L;
+  for (int it = 0; it * P::WAVES * TPW < N / 2; ++it) {
+    const int t = (it * P::WAVES + wave) * TPW + lane / L;
     if (t < N / 2) {
       float2* reg = W + t * P::PAIR;
       fft_inplace<N, -1>(l, tw, reg, 1);
@@ -360,8 +403,8 @@ __device__ void plane_forward_lds(float2* W, const Twiddles<N>& tw) {
   __syncthreads();
   // y: columns 1 .. N/2-1 in place; column 0 carries the real columns kz = 0
   // (real part) and kz = N/2 (imaginary part) and is split afterwards.
-  for (int t0 = wave * TPW; t0 < N / 2; t0 += P::WAVES * TPW) {
-    const int t = t0 + lane / L;
+  for (int it = 0; it * P::WAVES * TPW < N / 2; ++it) {
+    const int t = (it * P::WAVES + wave) * TPW + lane / L;
     if (t < N / 2) {
       float2* col = W + t;
       auto ld = [&](int pos) -> float2 {
@@ -440,9 +483,7 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_fwd
   const int x = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
   float* Wf = reinterpret_cast<float*>(W);
   const size_t plane_sz = (size_t)N * P::H;
-  constexpr int NPASS = (NCH == 4) ? 3 : 1;
-#pragma unroll 1
-  for (int pass = 0; pass < NPASS; ++pass) {
+  auto run_pass = [&](int pass) {
     const int chan = (pass == 0) ? 0 : pass + 1;  // 0, 2, 3
     if constexpr (GRID) {
       const float2* src = reinterpret_cast<const float2*>(grid + ((size_t)b * N + x) * N * N);
@@ -475,6 +516,14 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_fwd
       }
     }
     __syncthreads();
+  };
+  if constexpr (NCH == 1) {
+    run_pass(0);
+  } else if (gridDim.z > 1) {
+    run_pass(blockIdx.z);  // one channel pass per workgroup
+  } else {
+#pragma unroll 1
+    for (int pass = 0; pass < 3; ++pass) run_pass(pass);
   }
 }
 
@@ -523,8 +572,8 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_inv
   // of columns kz = 0 and kz = N/2, so both go through one transform of
   // c = h(col0) + i h(colN/2), h(a)(k) = (a(k) + conj a(-k))/2, whose
   // inverse is Re IFFT(col0) + i Re IFFT(colN/2).
-  for (int t0 = wave * TPW; t0 < N / 2; t0 += P::WAVES * TPW) {
-    const int t = t0 + lane / L;
+  for (int it = 0; it * P::WAVES * TPW < N / 2; ++it) {
+    const int t = (it * P::WAVES + wave) * TPW + lane / L;
     if (t < N / 2) {
       float2* col = W + t;
       auto ld = [&](int pos) -> float2 {
@@ -549,8 +598,8 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_inv
   }
   __syncthreads();
   float* dst = out + ((size_t)b * N + x) * (size_t)N * N;
-  for (int t0 = wave * TPW; t0 < N / 2; t0 += P::WAVES * TPW) {
-    const int t = t0 + lane / L;
+  for (int it = 0; it * P::WAVES * TPW < N / 2; ++it) {
+    const int t = (it * P::WAVES + wave) * TPW + lane / L;
     if (t < N / 2) {
       float2* reg = W + t * P::PAIR;
       // Z(k) = A(k) + i B(k), completed by Hermitian symmetry; A, B are the
@@ -589,7 +638,7 @@ template <int N, int G> struct Strip {
 };
 
 template <int N, int G>
-__device__ __forceinline__ void strip_load(float2* S, const float2* __restrict__ src, int c0) {
+__device__ __forceinline__ void strip_load(float2* S, const float2* src, int c0) {
   using T = Strip<N, G>;
   batched_copy<N * G, T::THREADS, float2>(
       [&](int i) {
@@ -599,7 +648,7 @@ __device__ __forceinline__ void strip_load(float2* S, const float2* __restrict__
       [&](int i, float2 v) { S[(i / G) * T::LD + i % G] = v; });
 }
 template <int N, int G>
-__device__ __forceinline__ void strip_store(const float2* S, float2* __restrict__ dst, int c0) {
+__device__ __forceinline__ void strip_store(const float2* S, float2* dst, int c0) {
   using T = Strip<N, G>;
   for (int i = threadIdx.x; i < N * G; i += T::THREADS) {
     const int x = i / G, g = i % G, c = c0 + g;
@@ -616,9 +665,10 @@ __device__ __forceinline__ void strip_fft(float2* S, const Twiddles<N>& tw) {
 
 // x FFT of a strip of columns, in place or out of place.
 // grid = (ceil(C/G), batch); element stride between batch members = N*C.
+// in and out may be the same buffer (in-place transform), so neither is
+// declared __restrict__.
 template <int N, int G, int DIR>
-__global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_fft(const float2* __restrict__ in,
-                                                                    float2* __restrict__ out,
+__global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_fft(const float2* in, float2* out,
                                                                     const float2* __restrict__ table) {
   using T = Strip<N, G>;
   __shared__ float2 S[N * T::LD];
@@ -636,10 +686,11 @@ __global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_fft(const floa
 // Conjugate product with the stationary spectrum and inverse x FFT.
 // FWD = true: `B` holds pass-1 output (x not yet transformed): forward x FFT
 // first (the fused field path). FWD = false: `B` is a full spectrum.
+// B and out may be the same buffer (the fused path works in place), so
+// neither is declared __restrict__.
 template <int N, int G, bool FWD>
 __global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_corr(const float2* __restrict__ A, long long a_stride,
-                                                                     const float2* __restrict__ B,
-                                                                     float2* __restrict__ out,
+                                                                     const float2* B, float2* out,
                                                                      const float2* __restrict__ table) {
   using T = Strip<N, G>;
   __shared__ float2 S[N * T::LD];
@@ -790,6 +841,249 @@ __global__ void __launch_bounds__(256) k_single_partials(const float2* __restric
   }
 }
 
+// Serving path, pass 2: for query b and one strip of G columns, the x FFT of
+// each of the 4 channels (u, m_x, m_y, m_z; x not yet transformed) and the
+// partial sums over the strip of w(kz) Re[P_o(k) exp(+2 pi i k.t/N)] of the 7
+// products of eq. 5, 6a, 6b, in float64. The sums are linear in each channel,
+// so the channels pass through one LDS strip in turn:
+//   u:    E += Re z, F_a += 2 pi w_a Im z,           z = A conj(u) e
+//   m_b:  Q_b = Re[2 pi i conj(m_b) A e] = -2 pi Im z_b
+//         tau_x = w_y Q_z - w_z Q_y, tau_y = w_z Q_x - w_x Q_z,
+//         tau_z = w_x Q_y - w_y Q_x.
+// part[(b*nblk + blk)*7 + o]; grid = (nblk, batch).
+template <int N, int G>
+__global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_single(const float2* __restrict__ B4,
+                                                                         const QueryItem* __restrict__ items,
+                                                                         double* __restrict__ part,
+                                                                         const float2* __restrict__ table) {
+  using T = Strip<N, G>;
+  __shared__ float2 S[N * T::LD];
+  __shared__ float2 As[N * T::LD];
+  __shared__ float2 tab[N];
+  __shared__ double red[T::WAVES][7];
+  const int tid = threadIdx.x, b = blockIdx.y;
+  const QueryItem& it = items[b];
+  const int t0 = it.t[0], t1 = it.t[1], t2 = it.t[2];
+  const size_t spec = (size_t)N * T::C;
+  const int c0 = blockIdx.x * G;
+  for (int i = tid; i < N; i += T::THREADS) tab[i] = table[i];
+  strip_load<N, G>(As, it.Ahat, c0);
+  Twiddles<N> tw;
+  load_twiddles<N>(tw, table, (tid & 63) % T::L);
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 1
+  for (int ch = 0; ch < 4; ++ch) {
+    strip_load<N, G>(S, B4 + ((size_t)b * 4 + ch) * spec, c0);
+    __syncthreads();
+    strip_fft<N, G, -1>(S, tw);
+    __syncthreads();
+    for (int i = tid; i < N * G; i += T::THREADS) {
+      const int x = i / G, g = i % G, c = c0 + g;
+      if (c < T::C) {
+        const int ky = c / T::H, kz = c % T::H;
+        const int m = (int)(((long long)x * t0 + (long long)ky * t1 + (long long)kz * t2) % N);
+        const float2 e = make_float2(tab[m].x, -tab[m].y);  // exp(+2 pi i m / N)
+        const float2 z = cmul(cmulc(As[x * T::LD + g], S[x * T::LD + g]), e);
+        const double wgt = (kz == 0 || kz == N / 2) ? 1.0 : 2.0;
+        const float wx = omega_of<N>(x), wy = omega_of<N>(ky), wz = omega_of<N>(kz);
+        if (ch == 0) {
+          acc[0] += wgt * z.x;
+          acc[1] += wgt * (kTwoPi * wx * z.y);
+          acc[2] += wgt * (kTwoPi * wy * z.y);
+          acc[3] += wgt * (kTwoPi * wz * z.y);
+        } else {
+          const double q = wgt * (-kTwoPi * z.y);
+          if (ch == 1) {
+            acc[5] += wz * q;
+            acc[6] -= wy * q;
+          } else if (ch == 2) {
+            acc[4] -= wz * q;
+            acc[6] += wx * q;
+          } else {
+            acc[4] += wy * q;
+            acc[5] -= wx * q;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int o = 0; o < 7; ++o) {
+    double v = acc[o];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((tid & 63) == 0) red[tid >> 6][o] = v;
+  }
+  __syncthreads();
+  if (tid < 7) {
+    double sum = 0;
+    for (int wv = 0; wv < T::WAVES; ++wv) sum += red[wv][tid];
+    part[((size_t)b * gridDim.x + blockIdx.x) * 7 + tid] = sum;
+  }
+}
+
+// Spectral gradient spectra of the stationary part: out3[a] = 2 pi i w_a Ahat
+// (eq. 6a multiplier; the C2R that follows applies 1/N^3).
+template <int N>
+__global__ void k_grad_spectra(const float2* __restrict__ A, float2* __restrict__ out3) {
+  constexpr int H = N / 2 + 1;
+  const size_t spec = (size_t)N * N * H;
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= spec) return;
+  const int kz = (int)(e % H), ky = (int)((e / H) % N), kx = (int)(e / ((size_t)N * H));
+  const float2 a = A[e];
+  const float w3[3] = {omega_of<N>(kx), omega_of<N>(ky), omega_of<N>(kz)};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) out3[d * spec + e] = make_float2(-kTwoPi * w3[d] * a.y, kTwoPi * w3[d] * a.x);
+}
+
+// Exact division of small non-negative integers through a float reciprocal
+// with one correction step (the estimate is within one for v < 2^24).
+__device__ __forceinline__ int divq(int v, int d, float rcp) {
+  int q = (int)((float)v * rcp);
+  q -= (q * d > v) ? 1 : 0;
+  q += ((q + 1) * d <= v) ? 1 : 0;
+  return q;
+}
+
+// Single-translation energy, force and torque by local sums over the moving
+// part's balls (equal to the partial sum of eq. 7b: moving the spectral
+// derivative from B to A is summation by parts, the multiplier being
+// anti-Hermitian):
+//   E = sum_q u_A(q + t) u_B(q),  F = -sum_q grad u_A(q + t) u_B(q),
+//   tau = sum_q grad u_A(q + t) x yhat(q) u_B(q),
+// u_B(q) = sum_j w_j K(|q - y_j|) on the torus, yhat the minimum-image
+// coordinate. Item b = blockIdx.y, samples [blk*SPB, blk*SPB + SPB) of it;
+// partials in float64 to part[(b*gridDim.x + blk)*7 + o]. block = 256.
+constexpr int kLocalSPB = 64;
+template <int N>
+__global__ void __launch_bounds__(256) k_local_query(const QueryItem* __restrict__ items, double* __restrict__ part,
+                                                     float sig_c, float e0, float inv1me0) {
+  // a ball's box holds at most N^3 voxels (rho < N/2): divq needs < 2^24 and
+  // the block's 64 boxes must sum below 2^31
+  static_assert(N <= 256, "local query box sizes");
+  __shared__ float4 sf[kLocalSPB];   // fx, fy, fz, w
+  __shared__ int4 sb[kLocalSPB];     // bx, by, bz (B-frame voxel base), ez
+  __shared__ int4 sl[kLocalSPB];     // box origin offsets lox, loy, loz, ey
+  __shared__ float2 sr[kLocalSPB];   // rho^2, 1/(2 s^2)
+  __shared__ int scnt[kLocalSPB + 1];
+  __shared__ int sn;
+  __shared__ double red[4][7];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const QueryItem& it = items[blockIdx.y];
+  const long long s0 = (long long)blockIdx.x * kLocalSPB;
+  if (tid == 0) sn = 0;
+  __syncthreads();
+  if (tid < kLocalSPB && s0 + tid < it.n_pts) {
+    const float4 q = it.xyzr[s0 + tid];
+    const float w = it.w[s0 + tid];
+    const float rho = fmaxf(q.w, 1.0f);
+    int cnt = 0;
+    float fx = 0.f, fy = 0.f, fz = 0.f;
+    int bx = 0, by = 0, bz = 0, lx = 0, ly = 0, lz = 0, ey = 0, ez = 0;
+    if (rho < 0.5f * N && isfinite(w) && w != 0.0f) {
+      const double dx0 = (double)q.x - (double)it.c[0], dy0 = (double)q.y - (double)it.c[1],
+                   dz0 = (double)q.z - (double)it.c[2];
+      const double yx = (double)it.R[0] * dx0 + (double)it.R[1] * dy0 + (double)it.R[2] * dz0;
+      const double yy = (double)it.R[3] * dx0 + (double)it.R[4] * dy0 + (double)it.R[5] * dz0;
+      const double yz = (double)it.R[6] * dx0 + (double)it.R[7] * dy0 + (double)it.R[8] * dz0;
+      if (fabs(yx) < 1.0e7 && fabs(yy) < 1.0e7 && fabs(yz) < 1.0e7) {
+        const double gx = floor(yx), gy = floor(yy), gz = floor(yz);
+        fx = (float)(yx - gx);
+        fy = (float)(yy - gy);
+        fz = (float)(yz - gz);
+        long long ix = (long long)gx % N, iy = (long long)gy % N, iz = (long long)gz % N;
+        bx = (int)(ix < 0 ? ix + N : ix);
+        by = (int)(iy < 0 ? iy + N : iy);
+        bz = (int)(iz < 0 ? iz + N : iz);
+        lx = (int)ceilf(fx - rho);
+        ly = (int)ceilf(fy - rho);
+        lz = (int)ceilf(fz - rho);
+        const int ex = (int)floorf(fx + rho) - lx + 1;
+        ey = (int)floorf(fy + rho) - ly + 1;
+        ez = (int)floorf(fz + rho) - lz + 1;
+        cnt = ex * ey * ez;
+      }
+    }
+    sf[tid] = make_float4(fx, fy, fz, w);
+    sb[tid] = make_int4(bx, by, bz, ez);
+    sl[tid] = make_int4(lx, ly, lz, ey);
+    sr[tid] = make_float2(rho * rho, sig_c / (rho * rho));
+    scnt[tid] = cnt;
+    atomicMax(&sn, tid + 1);
+  }
+  __syncthreads();
+  const int ns = sn;
+  if (tid < 64) {  // exclusive scan of the box sizes (ns <= 64)
+    const int v = (tid < ns) ? scnt[tid] : 0;
+    int incl = v;
+    for (int d = 1; d < 64; d <<= 1) {
+      const int o = __shfl_up(incl, d, 64);
+      if (tid >= d) incl += o;
+    }
+    if (tid < ns) scnt[tid] = incl - v;
+    if (tid == 63) scnt[ns] = incl;
+  }
+  __syncthreads();
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  const int V = (ns > 0) ? scnt[ns] : 0;
+  const int per = (((V + 3) / 4) + 63) & ~63;  // contiguous voxel range per wave
+  const int g0 = wave * per, g1 = min(V, g0 + per);
+  if (g0 < g1) {
+    int lo = 0, hi = ns - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (scnt[mid] <= g0) lo = mid;
+      else hi = mid - 1;
+    }
+    int h = lo;
+    for (int gb = g0; gb < g1; gb += 64) {
+      const int g = gb + lane;
+      if (g < g1) {
+        while (scnt[h + 1] <= g) ++h;
+        const int v = g - scnt[h];
+        const int4 b = sb[h], l = sl[h];
+        const int eyz = l.w * b.w;
+        const int ox = divq(v, eyz, __builtin_amdgcn_rcpf((float)eyz));
+        const int rem = v - ox * eyz;
+        const int oy = divq(rem, b.w, __builtin_amdgcn_rcpf((float)b.w));
+        const int oz = rem - oy * b.w;
+        const float4 f = sf[h];
+        const float dx = (float)(l.x + ox) - f.x, dy = (float)(l.y + oy) - f.y, dz = (float)(l.z + oz) - f.z;
+        const float2 r = sr[h];
+        const float d2 = dx * dx + dy * dy + dz * dz;
+        if (d2 < r.x) {
+          const float cval = f.w * (__expf(-d2 * r.y) - e0) * inv1me0;  // w K(d): u_B contribution at q
+          const int qx = wrapn(b.x + l.x + ox, N), qy = wrapn(b.y + l.y + oy, N), qz = wrapn(b.z + l.z + oz, N);
+          const int px = wrapn(qx + it.t[0], N), py = wrapn(qy + it.t[1], N), pz = wrapn(qz + it.t[2], N);
+          const float4 fa = it.FA[((size_t)px * N + py) * N + pz];
+          const float hx = yhat(qx, N), hy = yhat(qy, N), hz = yhat(qz, N);
+          acc[0] += (double)(cval * fa.x);
+          acc[1] -= (double)(cval * fa.y);
+          acc[2] -= (double)(cval * fa.z);
+          acc[3] -= (double)(cval * fa.w);
+          acc[4] += (double)(cval * (fa.z * hz - fa.w * hy));
+          acc[5] += (double)(cval * (fa.w * hx - fa.y * hz));
+          acc[6] += (double)(cval * (fa.y * hy - fa.z * hx));
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 0; o < 7; ++o) {
+    double v = acc[o];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[wave][o] = v;
+  }
+  __syncthreads();
+  if (tid < 7) part[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 7 + tid] = red[0][tid] + red[1][tid] + red[2][tid] +
+                                                                              red[3][tid];
+}
+
+// Kernels without template parameters get internal linkage: the header is
+// included by more than one translation unit.
+namespace {
+
 // Sum of the per-strip partials of each pose in a fixed order, times scale.
 // grid = n_poses, block = 64.
 __global__ void __launch_bounds__(64) k_reduce_partials(const double* __restrict__ part, int nblk, float* __restrict__ out7,
@@ -840,5 +1134,39 @@ __global__ void k_gather7(const float* __restrict__ fields, int n, const float* 
       }
   out7[p * 7 + o] = acc;
 }
+
+// Interleaves u and its three gradient fields into one float4 per voxel.
+__global__ void k_pack4(const float* __restrict__ u, const float* __restrict__ g3, float4* __restrict__ FA,
+                        long long n3) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n3) FA[i] = make_float4(u[i], g3[i], g3[n3 + i], g3[2 * n3 + i]);
+}
+
+// Query descriptors for a batch of (rotation, translation) poses of one part:
+// t rounded to the nearest lattice point (ties away from zero) mod n.
+__global__ void k_make_items(QueryItem* __restrict__ items, int batch, const float4* xyzr, const float* w,
+                             long long n_pts, const float4* FA, const float* __restrict__ R,
+                             const float* __restrict__ t, float c0, float c1, float c2, int n) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  QueryItem it;
+  it.xyzr = xyzr;
+  it.w = w;
+  it.n_pts = n_pts;
+  it.Ahat = nullptr;
+  it.FA = FA;
+  for (int i = 0; i < 9; ++i) it.R[i] = R[b * 9 + i];
+  it.c[0] = c0;
+  it.c[1] = c1;
+  it.c[2] = c2;
+  for (int a = 0; a < 3; ++a) {
+    long long v = (long long)roundf(t[b * 3 + a]) % n;
+    it.t[a] = (int)(v < 0 ? v + n : v);
+  }
+  it.pad = 0;
+  items[b] = it;
+}
+
+}  // namespace
 
 }  // namespace ga

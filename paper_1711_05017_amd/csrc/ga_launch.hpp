@@ -1,0 +1,219 @@
+// ga_launch.hpp -- plan object, launch helpers and workspace layout shared by
+// the library's translation units (ga_lib.hip, ga_server.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <vector>
+
+#include "ga.h"
+#include "ga_kernels.hpp"
+
+struct ga_prof_entry {
+  int kind;
+  hipEvent_t start, stop;
+};
+
+struct ga_plan {
+  int n;
+  int max_batch;
+  uint32_t flags;
+  int device;
+  float2* d_tw;  // exp(-2 pi i k / n), k < n, float64-accurate values rounded to float32
+  // per-kernel timing (ga_profile_*); mutable because compute calls take a const plan
+  mutable bool prof = false;
+  mutable std::vector<ga_prof_entry> prof_pending;
+  mutable double prof_ms[GA_K_COUNT] = {};
+  mutable long long prof_count[GA_K_COUNT] = {};
+};
+
+namespace ga_detail {
+
+using namespace ga;
+
+inline constexpr const char* kVersion = "ga 0.1.0 (gfx950)";
+
+inline bool valid_stream_call(const ga_plan* p) { return p != nullptr && p->d_tw != nullptr; }
+
+// Brackets one kernel launch with events on its stream when profiling is on.
+struct ProfScope {
+  const ga_plan* plan;
+  hipStream_t stream;
+  ga_prof_entry e{};
+  bool on;
+  ProfScope(const ga_plan* p, int kind, hipStream_t s) : plan(p), stream(s), on(p->prof) {
+    if (!on) return;
+    e.kind = kind;
+    if (hipEventCreate(&e.start) != hipSuccess || hipEventCreate(&e.stop) != hipSuccess) {
+      on = false;
+      return;
+    }
+    (void)hipEventRecord(e.start, stream);
+  }
+  ~ProfScope() {
+    if (!on) return;
+    (void)hipEventRecord(e.stop, stream);
+    plan->prof_pending.push_back(e);
+  }
+};
+
+inline void prof_drain(const ga_plan* p) {
+  for (auto& e : p->prof_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(e.stop) == hipSuccess && hipEventElapsedTime(&ms, e.start, e.stop) == hipSuccess) {
+      p->prof_ms[e.kind] += ms;
+      p->prof_count[e.kind] += 1;
+    }
+    (void)hipEventDestroy(e.start);
+    (void)hipEventDestroy(e.stop);
+  }
+  p->prof_pending.clear();
+}
+
+inline ga_status launch_status() {
+  const hipError_t e = hipGetLastError();
+  return (e == hipSuccess) ? GA_OK : GA_EDEVICE;
+}
+
+inline size_t spectrum_elems(int n) { return (size_t)n * n * (n / 2 + 1); }
+
+// Strip width per grid edge: four transforms-per-wave groups, i.e. 4 waves.
+template <int N> constexpr int strip_g() { return 4 * ffts_per_wave<N>(); }
+constexpr int kSingleG = 64;
+
+template <int N> struct Launch {
+  using P = Plane<N>;
+  static constexpr int G = strip_g<N>();
+  using T = Strip<N, G>;
+  static int nstrips() { return (T::C + G - 1) / G; }
+  static int nsingle() { return (T::C + kSingleG - 1) / kSingleG; }
+
+  static void bin_samples(const SplatParams& sp, Placed* rec, int* off, float* rmax, int batch, hipStream_t s) {
+    hipLaunchKernelGGL(k_bin_samples<N>, dim3(batch), dim3(256), 0, s, sp, rec, off, rmax);
+  }
+  // pass 1 from real grids (nch = 1) or from binned samples (nch = 1 or 4)
+  static void plane_fwd(const SplatParams& sp, const float* grid, int nch, float2* out, int batch, const float2* tw,
+                        hipStream_t s) {
+    if (grid)
+      hipLaunchKernelGGL((k_plane_fwd<N, true, 1>), dim3(N, batch), dim3(P::THREADS), 0, s, sp, grid, out, tw);
+    else if (nch == 4)
+      hipLaunchKernelGGL((k_plane_fwd<N, false, 4>), dim3(N, batch), dim3(P::THREADS), 0, s, sp, grid, out, tw);
+    else
+      hipLaunchKernelGGL((k_plane_fwd<N, false, 1>), dim3(N, batch), dim3(P::THREADS), 0, s, sp, grid, out, tw);
+  }
+  static void plane_inv(const float2* in, float* out, float scale, int batch, const float2* tw, hipStream_t s) {
+    hipLaunchKernelGGL(k_plane_inv<N>, dim3(N, batch), dim3(P::THREADS), 0, s, in, out, scale, tw);
+  }
+  static void strip_fft(int dir, const float2* in, float2* out, int batch, const float2* tw, hipStream_t s) {
+    if (dir < 0)
+      hipLaunchKernelGGL((k_strip_fft<N, G, -1>), dim3(nstrips(), batch), dim3(T::THREADS), 0, s, in, out, tw);
+    else
+      hipLaunchKernelGGL((k_strip_fft<N, G, +1>), dim3(nstrips(), batch), dim3(T::THREADS), 0, s, in, out, tw);
+  }
+  static void strip_corr(bool fwd, const float2* A, long long a_stride, const float2* B, float2* out, int batch,
+                         const float2* tw, hipStream_t s) {
+    if (fwd)
+      hipLaunchKernelGGL((k_strip_corr<N, G, true>), dim3(nstrips(), batch), dim3(T::THREADS), 0, s, A, a_stride, B,
+                         out, tw);
+    else
+      hipLaunchKernelGGL((k_strip_corr<N, G, false>), dim3(nstrips(), batch), dim3(T::THREADS), 0, s, A, a_stride, B,
+                         out, tw);
+  }
+  static void ft_fields(const float2* A, const float2* B4, float2* out7, const float2* tw, hipStream_t s) {
+    hipLaunchKernelGGL((k_strip_ft_fields<N, G>), dim3(nstrips(), 7), dim3(T::THREADS), 0, s, A, B4, out7, tw);
+  }
+  static void single(const float2* A, const float2* B4, const float* poses, int n_poses, double* part,
+                     const float2* tw, hipStream_t s) {
+    hipLaunchKernelGGL((k_single_partials<N, kSingleG>), dim3(nsingle(), n_poses), dim3(256), 0, s, A, B4, poses,
+                       part, tw);
+  }
+};
+
+// Calls f.template operator()<N>() for a supported N; returns false otherwise.
+template <class F> bool dispatch(int n, F&& f) {
+  switch (n) {
+    case 16: f.template operator()<16>(); return true;
+    case 24: f.template operator()<24>(); return true;
+    case 32: f.template operator()<32>(); return true;
+    case 48: f.template operator()<48>(); return true;
+    case 64: f.template operator()<64>(); return true;
+    case 96: f.template operator()<96>(); return true;
+    case 128: f.template operator()<128>(); return true;
+    case 192: f.template operator()<192>(); return true;
+    default: return false;
+  }
+}
+
+inline int nstrips_of(int n) {
+  int v = 0;
+  dispatch(n, [&]<int N>() { v = Launch<N>::nstrips(); });
+  return v;
+}
+inline int nsingle_of(int n) {
+  int v = 0;
+  dispatch(n, [&]<int N>() { v = Launch<N>::nsingle(); });
+  return v;
+}
+
+// Whether the byte ranges [a, a + na) and [b, b + nb) overlap.
+inline bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  if (!a || !b || na == 0 || nb == 0) return false;
+  const char* pa = static_cast<const char*>(a);
+  const char* pb = static_cast<const char*>(b);
+  return pa < pb + nb && pb < pa + na;
+}
+
+// Workgroups of the local single-pose sums for a part of n_pts samples.
+inline int nlocal_of(int64_t n_pts) { return (int)((n_pts + kLocalSPB - 1) / kLocalSPB > 0 ? (n_pts + kLocalSPB - 1) / kLocalSPB : 1); }
+
+inline bool valid_sigma(float s) { return std::isfinite(s) && s > 0.0f; }
+
+// Workspace of the fused field path: batch spectra, then the binned samples
+// (records, bin offsets, largest radius per batch member).
+inline size_t bin_offset(int n, int batch) { return (size_t)batch * spectrum_elems(n) * sizeof(float2); }
+inline size_t bin_bytes(int n, int batch, int64_t n_pts) {
+  const size_t rec = (size_t)batch * (size_t)n_pts * sizeof(Placed);
+  const size_t off = ((size_t)batch * (n + 1) * sizeof(int) + 15) / 16 * 16;
+  return rec + off + (size_t)batch * sizeof(float);
+}
+
+inline SplatParams make_splat(const float* xyzr, const float* w, int64_t n_pts, const float* Rdev, const float* hR,
+                       const float* hc, float sigma) {
+  SplatParams p{};
+  p.rec = nullptr;
+  p.off = nullptr;
+  p.rmax = nullptr;
+  p.xyzr = reinterpret_cast<const float4*>(xyzr);
+  p.w = w;
+  p.n_pts = n_pts;
+  p.Rdev = Rdev;
+  for (int i = 0; i < 9; ++i) p.Rh[i] = hR ? hR[i] : ((i % 4 == 0) ? 1.f : 0.f);
+  for (int i = 0; i < 3; ++i) p.c[i] = hc ? hc[i] : 0.f;
+  const double sc = 1.0 / (2.0 * (double)sigma * (double)sigma);
+  const double e0 = std::exp(-sc);
+  p.sig_c = (float)sc;
+  p.e0 = (float)e0;
+  p.inv1me0 = (float)(1.0 / (1.0 - e0));
+  return p;
+}
+
+inline bool rotation_ok(const float* R) {
+  double M[9];
+  for (int i = 0; i < 9; ++i) {
+    if (!std::isfinite(R[i])) return false;
+    M[i] = R[i];
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0;
+      for (int k = 0; k < 3; ++k) s += M[i * 3 + k] * M[j * 3 + k];
+      if (std::fabs(s - (i == j ? 1.0 : 0.0)) > 1e-4) return false;
+    }
+  const double det = M[0] * (M[4] * M[8] - M[5] * M[7]) - M[1] * (M[3] * M[8] - M[5] * M[6]) +
+                     M[2] * (M[3] * M[7] - M[4] * M[6]);
+  return std::fabs(det - 1.0) < 1e-4;
+}
+
+}  // namespace ga_detail

@@ -9,203 +9,11 @@
 #include <vector>
 
 #include "ga.h"
-#include "ga_kernels.hpp"
-
-struct ga_prof_entry {
-  int kind;
-  hipEvent_t start, stop;
-};
-
-struct ga_plan {
-  int n;
-  int max_batch;
-  uint32_t flags;
-  int device;
-  float2* d_tw;  // exp(-2 pi i k / n), k < n, float64-accurate values rounded to float32
-  // per-kernel timing (ga_profile_*); mutable because compute calls take a const plan
-  mutable bool prof = false;
-  mutable std::vector<ga_prof_entry> prof_pending;
-  mutable double prof_ms[GA_K_COUNT] = {};
-  mutable long long prof_count[GA_K_COUNT] = {};
-};
-
-namespace {
+#include "ga_launch.hpp"
 
 using namespace ga;
+using namespace ga_detail;
 
-constexpr const char* kVersion = "ga 0.1.0 (gfx950)";
-
-bool valid_stream_call(const ga_plan* p) { return p != nullptr && p->d_tw != nullptr; }
-
-// Brackets one kernel launch with events on its stream when profiling is on.
-struct ProfScope {
-  const ga_plan* plan;
-  hipStream_t stream;
-  ga_prof_entry e{};
-  bool on;
-  ProfScope(const ga_plan* p, int kind, hipStream_t s) : plan(p), stream(s), on(p->prof) {
-    if (!on) return;
-    e.kind = kind;
-    if (hipEventCreate(&e.start) != hipSuccess || hipEventCreate(&e.stop) != hipSuccess) {
-      on = false;
-      return;
-    }
-    (void)hipEventRecord(e.start, stream);
-  }
-  ~ProfScope() {
-    if (!on) return;
-    (void)hipEventRecord(e.stop, stream);
-    plan->prof_pending.push_back(e);
-  }
-};
-
-void prof_drain(const ga_plan* p) {
-  for (auto& e : p->prof_pending) {
-    float ms = 0.f;
-    if (hipEventSynchronize(e.stop) == hipSuccess && hipEventElapsedTime(&ms, e.start, e.stop) == hipSuccess) {
-      p->prof_ms[e.kind] += ms;
-      p->prof_count[e.kind] += 1;
-    }
-    (void)hipEventDestroy(e.start);
-    (void)hipEventDestroy(e.stop);
-  }
-  p->prof_pending.clear();
-}
-
-ga_status launch_status() {
-  const hipError_t e = hipGetLastError();
-  return (e == hipSuccess) ? GA_OK : GA_EDEVICE;
-}
-
-size_t spectrum_elems(int n) { return (size_t)n * n * (n / 2 + 1); }
-
-// Strip width per grid edge: four transforms-per-wave groups, i.e. 4 waves.
-template <int N> constexpr int strip_g() { return 4 * ffts_per_wave<N>(); }
-constexpr int kSingleG = 64;
-
-template <int N> struct Launch {
-  using P = Plane<N>;
-  static constexpr int G = strip_g<N>();
-  using T = Strip<N, G>;
-  static int nstrips() { return (T::C + G - 1) / G; }
-  static int nsingle() { return (T::C + kSingleG - 1) / kSingleG; }
-
-  static void bin_samples(const SplatParams& sp, Placed* rec, int* off, float* rmax, int batch, hipStream_t s) {
-    hipLaunchKernelGGL(k_bin_samples<N>, dim3(batch), dim3(256), 0, s, sp, rec, off, rmax);
-  }
-  // pass 1 from real grids (nch = 1) or from binned samples (nch = 1 or 4)
-  static void plane_fwd(const SplatParams& sp, const float* grid, int nch, float2* out, int batch, const float2* tw,
-                        hipStream_t s) {
-    if (grid)
-      hipLaunchKernelGGL((k_plane_fwd<N, true, 1>), dim3(N, batch), dim3(P::THREADS), 0, s, sp, grid, out, tw);
-    else if (nch == 4)
-      hipLaunchKernelGGL((k_plane_fwd<N, false, 4>), dim3(N, batch), dim3(P::THREADS), 0, s, sp, grid, out, tw);
-    else
-      hipLaunchKernelGGL((k_plane_fwd<N, false, 1>), dim3(N, batch), dim3(P::THREADS), 0, s, sp, grid, out, tw);
-  }
-  static void plane_inv(const float2* in, float* out, float scale, int batch, const float2* tw, hipStream_t s) {
-    hipLaunchKernelGGL(k_plane_inv<N>, dim3(N, batch), dim3(P::THREADS), 0, s, in, out, scale, tw);
-  }
-  static void strip_fft(int dir, const float2* in, float2* out, int batch, const float2* tw, hipStream_t s) {
-    if (dir < 0)
-      hipLaunchKernelGGL((k_strip_fft<N, G, -1>), dim3(nstrips(), batch), dim3(T::THREADS), 0, s, in, out, tw);
-    else
-      hipLaunchKernelGGL((k_strip_fft<N, G, +1>), dim3(nstrips(), batch), dim3(T::THREADS), 0, s, in, out, tw);
-  }
-  static void strip_corr(bool fwd, const float2* A, long long a_stride, const float2* B, float2* out, int batch,
-                         const float2* tw, hipStream_t s) {
-    if (fwd)
-      hipLaunchKernelGGL((k_strip_corr<N, G, true>), dim3(nstrips(), batch), dim3(T::THREADS), 0, s, A, a_stride, B,
-                         out, tw);
-    else
-      hipLaunchKernelGGL((k_strip_corr<N, G, false>), dim3(nstrips(), batch), dim3(T::THREADS), 0, s, A, a_stride, B,
-                         out, tw);
-  }
-  static void ft_fields(const float2* A, const float2* B4, float2* out7, const float2* tw, hipStream_t s) {
-    hipLaunchKernelGGL((k_strip_ft_fields<N, G>), dim3(nstrips(), 7), dim3(T::THREADS), 0, s, A, B4, out7, tw);
-  }
-  static void single(const float2* A, const float2* B4, const float* poses, int n_poses, double* part,
-                     const float2* tw, hipStream_t s) {
-    hipLaunchKernelGGL((k_single_partials<N, kSingleG>), dim3(nsingle(), n_poses), dim3(256), 0, s, A, B4, poses,
-                       part, tw);
-  }
-};
-
-// Calls f.template operator()<N>() for a supported N; returns false otherwise.
-template <class F> bool dispatch(int n, F&& f) {
-  switch (n) {
-    case 16: f.template operator()<16>(); return true;
-    case 24: f.template operator()<24>(); return true;
-    case 32: f.template operator()<32>(); return true;
-    case 48: f.template operator()<48>(); return true;
-    case 64: f.template operator()<64>(); return true;
-    case 96: f.template operator()<96>(); return true;
-    case 128: f.template operator()<128>(); return true;
-    case 192: f.template operator()<192>(); return true;
-    default: return false;
-  }
-}
-
-int nstrips_of(int n) {
-  int v = 0;
-  dispatch(n, [&]<int N>() { v = Launch<N>::nstrips(); });
-  return v;
-}
-int nsingle_of(int n) {
-  int v = 0;
-  dispatch(n, [&]<int N>() { v = Launch<N>::nsingle(); });
-  return v;
-}
-
-bool valid_sigma(float s) { return std::isfinite(s) && s > 0.0f; }
-
-// Workspace of the fused field path: batch spectra, then the binned samples
-// (records, bin offsets, largest radius per batch member).
-size_t bin_offset(int n, int batch) { return (size_t)batch * spectrum_elems(n) * sizeof(float2); }
-size_t bin_bytes(int n, int batch, int64_t n_pts) {
-  const size_t rec = (size_t)batch * (size_t)n_pts * sizeof(Placed);
-  const size_t off = ((size_t)batch * (n + 1) * sizeof(int) + 15) / 16 * 16;
-  return rec + off + (size_t)batch * sizeof(float);
-}
-
-SplatParams make_splat(const float* xyzr, const float* w, int64_t n_pts, const float* Rdev, const float* hR,
-                       const float* hc, float sigma) {
-  SplatParams p{};
-  p.rec = nullptr;
-  p.off = nullptr;
-  p.rmax = nullptr;
-  p.xyzr = reinterpret_cast<const float4*>(xyzr);
-  p.w = w;
-  p.n_pts = n_pts;
-  p.Rdev = Rdev;
-  for (int i = 0; i < 9; ++i) p.Rh[i] = hR ? hR[i] : ((i % 4 == 0) ? 1.f : 0.f);
-  for (int i = 0; i < 3; ++i) p.c[i] = hc ? hc[i] : 0.f;
-  const double sc = 1.0 / (2.0 * (double)sigma * (double)sigma);
-  const double e0 = std::exp(-sc);
-  p.sig_c = (float)sc;
-  p.e0 = (float)e0;
-  p.inv1me0 = (float)(1.0 / (1.0 - e0));
-  return p;
-}
-
-bool rotation_ok(const float* R) {
-  double M[9];
-  for (int i = 0; i < 9; ++i) {
-    if (!std::isfinite(R[i])) return false;
-    M[i] = R[i];
-  }
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) {
-      double s = 0;
-      for (int k = 0; k < 3; ++k) s += M[i * 3 + k] * M[j * 3 + k];
-      if (std::fabs(s - (i == j ? 1.0 : 0.0)) > 1e-4) return false;
-    }
-  const double det = M[0] * (M[4] * M[8] - M[5] * M[7]) - M[1] * (M[3] * M[8] - M[5] * M[6]) +
-                     M[2] * (M[3] * M[7] - M[4] * M[6]);
-  return std::fabs(det - 1.0) < 1e-4;
-}
-
-}  // namespace
 
 extern "C" {
 
@@ -283,6 +91,9 @@ size_t ga_workspace_size(const ga_plan* plan, int32_t op, int32_t batch, int64_t
     case GA_OP_ENERGY: return bin_offset(n, batch) + bin_bytes(n, batch, n_items);
     case GA_OP_FORCE_FIELDS: return 7 * spec + 7 * real;
     case GA_OP_FORCE_SINGLE: return (size_t)n_items * nsingle_of(n) * 7 * sizeof(double);
+    case GA_OP_FIELD_GRAD: return 6 * spec + 3 * real;
+    case GA_OP_POSE_LOCAL:
+      return (size_t)batch * sizeof(QueryItem) + (size_t)batch * nlocal_of(n_items) * 7 * sizeof(double);
     default: return 0;
   }
 }
@@ -313,6 +124,11 @@ ga_status ga_fft3d(const ga_plan* plan, int32_t dir, const void* d_in, void* d_o
   if (!valid_stream_call(plan) || !d_in || !d_out || batch < 1 || batch > plan->max_batch) return GA_EINVAL;
   if (dir != GA_R2C && dir != GA_C2R) return GA_EINVAL;
   const int n = plan->n;
+  const size_t real_b = (size_t)batch * n * n * n * sizeof(float);
+  const size_t spec_b = (size_t)batch * spectrum_elems(n) * sizeof(float2);
+  if (overlaps(d_in, dir == GA_R2C ? real_b : spec_b, d_out, dir == GA_R2C ? spec_b : real_b)) return GA_EINVAL;
+  if (dir == GA_C2R && (overlaps(d_work, work_bytes, d_in, spec_b) || overlaps(d_work, work_bytes, d_out, real_b)))
+    return GA_EINVAL;
   if (dir == GA_R2C) {
     float2* out = static_cast<float2*>(d_out);
     SplatParams sp = make_splat(nullptr, nullptr, 0, nullptr, nullptr, nullptr, 0.5f);
@@ -347,6 +163,15 @@ ga_status ga_correlate(const ga_plan* plan, const float* d_Ahat, int64_t a_strid
     return GA_EINVAL;
   if (!d_work || work_bytes < ga_workspace_size(plan, GA_OP_CORRELATE, batch, 0)) return GA_ENOMEM;
   const int n = plan->n;
+  {
+    const size_t spec_b = (size_t)batch * spectrum_elems(n) * sizeof(float2);
+    const size_t a_b = (size_t)((batch - 1) * a_stride + (int64_t)spectrum_elems(n)) * sizeof(float2);
+    const size_t real_b = (size_t)batch * n * n * n * sizeof(float);
+    if (overlaps(d_E, real_b, d_Bhat, spec_b) || overlaps(d_E, real_b, d_Ahat, a_b) ||
+        overlaps(d_work, work_bytes, d_E, real_b) || overlaps(d_work, work_bytes, d_Bhat, spec_b) ||
+        overlaps(d_work, work_bytes, d_Ahat, a_b))
+      return GA_EINVAL;
+  }
   float2* tmp = static_cast<float2*>(d_work);
   const float scale = (float)(1.0 / ((double)n * n * n));
   dispatch(n, [&]<int N>() {
@@ -370,6 +195,13 @@ ga_status ga_energy_fields(const ga_plan* plan, const float* d_Ahat, const float
   if (!(std::isfinite(h_c[0]) && std::isfinite(h_c[1]) && std::isfinite(h_c[2]))) return GA_EINVAL;
   if (!d_work || work_bytes < ga_workspace_size(plan, GA_OP_ENERGY, batch, n_pts)) return GA_ENOMEM;
   const int n = plan->n;
+  {
+    const size_t real_b = (size_t)batch * n * n * n * sizeof(float);
+    const size_t spec_b = spectrum_elems(n) * sizeof(float2);
+    if (overlaps(d_work, work_bytes, d_E, real_b) || overlaps(d_work, work_bytes, d_Ahat, spec_b) ||
+        overlaps(d_E, real_b, d_Ahat, spec_b))
+      return GA_EINVAL;
+  }
   float2* tmp = static_cast<float2*>(d_work);
   const float scale = (float)(1.0 / ((double)n * n * n));
   SplatParams sp = make_splat(d_xyzr, d_w, n_pts, d_R, nullptr, h_c, sigma);
@@ -411,6 +243,12 @@ ga_status ga_force_torque(const ga_plan* plan, const float* d_Ahat, const float*
   const int n = plan->n;
   const int op = (mode == GA_FIELDS) ? GA_OP_FORCE_FIELDS : GA_OP_FORCE_SINGLE;
   if (!d_work || work_bytes < ga_workspace_size(plan, op, 1, (int64_t)n_poses)) return GA_ENOMEM;
+  {
+    const size_t spec_b = spectrum_elems(n) * sizeof(float2);
+    if (overlaps(d_work, work_bytes, d_Ahat, spec_b) || overlaps(d_work, work_bytes, d_Bhat4, 4 * spec_b) ||
+        overlaps(d_work, work_bytes, d_out7, sizeof(float) * 7 * (size_t)n_poses))
+      return GA_EINVAL;
+  }
   const float2* A = reinterpret_cast<const float2*>(d_Ahat);
   const float2* B4 = reinterpret_cast<const float2*>(d_Bhat4);
   if (mode == GA_FIELDS) {
@@ -436,6 +274,61 @@ ga_status ga_force_torque(const ga_plan* plan, const float* d_Ahat, const float*
     const double scale = 1.0 / ((double)n * n * n);
     hipLaunchKernelGGL(k_reduce_partials, dim3(n_poses), dim3(64), 0, stream, part, nsingle_of(n), d_out7, scale);
   }
+  return launch_status();
+}
+
+ga_status ga_field_grad(const ga_plan* plan, const float* d_uA, const float* d_Ahat, float* d_FA4, void* d_work,
+                        size_t work_bytes, hipStream_t stream) {
+  if (!valid_stream_call(plan) || !d_uA || !d_Ahat || !d_FA4) return GA_EINVAL;
+  if (!d_work || work_bytes < ga_workspace_size(plan, GA_OP_FIELD_GRAD, 1, 0)) return GA_ENOMEM;
+  const int n = plan->n;
+  const size_t spec = spectrum_elems(n);
+  const size_t n3 = (size_t)n * n * n;
+  if (overlaps(d_work, work_bytes, d_FA4, 16 * n3) || overlaps(d_work, work_bytes, d_uA, 4 * n3) ||
+      overlaps(d_work, work_bytes, d_Ahat, 8 * spec) || overlaps(d_FA4, 16 * n3, d_uA, 4 * n3) ||
+      overlaps(d_FA4, 16 * n3, d_Ahat, 8 * spec))
+    return GA_EINVAL;
+  float2* g3 = static_cast<float2*>(d_work);
+  float2* tmp = g3 + 3 * spec;
+  float* real3 = reinterpret_cast<float*>(tmp + 3 * spec);
+  const float scale = (float)(1.0 / ((double)n * n * n));
+  dispatch(n, [&]<int N>() {
+    ProfScope ps(plan, GA_K_READOUT, stream);
+    const int threads = 256;
+    hipLaunchKernelGGL(k_grad_spectra<N>, dim3((unsigned)((spec + threads - 1) / threads)), dim3(threads), 0, stream,
+                       reinterpret_cast<const float2*>(d_Ahat), g3);
+    Launch<N>::strip_fft(+1, g3, tmp, 3, plan->d_tw, stream);
+    Launch<N>::plane_inv(tmp, real3, scale, 3, plan->d_tw, stream);
+    hipLaunchKernelGGL(k_pack4, dim3((unsigned)((n3 + threads - 1) / threads)), dim3(threads), 0, stream, d_uA,
+                       (const float*)real3, reinterpret_cast<float4*>(d_FA4), (long long)n3);
+  });
+  return launch_status();
+}
+
+ga_status ga_pose_local(const ga_plan* plan, const float* d_FA4, const float* d_xyzr, const float* d_w, int64_t n_pts,
+                        const float* d_R, const float* h_c, float sigma, const float* d_t, int32_t n_poses,
+                        float* d_out7, void* d_work, size_t work_bytes, hipStream_t stream) {
+  if (!valid_stream_call(plan) || !d_FA4 || n_pts < 0 || (n_pts > 0 && (!d_xyzr || !d_w)) || !h_c ||
+      !valid_sigma(sigma) || n_poses < 0 || (n_poses > 0 && (!d_R || !d_t || !d_out7)))
+    return GA_EINVAL;
+  if (!(std::isfinite(h_c[0]) && std::isfinite(h_c[1]) && std::isfinite(h_c[2]))) return GA_EINVAL;
+  if (n_poses == 0) return GA_OK;
+  if (!d_work || work_bytes < ga_workspace_size(plan, GA_OP_POSE_LOCAL, n_poses, n_pts)) return GA_ENOMEM;
+  if (overlaps(d_work, work_bytes, d_out7, sizeof(float) * 7 * (size_t)n_poses)) return GA_EINVAL;
+  const int n = plan->n;
+  QueryItem* items = static_cast<QueryItem*>(d_work);
+  double* part = reinterpret_cast<double*>(items + n_poses);
+  const int nblk = nlocal_of(n_pts);
+  SplatParams sp = make_splat(nullptr, nullptr, 0, nullptr, nullptr, nullptr, sigma);
+  ProfScope ps(plan, GA_K_READOUT, stream);
+  hipLaunchKernelGGL(k_make_items, dim3((n_poses + 63) / 64), dim3(64), 0, stream, items, n_poses,
+                     reinterpret_cast<const float4*>(d_xyzr), d_w, (long long)n_pts,
+                     reinterpret_cast<const float4*>(d_FA4), d_R, d_t, h_c[0], h_c[1], h_c[2], n);
+  dispatch(n, [&]<int N>() {
+    hipLaunchKernelGGL(k_local_query<N>, dim3(nblk, n_poses), dim3(256), 0, stream, (const QueryItem*)items, part,
+                       sp.sig_c, sp.e0, sp.inv1me0);
+  });
+  hipLaunchKernelGGL(k_reduce_partials, dim3(n_poses), dim3(64), 0, stream, (const double*)part, nblk, d_out7, 1.0);
   return launch_status();
 }
 

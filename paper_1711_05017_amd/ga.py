@@ -21,17 +21,45 @@ GA_OK, GA_PENDING = 0, 1
 GA_R2C, GA_C2R = -1, 1
 GA_FIELDS, GA_SINGLE = 0, 1
 GA_OP_FFT_C2R, GA_OP_CORRELATE, GA_OP_ENERGY, GA_OP_FORCE_FIELDS, GA_OP_FORCE_SINGLE = 1, 2, 3, 4, 5
+GA_OP_FIELD_GRAD, GA_OP_POSE_LOCAL = 6, 7
+GA_SERVE_LOCAL, GA_SERVE_SPECTRAL = 0, 1
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = [
     "ga_status_str", "ga_version", "ga_supported_n", "ga_plan_create", "ga_plan_destroy", "ga_plan_n",
     "ga_workspace_size", "ga_splat", "ga_fft3d", "ga_correlate", "ga_energy_fields", "ga_force_torque",
-    "ga_profile_enable", "ga_profile_read",
+    "ga_field_grad", "ga_pose_local", "ga_profile_enable", "ga_profile_read",
+    "ga_server_create", "ga_server_destroy", "ga_pair_register", "ga_pair_release", "ga_submit", "ga_poll",
+    "ga_server_get_stats",
 ]
 GA_K_SPLAT, GA_K_PLANE_FWD, GA_K_STRIP, GA_K_PLANE_INV, GA_K_READOUT, GA_K_BIN = 0, 1, 2, 3, 4, 5
 KERNEL_KINDS = {"splat": 0, "plane_fwd": 1, "strip": 2, "plane_inv": 3, "readout": 4, "bin": 5}
 
 _vp = ctypes.c_void_p
+
+
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int32),
+                ("queue_depth", ctypes.c_int32), ("mode", ctypes.c_uint32)]
+
+
+class PartDesc(ctypes.Structure):
+    _fields_ = [("xyzr", ctypes.c_void_p), ("w", ctypes.c_void_p), ("n_pts", ctypes.c_int64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("E", ctypes.c_float), ("F", ctypes.c_float * 3), ("tau", ctypes.c_float * 3),
+                ("t_submit_ns", ctypes.c_uint64), ("t_start_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64)]
+
+    def values(self):
+        return [self.E, *self.F, *self.tau]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("launches", ctypes.c_uint64),
+                ("rejected_full", ctypes.c_uint64), ("bytes_in_use", ctypes.c_uint64), ("pairs", ctypes.c_int32)]
+
+
 _SIGS = {
     "ga_status_str": (ctypes.c_char_p, [ctypes.c_int32]),
     "ga_version": (ctypes.c_char_p, []),
@@ -47,7 +75,20 @@ _SIGS = {
                                           _vp, _vp, ctypes.c_size_t, _vp]),
     "ga_force_torque": (ctypes.c_int32, [_vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_uint32, _vp, _vp, ctypes.c_size_t,
                                          _vp]),
+    "ga_field_grad": (ctypes.c_int32, [_vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "ga_pose_local": (ctypes.c_int32, [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_float, _vp,
+                                       ctypes.c_int32, _vp, _vp, ctypes.c_size_t, _vp]),
     "ga_profile_enable": (ctypes.c_int32, [_vp, ctypes.c_int32]),
+    "ga_server_create": (ctypes.c_int32, [ctypes.POINTER(_vp), ctypes.POINTER(ServerCfg)]),
+    "ga_server_destroy": (ctypes.c_int32, [_vp]),
+    "ga_pair_register": (ctypes.c_int32, [_vp, ctypes.POINTER(PartDesc), ctypes.POINTER(PartDesc),
+                                          ctypes.POINTER(ctypes.c_float), ctypes.c_int32, ctypes.c_float,
+                                          ctypes.POINTER(ctypes.c_uint32)]),
+    "ga_pair_release": (ctypes.c_int32, [_vp, ctypes.c_uint32]),
+    "ga_submit": (ctypes.c_int32, [_vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                                   ctypes.POINTER(ctypes.c_uint64)]),
+    "ga_poll": (ctypes.c_int32, [_vp, ctypes.c_uint64, ctypes.POINTER(Result)]),
+    "ga_server_get_stats": (ctypes.c_int32, [_vp, ctypes.POINTER(ServerStats)]),
     "ga_profile_read": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int64)]),
 }
@@ -270,3 +311,138 @@ def ga_force_torque(plan: Plan, Ahat: torch.Tensor, Bhat4: torch.Tensor, t: torc
                                 _ptr(work), int(work.numel()), _stream(stream))
     _check("ga_force_torque", st)
     return out
+
+
+def ga_field_grad(plan: Plan, uA: torch.Tensor, Ahat: torch.Tensor, out: Optional[torch.Tensor] = None, work=None,
+                  stream=None) -> torch.Tensor:
+    """(u_A, grad u_A) per voxel as an [n, n, n, 4] float32 tensor."""
+    n = plan.n
+    _need(uA, torch.float32, n ** 3, "uA", exact=True)
+    _need(Ahat, torch.complex64, _spec_elems(n), "Ahat", exact=True)
+    if out is None:
+        out = torch.empty((n, n, n, 4), dtype=torch.float32, device=uA.device)
+    _need(out, torch.float32, 4 * n ** 3, "out")
+    if work is None:
+        work = plan.workspace(GA_OP_FIELD_GRAD, 1, device=uA.device)
+    st = load().ga_field_grad(plan.handle, _ptr(uA), _ptr(Ahat), _ptr(out), _ptr(work), int(work.numel()),
+                              _stream(stream))
+    _check("ga_field_grad", st)
+    return out
+
+
+def ga_pose_local(plan: Plan, FA4: torch.Tensor, xyzr: torch.Tensor, w: torch.Tensor, R: torch.Tensor, c,
+                  t: torch.Tensor, sigma: float = 0.5, out: Optional[torch.Tensor] = None, work=None,
+                  stream=None) -> torch.Tensor:
+    """(E, F, tau) at n_poses single poses by local sums over the moving part."""
+    n = plan.n
+    m = _samples(xyzr, w)
+    n_poses = int(t.shape[0])
+    _need(FA4, torch.float32, 4 * n ** 3, "FA4", exact=True)
+    _need(R, torch.float32, 9 * n_poses, "R", exact=True)
+    _need(t, torch.float32, 3 * n_poses, "t", exact=True)
+    if out is None:
+        out = torch.empty((n_poses, 7), dtype=torch.float32, device=t.device)
+    _need(out, torch.float32, 7 * n_poses, "out")
+    if work is None:
+        work = plan.workspace(GA_OP_POSE_LOCAL, n_poses, m, device=t.device)
+    st = load().ga_pose_local(plan.handle, _ptr(FA4), _ptr(xyzr), _ptr(w), m, _ptr(R), _host_f32(c, 3), float(sigma),
+                              _ptr(t), n_poses, _ptr(out), _ptr(work), int(work.numel()), _stream(stream))
+    _check("ga_pose_local", st)
+    return out
+
+
+GA_EAGAIN, GA_ENOTFOUND = -3, -5
+
+
+class Server:
+    """A ga_server: resident pair fields, queued pose queries, continuous
+    batching. Host numpy arrays in; results as ga_result. mode selects how a
+    query is evaluated (GA_SERVE_LOCAL or GA_SERVE_SPECTRAL, same values)."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 8 << 30, max_slots: int = 8, queue_depth: int = 4096,
+                 mode: int = GA_SERVE_LOCAL):
+        lib = load()
+        cfg = ServerCfg(device, hbm_budget_bytes, max_slots, queue_depth, mode)
+        h = ctypes.c_void_p()
+        _check("ga_server_create", lib.ga_server_create(ctypes.byref(h), ctypes.byref(cfg)))
+        self._h = h
+        self._keep = []
+
+    @staticmethod
+    def _part(xyzr, w):
+        import numpy as np
+
+        x = np.ascontiguousarray(xyzr, dtype=np.float32).reshape(-1, 4)
+        ww = np.ascontiguousarray(w, dtype=np.float32).reshape(-1)
+        if ww.shape[0] != x.shape[0]:
+            raise ValueError("xyzr and w lengths differ")
+        return PartDesc(x.ctypes.data, ww.ctypes.data, x.shape[0]), (x, ww)
+
+    def register_pair(self, A_xyzr, A_w, B_xyzr, B_w, cB, n: int, sigma: float = 0.5) -> int:
+        pa, ka = self._part(A_xyzr, A_w)
+        pb, kb = self._part(B_xyzr, B_w)
+        c = (ctypes.c_float * 3)(*[float(v) for v in cB])
+        pid = ctypes.c_uint32()
+        _check("ga_pair_register", load().ga_pair_register(self._h, ctypes.byref(pa), ctypes.byref(pb), c, int(n),
+                                                           float(sigma), ctypes.byref(pid)))
+        del ka, kb
+        return pid.value
+
+    def release_pair(self, pair_id: int):
+        _check("ga_pair_release", load().ga_pair_release(self._h, int(pair_id)))
+
+    def submit(self, pair_id: int, R, t):
+        """Ticket, or None when the queue is full."""
+        r = (ctypes.c_float * 9)(*[float(v) for v in list(_flat(R))])
+        tt = (ctypes.c_float * 3)(*[float(v) for v in list(_flat(t))])
+        tk = ctypes.c_uint64()
+        st = load().ga_submit(self._h, int(pair_id), r, tt, ctypes.byref(tk))
+        if st == GA_EAGAIN:
+            return None
+        _check("ga_submit", st)
+        return tk.value
+
+    def poll(self, ticket: int):
+        """Result when done, None while pending."""
+        res = Result()
+        st = load().ga_poll(self._h, int(ticket), ctypes.byref(res))
+        if st == GA_PENDING:
+            return None
+        _check("ga_poll", st)
+        return res
+
+    def wait(self, ticket: int, timeout_s: float = 30.0):
+        import time
+
+        t0 = time.perf_counter()
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            if time.perf_counter() - t0 > timeout_s:
+                raise TimeoutError(f"ticket {ticket} not done after {timeout_s} s")
+
+    def stats(self) -> ServerStats:
+        st = ServerStats()
+        _check("ga_server_get_stats", load().ga_server_get_stats(self._h, ctypes.byref(st)))
+        return st
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().ga_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _flat(a):
+    try:
+        import numpy as np
+
+        return np.asarray(a, dtype=np.float64).reshape(-1).tolist()
+    except Exception:
+        return list(a)

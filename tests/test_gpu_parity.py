@@ -227,6 +227,87 @@ def test_single_pose_rounds_to_nearest_lattice_point(G):
 
 
 # ---------------------------------------------------------------------------
+# resident field (u_A, grad u_A) and single poses by local sums
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,npts", [(16, 40), (48, 300), (96, 900)])
+def test_field_grad_matches_oracle(G, n, npts):
+    A = _part(n, 500 + n, npts, 1.0, 4.0)
+    uA = O.splat(A.xyzr[:, :3].astype(np.float64), A.xyzr[:, 3].astype(np.float64), A.w.astype(np.float64), n)
+    g = O.grad_spectral(uA)
+    plan = G.Plan(n)
+    u = G.ga_splat(plan, _dev(A.xyzr), _dev(A.w))
+    Ahat = G.ga_fft3d(plan, G.GA_R2C, u)[0]
+    FA = G.ga_field_grad(plan, u[0], Ahat).cpu().numpy().astype(np.float64)
+    assert O.rel_l2(FA[..., 0], uA) < FIELD_TOL
+    assert O.rel_l2(np.moveaxis(FA[..., 1:], -1, 0), g) < FIELD_TOL
+
+
+@pytest.mark.parametrize("n,npts,nrot", [(16, 40, 2), (24, 120, 3), (48, 400, 3), (96, 1000, 2)])
+def test_pose_local_matches_oracle(G, n, npts, nrot):
+    """Every pose has its own rotation; translations include both ends of
+    the lattice, negative and non-integer values (rounded half away from
+    zero), so that the gathers wrap on the torus."""
+    A = _part(n, 600 + n, npts, 1.0, 4.0)
+    B = _part(n, 700 + n, npts // 2 + 1, 1.0, 4.0, conf=n / 6)
+    cB = B.ref_point()
+    rots = synth.shoemake_rotations(800 + n, nrot)
+    rng = np.random.default_rng(n)
+    plan = G.Plan(n)
+    u = G.ga_splat(plan, _dev(A.xyzr), _dev(A.w))
+    FA = G.ga_field_grad(plan, u[0], G.ga_fft3d(plan, G.GA_R2C, u)[0])
+    Rs, ts, refs = [], [], []
+    for r in range(nrot):
+        d = O.pair_fields(A.xyzr, A.w, B.xyzr, B.w, rots[r], cB, n)
+        fields = np.concatenate([d["E"][None], d["F"], d["tau"]])
+        t = (n // 2 + rng.integers(-n // 4, n // 4 + 1, (12, 3))).astype(np.float32)
+        t[0] = [0, 0, 0]
+        t[1] = [n - 1, n - 1, 0]
+        t[2] = [-2, n + 3, 2 * n - 1]
+        t[3] = [n / 2 + 0.5, n / 2 - 0.5, n / 2 + 0.4]
+        lat = np.array([[np.floor(abs(v) + 0.5) * np.sign(v) for v in row] for row in t])
+        refs.append(O.lattice_read(fields, lat).T)
+        Rs.append(np.repeat(rots[r][None], len(t), 0))
+        ts.append(t)
+    got = G.ga_pose_local(plan, FA, _dev(B.xyzr), _dev(B.w), _dev(np.concatenate(Rs).astype(np.float32)), cB,
+                          _dev(np.concatenate(ts))).cpu().numpy()
+    ref = np.concatenate(refs)
+    assert np.abs(ref[:, 0]).max() > 0
+    assert O.rel_l2(got[:, 0], ref[:, 0]) < FIELD_TOL
+    assert O.rel_l2(got[:, 1:4], ref[:, 1:4]) < FORCE_TOL
+    assert O.rel_l2(got[:, 4:7], ref[:, 4:7]) < FORCE_TOL
+
+
+def test_pose_local_edge_cases(G):
+    n = 32
+    A = _part(n, 31, 80, 1.0, 3.0)
+    plan = G.Plan(n)
+    u = G.ga_splat(plan, _dev(A.xyzr), _dev(A.w))
+    FA = G.ga_field_grad(plan, u[0], G.ga_fft3d(plan, G.GA_R2C, u)[0])
+    R = _dev(np.eye(3, dtype=np.float32)[None].repeat(2, 0))
+    t = _dev(np.full((2, 3), 16.0, np.float32))
+    # no samples: zero energy, force and torque
+    empty = torch.zeros((0, 4), dtype=torch.float32, device="cuda")
+    out = G.ga_pose_local(plan, FA, empty, torch.zeros(0, dtype=torch.float32, device="cuda"), R, [0, 0, 0], t)
+    assert torch.count_nonzero(out).item() == 0
+    # zero poses is a no-op; 65 samples span two sample blocks; zero weights add nothing
+    B = _part(n, 32, 65, 1.0, 3.0, conf=5.0)
+    G.ga_pose_local(plan, FA, _dev(B.xyzr), _dev(B.w), R[:0], B.ref_point(), t[:0])
+    w0 = B.w.copy()
+    w0[64] = 0.0
+    full = G.ga_pose_local(plan, FA, _dev(B.xyzr), _dev(w0), R, B.ref_point(), t).cpu().numpy()
+    first = G.ga_pose_local(plan, FA, _dev(np.ascontiguousarray(B.xyzr[:64])), _dev(np.ascontiguousarray(B.w[:64])),
+                            R, B.ref_point(), t).cpu().numpy()
+    assert np.array_equal(full[:, 0] != 0, first[:, 0] != 0)
+    assert np.allclose(full, first, rtol=1e-6, atol=1e-12)
+    # argument errors
+    with pytest.raises(G.GaError):
+        G.ga_pose_local(plan, FA, _dev(B.xyzr), _dev(B.w), R, B.ref_point(), t, sigma=0.0)
+    with pytest.raises(G.GaError):
+        G.ga_pose_local(plan, FA, _dev(B.xyzr), _dev(B.w), R, [np.nan, 0, 0], t)
+
+
+# ---------------------------------------------------------------------------
 # full-size workloads
 # ---------------------------------------------------------------------------
 
@@ -245,6 +326,14 @@ def test_c2_peg_in_hole_1000_poses(G):
     assert O.rel_l2(got[:, 0], ref[:, 0]) < FIELD_TOL
     assert O.rel_l2(got[:, 1:4], ref[:, 1:4]) < FORCE_TOL
     assert O.rel_l2(got[:, 4:7], ref[:, 4:7]) < FORCE_TOL
+    # the same 1000 poses by local sums over the peg's balls
+    u = G.ga_splat(plan, _dev(a.A.xyzr), _dev(a.A.w), sigma=a.sigma)
+    FA = G.ga_field_grad(plan, u[0], Ahat)
+    Rk = _dev(np.repeat(a.rotations[:1], len(a.poses), 0).astype(np.float32))
+    loc = G.ga_pose_local(plan, FA, _dev(a.B.xyzr), _dev(a.B.w), Rk, a.cB, _dev(a.poses), a.sigma).cpu().numpy()
+    assert O.rel_l2(loc[:, 0], ref[:, 0]) < FIELD_TOL
+    assert O.rel_l2(loc[:, 1:4], ref[:, 1:4]) < FORCE_TOL
+    assert O.rel_l2(loc[:, 4:7], ref[:, 4:7]) < FORCE_TOL
 
 
 def test_c3_batched_rotations_full_size_sampled(G):
