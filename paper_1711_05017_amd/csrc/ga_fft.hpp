@@ -204,11 +204,12 @@ __device__ __forceinline__ void load_twiddles(Twiddles<N>& tw, const float2* __r
   load_twiddles_stage<N, 0>(tw, table, lane);
 }
 
-// One Stockham stage, in place in buf (element stride es). Stage 0 takes its
-// inputs from ld(pos) and the last stage hands its outputs to st(pos, v);
-// positions are natural indices of the transform.
-template <int N, int S, int DIR, class Ld, class St>
-__device__ __forceinline__ void fft_stage(int lane, const Twiddles<N>& tw, float2* buf, int es, Ld& ld, St& st) {
+// One Stockham stage, in place in LDS: element `pos` of the transform lives
+// at at(pos) (a float2 pointer; any layout, e.g. strided or swizzled against
+// bank conflicts). Stage 0 takes its inputs from ld(pos) and the last stage
+// hands its outputs to st(pos, v); positions are natural indices.
+template <int N, int S, int DIR, class At, class Ld, class St>
+__device__ __forceinline__ void fft_stage(int lane, const Twiddles<N>& tw, At& at, Ld& ld, St& st) {
   constexpr int E = Shape<N>::E, L = N / E, R = Shape<N>::R[S], NS = ns_before<N>(S), NB = E / R;
   constexpr bool first = (S == 0), last = (S == Shape<N>::NST - 1);
   float2 v[E];
@@ -219,7 +220,7 @@ __device__ __forceinline__ void fft_stage(int lane, const Twiddles<N>& tw, float
     for (int r = 0; r < R; ++r) {
       const int pos = j + r * (N / R);
       if constexpr (first) v[b * R + r] = ld(pos);
-      else v[b * R + r] = buf[pos * es];
+      else v[b * R + r] = *at(pos);
     }
   }
   wave_sync();
@@ -240,25 +241,36 @@ __device__ __forceinline__ void fft_stage(int lane, const Twiddles<N>& tw, float
     for (int r = 0; r < R; ++r) {
       const int pos = base + r * NS;
       if constexpr (last) st(pos, v[b * R + r]);
-      else buf[pos * es] = v[b * R + r];
+      else *at(pos) = v[b * R + r];
     }
   }
   wave_sync();
-  if constexpr (!last) fft_stage<N, S + 1, DIR>(lane, tw, buf, es, ld, st);
+  if constexpr (!last) fft_stage<N, S + 1, DIR>(lane, tw, at, ld, st);
 }
 
 // Transform of length N on the L lanes [0, L) of this transform (`lane` is
-// the index within the transform), data in buf[pos * es].
-template <int N, int DIR, class Ld, class St>
-__device__ __forceinline__ void fft_lanes(int lane, const Twiddles<N>& tw, float2* buf, int es, Ld ld, St st) {
-  fft_stage<N, 0, DIR>(lane, tw, buf, es, ld, st);
+// the index within the transform), element pos at at(pos).
+template <int N, int DIR, class At, class Ld, class St>
+__device__ __forceinline__ void fft_at(int lane, const Twiddles<N>& tw, At at, Ld ld, St st) {
+  fft_stage<N, 0, DIR>(lane, tw, at, ld, st);
+}
+template <int N, int DIR, class At>
+__device__ __forceinline__ void fft_inplace_at(int lane, const Twiddles<N>& tw, At at) {
+  auto ld = [&](int pos) { return *at(pos); };
+  auto st = [&](int pos, float2 v) { *at(pos) = v; };
+  fft_stage<N, 0, DIR>(lane, tw, at, ld, st);
 }
 
+// The same with data in buf[pos * es].
+template <int N, int DIR, class Ld, class St>
+__device__ __forceinline__ void fft_lanes(int lane, const Twiddles<N>& tw, float2* buf, int es, Ld ld, St st) {
+  auto at = [=](int pos) { return buf + pos * es; };
+  fft_stage<N, 0, DIR>(lane, tw, at, ld, st);
+}
 template <int N, int DIR>
 __device__ __forceinline__ void fft_inplace(int lane, const Twiddles<N>& tw, float2* buf, int es) {
-  auto ld = [&](int pos) { return buf[pos * es]; };
-  auto st = [&](int pos, float2 v) { buf[pos * es] = v; };
-  fft_stage<N, 0, DIR>(lane, tw, buf, es, ld, st);
+  auto at = [=](int pos) { return buf + pos * es; };
+  fft_inplace_at<N, DIR>(lane, tw, at);
 }
 
 }  // namespace ga

@@ -23,10 +23,56 @@ namespace ga {
 
 constexpr float kTwoPi = 6.28318530717958647692f;
 
-template <int N> struct Plane {
+// LDS layout of one x-plane: region t (PAIR float2) belongs to rows 2t and
+// 2t+1. Two layouts share each region:
+//  * z transforms (the two real rows packed as one complex row of N values):
+//    position p at t*PAIR + (p ^ ((p >> ZS) & ZM));
+//  * spectrum rows (after the z pass, and for the y transforms): row 2t at
+//    the region's start, row 2t+1 at offset H + D; column c < N/2 of row y at
+//    c ^ g(y), g(y) = h((y >> GS) & 7) with h linear over GF(2) given by its
+//    images H1, H2, H4 of 1, 2, 4; the Nyquist column N/2 is not permuted.
+// 8-byte LDS reads are served per half-wave on 32 bank pairs (slot mod 32),
+// writes per quarter-wave on 16 (slot mod 16); the padding and the XORs
+// spread the access shapes of the transforms (lanes along consecutive
+// positions, and along positions in steps of the first radix) over distinct
+// bank pairs. The XOR terms depend either on bits that are the same for all
+// lanes of an access or on bits that are fixed per lane, so addresses keep
+// immediate offsets. Default: the dense layout.
+template <int N> struct PlaneSwz {
+  static constexpr int PAIR = 2 * (N / 2 + 1), D = 0, ZS = 0, ZM = 0, GS = 0, H1 = 0, H2 = 0, H4 = 0;
+};
+#define GA_PLANE_SWZ(NN, PR, DD, ZS_, ZM_, GS_, A1, A2, A4)                                               \
+  template <> struct PlaneSwz<NN> {                                                                       \
+    static constexpr int PAIR = PR, D = DD, ZS = ZS_, ZM = ZM_, GS = GS_, H1 = A1, H2 = A2, H4 = A4;     \
+  };
+GA_PLANE_SWZ(128, 136, 3, 3, 7, 3, 11, 4, 8)
+#undef GA_PLANE_SWZ
+
+// INV selects the layout of the inverse pass, which measured fastest with
+// the dense layout (its LDS traffic is a smaller share of its time).
+template <int N> struct PlaneDense {
+  static constexpr int PAIR = 2 * (N / 2 + 1), D = 0, ZS = 0, ZM = 0, GS = 0, H1 = 0, H2 = 0, H4 = 0;
+};
+template <int N, bool INV = false> struct Plane {
   static constexpr int H = N / 2 + 1;    // half-spectrum length along z
-  static constexpr int PAIR = 2 * H;     // float2 per row-pair region
-  static constexpr int SIZE = N * H;     // float2 per plane
+  using Z = std::conditional_t<INV, PlaneDense<N>, PlaneSwz<N>>;
+  static constexpr int PAIR = Z::PAIR;   // float2 per row-pair region
+  static constexpr int ROW1 = H + Z::D;  // offset of the odd row in its region
+  static constexpr int CS = N / 2;       // columns [0, CS) are permuted
+  static constexpr int SIZE = (N / 2) * PAIR;  // float2 per plane in LDS
+  static_assert(ROW1 + H <= PAIR && N <= PAIR && SIZE % 2 == 0, "plane regions");
+  static_assert((Z::H1 | Z::H2 | Z::H4) < 16 && CS % 16 == 0 || (Z::H1 | Z::H2 | Z::H4) == 0, "column XOR");
+  static_assert(Z::ZM < (1 << Z::ZS) || Z::ZM == 0, "z XOR must not read the bits it changes");
+  __device__ __forceinline__ static int g(int y) {
+    const int u = (y >> Z::GS) & 7;
+    return ((u & 1) ? Z::H1 : 0) ^ ((u & 2) ? Z::H2 : 0) ^ ((u & 4) ? Z::H4 : 0);
+  }
+  // spectrum element (row y, column c in [0, H))
+  __device__ __forceinline__ static int yc(int y, int c) {
+    return (y >> 1) * PAIR + (y & 1) * ROW1 + (c < CS ? (c ^ g(y)) : CS);
+  }
+  // z-transform position p in [0, N) of region t
+  __device__ __forceinline__ static int zs(int t, int p) { return t * PAIR + (p ^ ((p >> Z::ZS) & Z::ZM)); }
   static constexpr int L = lanes_per_fft<N>();
   static constexpr int TPW = ffts_per_wave<N>();
   static constexpr int WAVES = (N >= 128) ? 8 : 4;
@@ -34,7 +80,6 @@ template <int N> struct Plane {
   // waves per SIMD the register budget must allow: two 8-wave workgroups per
   // CU at n = 128 (the plane's LDS admits two)
   static constexpr int MINW = (N == 128) ? 4 : 1;
-  static_assert(SIZE % 2 == 0, "plane copies move two complex values at a time");
 };
 
 constexpr int kChunk = 256;  // records examined per round; bounds the LDS hit list
@@ -374,28 +419,31 @@ __device__ void plane_forward_lds(float2* W, const Twiddles<N>& tw) {
   for (int it = 0; it * P::WAVES * TPW < N / 2; ++it) {
     const int t = (it * P::WAVES + wave) * TPW + lane / L;
     if (t < N / 2) {
-      float2* reg = W + t * P::PAIR;
-      fft_inplace<N, -1>(l, tw, reg, 1);
-      // A(k) = (Z(k) + conj Z(N-k))/2 goes to position k, which no other lane
-      // reads; B(k) = (Z(k) - conj Z(N-k))/(2i) waits in registers until every
-      // lane has read its Z(N-k), then goes to position H + k.
+      auto reg = [=](int pos) { return W + P::zs(t, pos); };
+      fft_inplace_at<N, -1>(l, tw, reg);
+      // A(k) = (Z(k) + conj Z(N-k))/2 and B(k) = (Z(k) - conj Z(N-k))/(2i) are
+      // the spectra of rows 2t and 2t+1; every lane reads its Z values before
+      // any lane writes the rows (same region, other layout).
       constexpr int KPL = (H + L - 1) / L;
-      float2 bk[KPL];
+      float2 ak[KPL], bk[KPL];
 #pragma unroll
       for (int e = 0; e < KPL; ++e) {
         const int k = l + L * e;
         if (k < H) {
-          const float2 a = reg[k];
-          const float2 z = reg[(N - k) % N];
+          const float2 a = *reg(k % N);
+          const float2 z = *reg((N - k) % N);
+          ak[e] = make_float2(0.5f * (a.x + z.x), 0.5f * (a.y - z.y));
           bk[e] = make_float2(0.5f * (a.y + z.y), -0.5f * (a.x - z.x));
-          reg[k] = make_float2(0.5f * (a.x + z.x), 0.5f * (a.y - z.y));
         }
       }
       wave_sync();
 #pragma unroll
       for (int e = 0; e < KPL; ++e) {
         const int k = l + L * e;
-        if (k < H) reg[H + k] = bk[e];
+        if (k < H) {
+          W[P::yc(2 * t, k)] = ak[e];
+          W[P::yc(2 * t + 1, k)] = bk[e];
+        }
       }
       wave_sync();
     }
@@ -406,28 +454,28 @@ __device__ void plane_forward_lds(float2* W, const Twiddles<N>& tw) {
   for (int it = 0; it * P::WAVES * TPW < N / 2; ++it) {
     const int t = (it * P::WAVES + wave) * TPW + lane / L;
     if (t < N / 2) {
-      float2* col = W + t;
+      auto col = [=](int pos) { return W + P::yc(pos, t); };
       auto ld = [&](int pos) -> float2 {
-        float2 v = col[pos * H];
-        if (t == 0) v.y = col[pos * H + N / 2].x;
+        float2 v = *col(pos);
+        if (t == 0) v.y = W[P::yc(pos, N / 2)].x;
         return v;
       };
-      auto st = [&](int pos, float2 v) { col[pos * H] = v; };
-      fft_lanes<N, -1>(l, tw, col, H, ld, st);
+      auto st = [&](int pos, float2 v) { *col(pos) = v; };
+      fft_at<N, -1>(l, tw, col, ld, st);
       if (t == 0) {
         // C = A + i B with A, B the spectra of the real columns kz = 0 and
         // kz = N/2: B(k) = (C(k) - conj C(N-k))/(2i) to column N/2 (not read
         // here), then A(k) = C(k) - i B(k) in place, position by position.
         for (int k = l; k < N; k += L) {
-          const float2 a = col[k * H];
-          const float2 z = col[((N - k) % N) * H];
-          col[k * H + N / 2] = make_float2(0.5f * (a.y + z.y), -0.5f * (a.x - z.x));
+          const float2 a = W[P::yc(k, 0)];
+          const float2 z = W[P::yc((N - k) % N, 0)];
+          W[P::yc(k, N / 2)] = make_float2(0.5f * (a.y + z.y), -0.5f * (a.x - z.x));
         }
         wave_sync();
         for (int k = l; k < N; k += L) {
-          const float2 c = col[k * H];
-          const float2 bb = col[k * H + N / 2];
-          col[k * H] = make_float2(c.x + bb.y, c.y - bb.x);
+          const float2 c = W[P::yc(k, 0)];
+          const float2 bb = W[P::yc(k, N / 2)];
+          W[P::yc(k, 0)] = make_float2(c.x + bb.y, c.y - bb.x);
         }
         wave_sync();
       }
@@ -459,12 +507,41 @@ __device__ __forceinline__ void batched_copy(Ld ld, St st) {
   }
 }
 
-// Two complex values at a time between global memory and LDS.
-template <int THREADS, int SIZE>
-__device__ __forceinline__ void copy_plane(float2* __restrict__ dst, const float2* __restrict__ src) {
-  const float4* s4 = reinterpret_cast<const float4*>(src);
+// The plane's spectrum between LDS (layout of Plane<N>) and global memory
+// (dense [ky][kz], row stride H), times `scale` on the way out. Two complex
+// values per global access (N*H is even); up to 16 loads per thread are in
+// flight before the first store.
+template <int N>
+__device__ __forceinline__ void plane_to_global(float2* __restrict__ dst, const float2* W, float scale) {
+  using P = Plane<N>;
+  constexpr int H = P::H;
   float4* d4 = reinterpret_cast<float4*>(dst);
-  batched_copy<SIZE / 2, THREADS, float4>([&](int i) { return s4[i]; }, [&](int i, float4 v) { d4[i] = v; });
+  batched_copy<N * H / 2, P::THREADS, float4>(
+      [&](int i) {
+        const int e = 2 * i, y0 = e / H, c0 = e - y0 * H;
+        const int y1 = (c0 + 1 == H) ? y0 + 1 : y0, c1 = (c0 + 1 == H) ? 0 : c0 + 1;
+        const float2 a = W[P::yc(y0, c0)], b = W[P::yc(y1, c1)];
+        return make_float4(a.x * scale, a.y * scale, b.x * scale, b.y * scale);
+      },
+      [&](int i, float4 v) { d4[i] = v; });
+}
+template <int N>
+__device__ __forceinline__ void plane_from_global(float2* W, const float2* __restrict__ src) {
+  using P = Plane<N, true>;
+  constexpr int H = P::H;
+  const float4* s4 = reinterpret_cast<const float4*>(src);
+  if constexpr (P::PAIR == 2 * H && P::Z::D == 0 && (P::Z::H1 | P::Z::H2 | P::Z::H4) == 0) {
+    // dense layout: element e at slot e
+    float4* W4 = reinterpret_cast<float4*>(W);
+    batched_copy<N * H / 2, P::THREADS, float4>([&](int i) { return s4[i]; }, [&](int i, float4 v) { W4[i] = v; });
+    return;
+  }
+  batched_copy<N * H / 2, P::THREADS, float4>([&](int i) { return s4[i]; }, [&](int i, float4 v) {
+    const int e = 2 * i, y0 = e / H, c0 = e - y0 * H;
+    const int y1 = (c0 + 1 == H) ? y0 + 1 : y0, c1 = (c0 + 1 == H) ? 0 : c0 + 1;
+    W[P::yc(y0, c0)] = make_float2(v.x, v.y);
+    W[P::yc(y1, c1)] = make_float2(v.z, v.w);
+  });
 }
 
 // Pass 1. grid = (N planes, batch). GRID: real grids `grid` [batch][N^3]
@@ -490,15 +567,15 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_fwd
       // two adjacent z values of one row land in one pair-region entry each
       batched_copy<N * N / 2, P::THREADS, float2>([&](int i) { return src[i]; }, [&](int i, float2 v) {
         const int y = (2 * i) / N, z = (2 * i) % N;
-        Wf[((y >> 1) * P::PAIR + z) * 2 + (y & 1)] = v.x;
-        Wf[((y >> 1) * P::PAIR + z + 1) * 2 + (y & 1)] = v.y;
+        Wf[P::zs(y >> 1, z) * 2 + (y & 1)] = v.x;
+        Wf[P::zs(y >> 1, z + 1) * 2 + (y & 1)] = v.y;
       });
     } else {
       float4* W4 = reinterpret_cast<float4*>(W);
       for (int i = tid; i < P::SIZE / 2; i += P::THREADS) W4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
       __syncthreads();
       splat_plane<N, P::WAVES, P::THREADS>(p, nullptr, b, x, chan, Wf, hl, [](int yy, int zz) {
-        return ((yy >> 1) * P::PAIR + zz) * 2 + (yy & 1);
+        return P::zs(yy >> 1, zz) * 2 + (yy & 1);
       });
     }
     __syncthreads();
@@ -507,13 +584,9 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_fwd
       load_twiddles<N>(tw, table, (tid & 63) % P::L);
       plane_forward_lds<N>(W, tw);
     }
-    copy_plane<P::THREADS, P::SIZE>(out + (((size_t)b * NCH + chan) * N + x) * plane_sz, W);
+    plane_to_global<N>(out + (((size_t)b * NCH + chan) * N + x) * plane_sz, W, 1.0f);
     if constexpr (NCH == 4) {
-      if (chan == 0) {
-        const float sx = yhat(x, N);
-        float2* dx = out + (((size_t)b * NCH + 1) * N + x) * plane_sz;
-        for (int i = tid; i < P::SIZE; i += P::THREADS) dx[i] = cscale(W[i], sx);
-      }
+      if (chan == 0) plane_to_global<N>(out + (((size_t)b * NCH + 1) * N + x) * plane_sz, W, yhat(x, N));
     }
     __syncthreads();
   };
@@ -559,12 +632,12 @@ __global__ void __launch_bounds__(Plane<N>::THREADS) k_splat_real(SplatParams p,
 template <int N>
 __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_inv(const float2* __restrict__ in, float* __restrict__ out,
                                                                  float scale, const float2* __restrict__ table) {
-  using P = Plane<N>;
+  using P = Plane<N, true>;
   constexpr int L = P::L, TPW = P::TPW, H = P::H;
   __shared__ __attribute__((aligned(16))) float2 W[P::SIZE];
   const int x = blockIdx.x, b = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l = lane % L;
-  copy_plane<P::THREADS, P::SIZE>(W, in + ((size_t)b * N + x) * (size_t)P::SIZE);
+  plane_from_global<N>(W, in + ((size_t)b * N + x) * (size_t)N * H);
   Twiddles<N> tw;
   load_twiddles<N>(tw, table, l);
   __syncthreads();
@@ -575,25 +648,25 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_inv
   for (int it = 0; it * P::WAVES * TPW < N / 2; ++it) {
     const int t = (it * P::WAVES + wave) * TPW + lane / L;
     if (t < N / 2) {
-      float2* col = W + t;
+      auto col = [=](int pos) { return W + P::yc(pos, t); };
       auto ld = [&](int pos) -> float2 {
-        if (t != 0) return col[pos * H];
+        if (t != 0) return *col(pos);
         const int m = (N - pos) % N;
-        const float2 a0 = col[pos * H], a1 = col[m * H];
-        const float2 b0 = col[pos * H + N / 2], b1 = col[m * H + N / 2];
+        const float2 a0 = W[P::yc(pos, 0)], a1 = W[P::yc(m, 0)];
+        const float2 b0 = W[P::yc(pos, N / 2)], b1 = W[P::yc(m, N / 2)];
         const float2 ha = make_float2(0.5f * (a0.x + a1.x), 0.5f * (a0.y - a1.y));
         const float2 hb = make_float2(0.5f * (b0.x + b1.x), 0.5f * (b0.y - b1.y));
         return make_float2(ha.x - hb.y, ha.y + hb.x);
       };
       auto st = [&](int pos, float2 v) {
         if (t != 0) {
-          col[pos * H] = v;
+          *col(pos) = v;
         } else {
-          col[pos * H] = make_float2(v.x, 0.f);
-          col[pos * H + N / 2] = make_float2(v.y, 0.f);
+          W[P::yc(pos, 0)] = make_float2(v.x, 0.f);
+          W[P::yc(pos, N / 2)] = make_float2(v.y, 0.f);
         }
       };
-      fft_lanes<N, +1>(l, tw, col, H, ld, st);
+      fft_at<N, +1>(l, tw, col, ld, st);
     }
   }
   __syncthreads();
@@ -601,19 +674,21 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_inv
   for (int it = 0; it * P::WAVES * TPW < N / 2; ++it) {
     const int t = (it * P::WAVES + wave) * TPW + lane / L;
     if (t < N / 2) {
-      float2* reg = W + t * P::PAIR;
+      auto reg = [=](int pos) { return W + P::zs(t, pos); };
       // Z(k) = A(k) + i B(k), completed by Hermitian symmetry; A, B are the
-      // spectra of rows 2t and 2t+1 (imaginary parts dropped at k = 0, N/2)
+      // spectra of rows 2t and 2t+1 (imaginary parts dropped at k = 0, N/2).
+      // The first stage reads every row value before any lane writes the
+      // region in the transform's own layout.
       auto ld = [&](int k) -> float2 {
         if (k < H) {
-          float2 a = reg[k], bb = reg[H + k];
+          float2 a = W[P::yc(2 * t, k)], bb = W[P::yc(2 * t + 1, k)];
           if (k == 0 || k == N / 2) {
             a.y = 0.f;
             bb.y = 0.f;
           }
           return make_float2(a.x - bb.y, a.y + bb.x);
         }
-        const float2 a = reg[N - k], bb = reg[H + N - k];
+        const float2 a = W[P::yc(2 * t, N - k)], bb = W[P::yc(2 * t + 1, N - k)];
         return make_float2(a.x + bb.y, bb.x - a.y);
       };
       float* r0 = dst + (size_t)(2 * t) * N;
@@ -621,10 +696,36 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_inv
         r0[k] = v.x * scale;
         r0[N + k] = v.y * scale;
       };
-      fft_lanes<N, +1>(l, tw, reg, 1, ld, st);
+      fft_at<N, +1>(l, tw, reg, ld, st);
     }
   }
 }
+
+// LDS layout of a strip (N x-values by G columns): element (x, g) at
+// x*LD + (g ^ (((x >> SH) & MASK) * MUL)). 8-byte LDS reads are served per
+// half-wave on 32 bank pairs (slot mod 32), writes per quarter-wave on 16
+// (slot mod 16); the row padding and the x-dependent XOR of the column
+// spread both access shapes of the Stockham stages (lanes walking
+// consecutive x, and lanes walking x in steps of the first radix) over
+// distinct bank pairs. The XOR reads only x bits that are either the same
+// for all lanes of an access or fixed per lane, and stays inside aligned
+// blocks of G columns, so each row keeps its G slots.
+template <int N> struct StripSwz {  // pad, shift, multiplier, mask
+  static constexpr int PAD = 1, SH = 0, MUL = 0, MASK = 0;
+};
+#define GA_STRIP_SWZ(NN, P, S, M, K)                                  \
+  template <> struct StripSwz<NN> {                                   \
+    static constexpr int PAD = P, SH = S, MUL = M, MASK = K;          \
+  };
+GA_STRIP_SWZ(16, 4, 2, 4, 3)
+GA_STRIP_SWZ(24, 8, 0, 0, 0)
+GA_STRIP_SWZ(32, 4, 2, 2, 7)
+GA_STRIP_SWZ(48, 4, 0, 0, 0)
+GA_STRIP_SWZ(64, 2, 3, 2, 7)
+GA_STRIP_SWZ(96, 4, 0, 0, 0)
+GA_STRIP_SWZ(128, 2, 3, 2, 7)
+GA_STRIP_SWZ(192, 2, 0, 0, 0)
+#undef GA_STRIP_SWZ
 
 template <int N, int G> struct Strip {
   static constexpr int H = N / 2 + 1;
@@ -633,8 +734,12 @@ template <int N, int G> struct Strip {
   static constexpr int TPW = ffts_per_wave<N>();
   static constexpr int WAVES = G / TPW;
   static constexpr int THREADS = 64 * WAVES;
-  static constexpr int LD = G + 1;  // padded LDS row
+  using Z = StripSwz<N>;
+  static constexpr int LD = G + Z::PAD;  // padded LDS row
+  static constexpr int SIZE = N * LD;
   static_assert(G % TPW == 0, "strip width must be a whole number of transforms per wave");
+  static_assert(Z::MUL * Z::MASK < G && (G & (G - 1)) == 0, "column XOR must stay inside the strip");
+  __device__ __forceinline__ static int idx(int x, int g) { return x * LD + (g ^ (((x >> Z::SH) & Z::MASK) * Z::MUL)); }
 };
 
 template <int N, int G>
@@ -645,14 +750,14 @@ __device__ __forceinline__ void strip_load(float2* S, const float2* src, int c0)
         const int x = i / G, c = c0 + i % G;
         return (c < T::C) ? src[(size_t)x * T::C + c] : make_float2(0.f, 0.f);
       },
-      [&](int i, float2 v) { S[(i / G) * T::LD + i % G] = v; });
+      [&](int i, float2 v) { S[T::idx(i / G, i % G)] = v; });
 }
 template <int N, int G>
 __device__ __forceinline__ void strip_store(const float2* S, float2* dst, int c0) {
   using T = Strip<N, G>;
   for (int i = threadIdx.x; i < N * G; i += T::THREADS) {
     const int x = i / G, g = i % G, c = c0 + g;
-    if (c < T::C) dst[(size_t)x * T::C + c] = S[x * T::LD + g];
+    if (c < T::C) dst[(size_t)x * T::C + c] = S[T::idx(x, g)];
   }
 }
 template <int N, int G, int DIR>
@@ -660,7 +765,7 @@ __device__ __forceinline__ void strip_fft(float2* S, const Twiddles<N>& tw) {
   using T = Strip<N, G>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = wave * T::TPW + lane / T::L;
-  fft_inplace<N, DIR>(lane % T::L, tw, S + g, T::LD);
+  fft_inplace_at<N, DIR>(lane % T::L, tw, [=](int x) { return S + T::idx(x, g); });
 }
 
 // x FFT of a strip of columns, in place or out of place.
@@ -671,7 +776,7 @@ template <int N, int G, int DIR>
 __global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_fft(const float2* in, float2* out,
                                                                     const float2* __restrict__ table) {
   using T = Strip<N, G>;
-  __shared__ float2 S[N * T::LD];
+  __shared__ float2 S[T::SIZE];
   Twiddles<N> tw;
   load_twiddles<N>(tw, table, (threadIdx.x & 63) % T::L);
   const size_t off = (size_t)blockIdx.y * N * T::C;
@@ -686,45 +791,73 @@ __global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_fft(const floa
 // Conjugate product with the stationary spectrum and inverse x FFT.
 // FWD = true: `B` holds pass-1 output (x not yet transformed): forward x FFT
 // first (the fused field path). FWD = false: `B` is a full spectrum.
-// B and out may be the same buffer (the fused path works in place), so
-// neither is declared __restrict__.
-template <int N, int G, bool FWD>
+// grid = (nstrips, ceil(batch / K)): a workgroup takes one strip of K batch
+// members in turn. With a shared stationary spectrum (a_stride = 0, FWD) each
+// thread keeps its elements of A in registers, so A is read once per K
+// members. B and out may be the same buffer (the fused path works in place),
+// so neither is declared __restrict__.
+template <int N, int G, bool FWD, int K = 1>
 __global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_corr(const float2* __restrict__ A, long long a_stride,
-                                                                     const float2* B, float2* out,
+                                                                     const float2* B, float2* out, int batch,
                                                                      const float2* __restrict__ table) {
   using T = Strip<N, G>;
-  __shared__ float2 S[N * T::LD];
+  constexpr int IT = (N * G + T::THREADS - 1) / T::THREADS;  // strip elements per thread
+  __shared__ float2 S[T::SIZE];
   Twiddles<N> tw;
   load_twiddles<N>(tw, table, (threadIdx.x & 63) % T::L);
-  const size_t boff = (size_t)blockIdx.y * N * T::C;
-  const float2* Ab = A + (size_t)blockIdx.y * (size_t)a_stride;
   const int c0 = blockIdx.x * G;
-  if constexpr (FWD) {
-    strip_load<N, G>(S, B + boff, c0);
-    __syncthreads();
-    strip_fft<N, G, -1>(S, tw);
-    __syncthreads();
-    batched_copy<N * G, T::THREADS, float2>(
-        [&](int i) {
-          const int x = i / G, c = c0 + i % G;
-          return (c < T::C) ? Ab[(size_t)x * T::C + c] : make_float2(0.f, 0.f);
-        },
-        [&](int i, float2 a) {
-          float2* e = &S[(i / G) * T::LD + i % G];
+  auto a_at = [&](const float2* Ab, int i) {
+    const int x = i / G, c = c0 + i % G;
+    return (c < T::C) ? Ab[(size_t)x * T::C + c] : make_float2(0.f, 0.f);
+  };
+  float2 areg[(FWD && K > 1) ? IT : 1];
+  if constexpr (FWD && K > 1) {
+#pragma unroll
+    for (int u = 0; u < IT; ++u) {
+      const int i = threadIdx.x + u * T::THREADS;
+      areg[u] = (i < N * G) ? a_at(A, i) : make_float2(0.f, 0.f);
+    }
+  }
+#pragma unroll 1
+  for (int kk = 0; kk < K; ++kk) {
+    const int b = blockIdx.y * K + kk;
+    if (b >= batch) break;  // uniform over the workgroup
+    const size_t boff = (size_t)b * N * T::C;
+    const float2* Ab = A + (size_t)b * (size_t)a_stride;
+    if constexpr (FWD) {
+      strip_load<N, G>(S, B + boff, c0);
+      __syncthreads();
+      strip_fft<N, G, -1>(S, tw);
+      __syncthreads();
+      if constexpr (K > 1) {
+#pragma unroll
+        for (int u = 0; u < IT; ++u) {
+          const int i = threadIdx.x + u * T::THREADS;
+          if (i < N * G) {
+            float2* e = &S[T::idx(i / G, i % G)];
+            *e = cmulc(areg[u], *e);
+          }
+        }
+      } else {
+        batched_copy<N * G, T::THREADS, float2>([&](int i) { return a_at(Ab, i); }, [&](int i, float2 a) {
+          float2* e = &S[T::idx(i / G, i % G)];
           *e = cmulc(a, *e);
         });
-  } else {
-    batched_copy<N * G, T::THREADS, float2>(
-        [&](int i) {
-          const int x = i / G, c = c0 + i % G;
-          return (c < T::C) ? cmulc(Ab[(size_t)x * T::C + c], B[boff + (size_t)x * T::C + c]) : make_float2(0.f, 0.f);
-        },
-        [&](int i, float2 v) { S[(i / G) * T::LD + i % G] = v; });
+      }
+    } else {
+      batched_copy<N * G, T::THREADS, float2>(
+          [&](int i) {
+            const int x = i / G, c = c0 + i % G;
+            return (c < T::C) ? cmulc(Ab[(size_t)x * T::C + c], B[boff + (size_t)x * T::C + c]) : make_float2(0.f, 0.f);
+          },
+          [&](int i, float2 v) { S[T::idx(i / G, i % G)] = v; });
+    }
+    __syncthreads();
+    strip_fft<N, G, +1>(S, tw);
+    __syncthreads();
+    strip_store<N, G>(S, out + boff, c0);
+    __syncthreads();
   }
-  __syncthreads();
-  strip_fft<N, G, +1>(S, tw);
-  __syncthreads();
-  strip_store<N, G>(S, out + boff, c0);
 }
 
 // kappa(k)/N for a half-spectrum index: k for k < N/2, k - N above, 0 at N/2.
@@ -762,7 +895,7 @@ __global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_ft_fields(cons
                                                                           float2* __restrict__ out7,
                                                                           const float2* __restrict__ table) {
   using T = Strip<N, G>;
-  __shared__ float2 S[N * T::LD];
+  __shared__ float2 S[T::SIZE];
   Twiddles<N> tw;
   load_twiddles<N>(tw, table, (threadIdx.x & 63) % T::L);
   const size_t spec = (size_t)N * T::C;
@@ -779,7 +912,7 @@ __global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_ft_fields(cons
 #pragma unroll
       for (int q = 0; q < 7; ++q) v = (q == o) ? pr[q] : v;  // keeps pr in registers
     }
-    S[x * T::LD + g] = v;
+    S[T::idx(x, g)] = v;
   }
   __syncthreads();
   strip_fft<N, G, +1>(S, tw);
@@ -857,8 +990,8 @@ __global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_single(const f
                                                                          double* __restrict__ part,
                                                                          const float2* __restrict__ table) {
   using T = Strip<N, G>;
-  __shared__ float2 S[N * T::LD];
-  __shared__ float2 As[N * T::LD];
+  __shared__ float2 S[T::SIZE];
+  __shared__ float2 As[T::SIZE];
   __shared__ float2 tab[N];
   __shared__ double red[T::WAVES][7];
   const int tid = threadIdx.x, b = blockIdx.y;
@@ -883,7 +1016,7 @@ __global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_single(const f
         const int ky = c / T::H, kz = c % T::H;
         const int m = (int)(((long long)x * t0 + (long long)ky * t1 + (long long)kz * t2) % N);
         const float2 e = make_float2(tab[m].x, -tab[m].y);  // exp(+2 pi i m / N)
-        const float2 z = cmul(cmulc(As[x * T::LD + g], S[x * T::LD + g]), e);
+        const float2 z = cmul(cmulc(As[T::idx(x, g)], S[T::idx(x, g)]), e);
         const double wgt = (kz == 0 || kz == N / 2) ? 1.0 : 2.0;
         const float wx = omega_of<N>(x), wy = omega_of<N>(ky), wz = omega_of<N>(kz);
         if (ch == 0) {

@@ -112,14 +112,22 @@ template <int N> struct Launch {
     else
       hipLaunchKernelGGL((k_strip_fft<N, G, +1>), dim3(nstrips(), batch), dim3(T::THREADS), 0, s, in, out, tw);
   }
+  // batch members per workgroup of the fused correlation when the stationary
+  // spectrum is shared by the batch
+  static constexpr int kCorrK = 4;
   static void strip_corr(bool fwd, const float2* A, long long a_stride, const float2* B, float2* out, int batch,
                          const float2* tw, hipStream_t s) {
-    if (fwd)
-      hipLaunchKernelGGL((k_strip_corr<N, G, true>), dim3(nstrips(), batch), dim3(T::THREADS), 0, s, A, a_stride, B,
-                         out, tw);
-    else
-      hipLaunchKernelGGL((k_strip_corr<N, G, false>), dim3(nstrips(), batch), dim3(T::THREADS), 0, s, A, a_stride, B,
-                         out, tw);
+    if (fwd && a_stride == 0 && batch > 1) {
+      const int gy = (batch + kCorrK - 1) / kCorrK;
+      hipLaunchKernelGGL((k_strip_corr<N, G, true, kCorrK>), dim3(nstrips(), gy), dim3(T::THREADS), 0, s, A, a_stride,
+                         B, out, batch, tw);
+    } else if (fwd) {
+      hipLaunchKernelGGL((k_strip_corr<N, G, true, 1>), dim3(nstrips(), batch), dim3(T::THREADS), 0, s, A, a_stride, B,
+                         out, batch, tw);
+    } else {
+      hipLaunchKernelGGL((k_strip_corr<N, G, false, 1>), dim3(nstrips(), batch), dim3(T::THREADS), 0, s, A, a_stride,
+                         B, out, batch, tw);
+    }
   }
   static void ft_fields(const float2* A, const float2* B4, float2* out7, const float2* tw, hipStream_t s) {
     hipLaunchKernelGGL((k_strip_ft_fields<N, G>), dim3(nstrips(), 7), dim3(T::THREADS), 0, s, A, B4, out7, tw);
