@@ -159,6 +159,49 @@ def serving_leg(n_queries, rate_hz, max_slots=8, mode="local"):
         srv.close()
 
 
+def graph_leg(G, synth, np, torch, dev, reps=20):
+    """The same 128^3 x 64 workload as one graph launch (ga_batch_*), and a
+    batch of four pairs on grid edges 64, 96, 128 and 192 (16 rotations each)
+    as one graph launch. fields/s over `reps` replays after warm-up."""
+    def item(n, seeds, nrot, npts):
+        A = synth.random_part(seeds, n, npts, 1.0, 4.0, conf_radius=n / 4)
+        B = synth.random_part(seeds + 1, n, npts, 1.0, 4.0, conf_radius=n / 4)
+        plan = G.Plan(n, max_batch=nrot)
+        Ahat = G.ga_fft3d(plan, G.GA_R2C, G.ga_splat(plan, torch.from_numpy(A.xyzr).to(dev),
+                                                     torch.from_numpy(A.w).to(dev)))[0].contiguous()
+        R = torch.from_numpy(np.ascontiguousarray(synth.shoemake_rotations(seeds + 2, nrot).reshape(nrot, 9))).to(dev)
+        return {"plan": plan, "Ahat": Ahat, "xyzr": torch.from_numpy(B.xyzr).to(dev),
+                "w": torch.from_numpy(B.w).to(dev), "R": R, "c": B.ref_point(), "sigma": 0.5}
+
+    def run(items):
+        b = G.Batch(items)
+        try:
+            for _ in range(3):
+                b.launch()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                b.launch()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        finally:
+            b.close()
+        nf = sum(int(it["R"].shape[0]) for it in items)
+        return {"fields_per_s": round(nf * reps / dt, 1), "ms_per_launch": round(dt * 1000 / reps, 4), "fields": nf}
+
+    a = synth.config_c3(64)
+    plan = G.Plan(a.n, max_batch=64)
+    Ahat = G.ga_fft3d(plan, G.GA_R2C, G.ga_splat(plan, torch.from_numpy(a.A.xyzr).to(dev),
+                                                 torch.from_numpy(a.A.w).to(dev), sigma=a.sigma))[0].contiguous()
+    c3 = {"plan": plan, "Ahat": Ahat, "xyzr": torch.from_numpy(a.B.xyzr).to(dev), "w": torch.from_numpy(a.B.w).to(dev),
+          "R": torch.from_numpy(np.ascontiguousarray(a.rotations.reshape(64, 9))).to(dev), "c": a.cB,
+          "sigma": a.sigma}
+    out = {"c3_one_graph": run([c3])}
+    mixed = [item(64, 710, 16, 1000), item(96, 720, 16, 1500), item(128, 730, 16, 2000), item(192, 740, 16, 3000)]
+    out["mixed_64_96_128_192"] = run(mixed)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,6 +210,7 @@ def main():
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--serving-queries", type=int, default=100000)
     ap.add_argument("--serving-rate", type=float, default=16000.0)
     ap.add_argument("--serving-mode", choices=["local", "spectral"], default="local",
@@ -255,6 +299,8 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": counter_traffic(dom),
                      "algorithmic_bytes_per_launch": abytes[dom]},
     }
+    if not args.no_graph:
+        out["graph"] = graph_leg(G, synth, np, torch, dev)
     if not args.no_serving:
         out["serving"] = serving_leg(args.serving_queries, args.serving_rate, mode=args.serving_mode)
     if not args.no_cpu_baseline:

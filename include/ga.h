@@ -212,6 +212,46 @@ ga_status ga_pose_local(const ga_plan* plan, const float* d_FA4, const float* d_
                         float* d_out7, void* d_work, size_t work_bytes, hipStream_t stream);
 
 /*
+ * Batched execution as one graph launch (Sec. 3.2: the energy field of many
+ * relative rotations per frame). A batch is a list of items, each one
+ * stationary spectrum against `batch` rotations of one moving part on the
+ * item's own grid edge, i.e. one ga_energy_fields call; items may use
+ * different plans (grid edges). ga_batch_create records all items into one
+ * HIP graph, each item on its own parallel branch, and instantiates it;
+ * ga_batch_launch replays it on `stream` with a single graph launch.
+ *
+ * Every pointer of an item is captured by the graph: a replay reads the
+ * current contents of d_Ahat, d_xyzr, d_w and d_R and overwrites d_E and
+ * d_work, so callers update inputs in place between launches. Items must not
+ * share d_E or d_work, and each d_work holds GA_OP_ENERGY bytes for the
+ * item's batch and n_pts. The plans and all buffers must outlive the batch.
+ * Errors: GA_EINVAL (an item fails the ga_energy_fields checks, overlapping
+ * outputs or workspaces between items, n_items < 1), GA_ENOMEM (workspace too
+ * small), GA_EDEVICE (graph capture or instantiation failed). Replays run
+ * without per-kernel timing.
+ */
+typedef struct ga_batch ga_batch;
+
+typedef struct {
+  const ga_plan* plan;
+  const float* d_Ahat;  /* stationary half spectrum (complex64 as float pairs) */
+  const float* d_xyzr;  /* moving part: n_pts x (x, y, z, r) */
+  const float* d_w;     /* n_pts weights */
+  int64_t n_pts;
+  const float* d_R;     /* batch x 9 rotations, row-major */
+  float c[3];           /* rotation centre of the moving part */
+  float sigma;
+  int32_t batch;
+  float* d_E;           /* batch x n^3 energy fields */
+  void* d_work;
+  size_t work_bytes;
+} ga_batch_item;
+
+ga_status ga_batch_create(ga_batch** out, const ga_batch_item* items, int32_t n_items);
+ga_status ga_batch_launch(const ga_batch* b, hipStream_t stream);
+ga_status ga_batch_destroy(ga_batch* b);
+
+/*
  * Per-kernel timing. With profiling enabled, every kernel the plan launches
  * is bracketed by two HIP events recorded on its launch stream.
  * ga_profile_read waits for the recorded events and returns, for one kernel

@@ -12,6 +12,7 @@ from .ga import (  # noqa: F401
     GA_SERVE_LOCAL,
     GA_SERVE_SPECTRAL,
     GA_SINGLE,
+    Batch,
     GaError,
     Plan,
     Server,

@@ -6,7 +6,7 @@ import subprocess
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libga.so")
-SRCS = [os.path.join(PKG, "csrc", f) for f in ("ga_lib.hip", "ga_server.hip")]
+SRCS = [os.path.join(PKG, "csrc", f) for f in ("ga_lib.hip", "ga_server.hip", "ga_batch.hip")]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -28,7 +28,7 @@ def sources():
 
 
 def build_lib(verbose: bool = False) -> str:
-    """Compile csrc/ga_lib.hip and csrc/ga_server.hip into
+    """Compile csrc/ga_lib.hip, csrc/ga_server.hip and csrc/ga_batch.hip into
     paper_1711_05017_amd/libga.so (always recompiles). Returns the library
     path."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -45,6 +45,11 @@ struct ProfScope {
   bool on;
   ProfScope(const ga_plan* p, int kind, hipStream_t s) : plan(p), stream(s), on(p->prof) {
     if (!on) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+      on = false;  // no timing events inside a captured graph
+      return;
+    }
     e.kind = kind;
     if (hipEventCreate(&e.start) != hipSuccess || hipEventCreate(&e.stop) != hipSuccess) {
       on = false;

@@ -30,7 +30,7 @@ EXPORTS = [
     "ga_workspace_size", "ga_splat", "ga_fft3d", "ga_correlate", "ga_energy_fields", "ga_force_torque",
     "ga_field_grad", "ga_pose_local", "ga_profile_enable", "ga_profile_read",
     "ga_server_create", "ga_server_destroy", "ga_pair_register", "ga_pair_release", "ga_submit", "ga_poll",
-    "ga_server_get_stats",
+    "ga_server_get_stats", "ga_batch_create", "ga_batch_launch", "ga_batch_destroy",
 ]
 GA_K_SPLAT, GA_K_PLANE_FWD, GA_K_STRIP, GA_K_PLANE_INV, GA_K_READOUT, GA_K_BIN = 0, 1, 2, 3, 4, 5
 KERNEL_KINDS = {"splat": 0, "plane_fwd": 1, "strip": 2, "plane_inv": 3, "readout": 4, "bin": 5}
@@ -53,6 +53,13 @@ class Result(ctypes.Structure):
 
     def values(self):
         return [self.E, *self.F, *self.tau]
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("d_Ahat", ctypes.c_void_p), ("d_xyzr", ctypes.c_void_p),
+                ("d_w", ctypes.c_void_p), ("n_pts", ctypes.c_int64), ("d_R", ctypes.c_void_p),
+                ("c", ctypes.c_float * 3), ("sigma", ctypes.c_float), ("batch", ctypes.c_int32),
+                ("d_E", ctypes.c_void_p), ("d_work", ctypes.c_void_p), ("work_bytes", ctypes.c_size_t)]
 
 
 class ServerStats(ctypes.Structure):
@@ -89,6 +96,9 @@ _SIGS = {
                                    ctypes.POINTER(ctypes.c_uint64)]),
     "ga_poll": (ctypes.c_int32, [_vp, ctypes.c_uint64, ctypes.POINTER(Result)]),
     "ga_server_get_stats": (ctypes.c_int32, [_vp, ctypes.POINTER(ServerStats)]),
+    "ga_batch_create": (ctypes.c_int32, [ctypes.POINTER(_vp), ctypes.POINTER(BatchItem), ctypes.c_int32]),
+    "ga_batch_launch": (ctypes.c_int32, [_vp, _vp]),
+    "ga_batch_destroy": (ctypes.c_int32, [_vp]),
     "ga_profile_read": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int64)]),
 }
@@ -349,6 +359,54 @@ def ga_pose_local(plan: Plan, FA4: torch.Tensor, xyzr: torch.Tensor, w: torch.Te
                               _ptr(t), n_poses, _ptr(out), _ptr(work), int(work.numel()), _stream(stream))
     _check("ga_pose_local", st)
     return out
+
+
+class Batch:
+    """Energy-field calls of several (plan, pair, rotations) items recorded
+    into one HIP graph (ga_batch_*). Each item is a dict with keys plan,
+    Ahat, xyzr, w, R, c, sigma; outputs and workspaces are allocated here and
+    kept with the batch. launch() replays the graph; inputs are read from the
+    same tensors at every replay, so update them in place."""
+
+    def __init__(self, items):
+        lib = load()
+        self._keep = []
+        arr = (BatchItem * len(items))()
+        self.outputs = []
+        for i, it in enumerate(items):
+            plan = it["plan"]
+            n = plan.n
+            xyzr, w, R, Ahat = it["xyzr"], it["w"], it["R"], it["Ahat"]
+            m = _samples(xyzr, w)
+            batch = int(R.shape[0])
+            _need(R, torch.float32, 9 * batch, "R", exact=True)
+            _need(Ahat, torch.complex64, _spec_elems(n), "Ahat")
+            E = torch.empty((batch, n, n, n), dtype=torch.float32, device=xyzr.device)
+            work = plan.workspace(GA_OP_ENERGY, batch, m, device=xyzr.device)
+            self._keep += [plan, xyzr, w, R, Ahat, E, work]
+            self.outputs.append(E)
+            c = [float(v) for v in torch.as_tensor(it["c"], dtype=torch.float64).reshape(-1).tolist()]
+            arr[i] = BatchItem(plan.handle.value, Ahat.data_ptr(), xyzr.data_ptr(), w.data_ptr(), m, R.data_ptr(),
+                               (ctypes.c_float * 3)(*c), float(it.get("sigma", 0.5)), batch, E.data_ptr(),
+                               work.data_ptr(), int(work.numel()))
+        h = ctypes.c_void_p()
+        _check("ga_batch_create", lib.ga_batch_create(ctypes.byref(h), arr, len(items)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check("ga_batch_launch", load().ga_batch_launch(self._h, _stream(stream)))
+        return self.outputs
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().ga_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 GA_EAGAIN, GA_ENOTFOUND = -3, -5
