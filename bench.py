@@ -253,6 +253,8 @@ def main():
     E = torch.empty((batch, n, n, n), dtype=torch.float32, device=dev)
     work = plan.workspace(G.ga.GA_OP_ENERGY, batch, a.B.n, device=dev)
 
+    tuned, tune_us = plan.autotune(Ahat, batch, work)  # before the timed region
+
     def step():
         G.ga_energy_fields(plan, Ahat, xb, wb, R, a.cB, a.sigma, out=E, work=work)
 
@@ -295,6 +297,8 @@ def main():
                    "grid": n, "batch": batch, "n_pts": a.B.n, "parallelism": "none"},
         "path_GBps_algorithmic": round(step_bytes * args.steps / wall / 1e9, 1),
         "kernel_ms": {k: round(v, 4) for k, v in kern.items()},
+        "autotune": {"strip_groups": tuned[0], "members_per_workgroup": tuned[1],
+                     "candidates_us": {f"{g}x{k}": v for (g, k), v in tune_us.items()}},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": counter_traffic(dom),
                      "algorithmic_bytes_per_launch": abytes[dom]},

@@ -68,8 +68,11 @@ template <int N, bool INV = false> struct Plane {
     return ((u & 1) ? Z::H1 : 0) ^ ((u & 2) ? Z::H2 : 0) ^ ((u & 4) ? Z::H4 : 0);
   }
   // spectrum element (row y, column c in [0, H))
+  static constexpr bool kXor = (Z::H1 | Z::H2 | Z::H4) != 0;
   __device__ __forceinline__ static int yc(int y, int c) {
-    return (y >> 1) * PAIR + (y & 1) * ROW1 + (c < CS ? (c ^ g(y)) : CS);
+    const int base = (PAIR == 2 * H && Z::D == 0) ? y * H : (y >> 1) * PAIR + (y & 1) * ROW1;
+    if constexpr (!kXor) return base + c;
+    else return base + (c < CS ? (c ^ g(y)) : CS);
   }
   // z-transform position p in [0, N) of region t
   __device__ __forceinline__ static int zs(int t, int p) { return t * PAIR + (p ^ ((p >> Z::ZS) & Z::ZM)); }
@@ -530,7 +533,7 @@ __device__ __forceinline__ void plane_from_global(float2* W, const float2* __res
   using P = Plane<N, true>;
   constexpr int H = P::H;
   const float4* s4 = reinterpret_cast<const float4*>(src);
-  if constexpr (P::PAIR == 2 * H && P::Z::D == 0 && (P::Z::H1 | P::Z::H2 | P::Z::H4) == 0) {
+  if constexpr (P::PAIR == 2 * H && P::Z::D == 0 && !P::kXor) {
     // dense layout: element e at slot e
     float4* W4 = reinterpret_cast<float4*>(W);
     batched_copy<N * H / 2, P::THREADS, float4>([&](int i) { return s4[i]; }, [&](int i, float4 v) { W4[i] = v; });
@@ -544,9 +547,10 @@ __device__ __forceinline__ void plane_from_global(float2* W, const float2* __res
   });
 }
 
-// Pass 1. grid = (N planes, batch). GRID: real grids `grid` [batch][N^3]
-// (NCH = 1). Otherwise splat from the binned samples (p.rec) of each batch
-// member. Writes NCH spectra planes per batch member,
+// Pass 1. grid = (N planes, batch, NCH == 4 ? 3 : 1). GRID: real grids
+// `grid` [batch][N^3] (NCH = 1). Otherwise splat from the binned samples
+// (p.rec) of each batch member; with NCH = 4 workgroup z splats channel
+// pass z (u, then yhat_y u, then yhat_z u; yhat_x u is u scaled per plane). Writes NCH spectra planes per batch member,
 // out[((b*NCH + c)*N + x)*N*H]: u, and with NCH = 4 the moment densities
 // yhat_x u, yhat_y u, yhat_z u.
 template <int N, bool GRID, int NCH>
@@ -590,14 +594,8 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_fwd
     }
     __syncthreads();
   };
-  if constexpr (NCH == 1) {
-    run_pass(0);
-  } else if (gridDim.z > 1) {
-    run_pass(blockIdx.z);  // one channel pass per workgroup
-  } else {
-#pragma unroll 1
-    for (int pass = 0; pass < 3; ++pass) run_pass(pass);
-  }
+  if constexpr (NCH == 1) run_pass(0);
+  else run_pass(blockIdx.z);  // one channel pass per workgroup: grid z = 3
 }
 
 // The density itself: grid = (N planes). Writes nch real grids
@@ -1216,6 +1214,12 @@ __global__ void __launch_bounds__(256) k_local_query(const QueryItem* __restrict
 // Kernels without template parameters get internal linkage: the header is
 // included by more than one translation unit.
 namespace {
+
+// Zero n4 float4 values (grid-stride loop).
+__global__ void k_zero4(float4* __restrict__ p, long long n4) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (long long)gridDim.x * blockDim.x)
+    p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
 
 // Sum of the per-strip partials of each pose in a fixed order, times scale.
 // grid = n_poses, block = 64.

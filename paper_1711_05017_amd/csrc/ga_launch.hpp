@@ -27,6 +27,10 @@ struct ga_plan {
   mutable std::vector<ga_prof_entry> prof_pending;
   mutable double prof_ms[GA_K_COUNT] = {};
   mutable long long prof_count[GA_K_COUNT] = {};
+  // fused x pass of ga_energy_fields: strip width in transform groups (4 or
+  // 8) and batch members per workgroup (1, 2, 4, 8); 0 = default
+  int tune_groups = 0;
+  int tune_k = 0;
 };
 
 namespace ga_detail {
@@ -104,7 +108,7 @@ template <int N> struct Launch {
     if (grid)
       hipLaunchKernelGGL((k_plane_fwd<N, true, 1>), dim3(N, batch), dim3(P::THREADS), 0, s, sp, grid, out, tw);
     else if (nch == 4)
-      hipLaunchKernelGGL((k_plane_fwd<N, false, 4>), dim3(N, batch), dim3(P::THREADS), 0, s, sp, grid, out, tw);
+      hipLaunchKernelGGL((k_plane_fwd<N, false, 4>), dim3(N, batch, 3), dim3(P::THREADS), 0, s, sp, grid, out, tw);
     else
       hipLaunchKernelGGL((k_plane_fwd<N, false, 1>), dim3(N, batch), dim3(P::THREADS), 0, s, sp, grid, out, tw);
   }
@@ -117,15 +121,39 @@ template <int N> struct Launch {
     else
       hipLaunchKernelGGL((k_strip_fft<N, G, +1>), dim3(nstrips(), batch), dim3(T::THREADS), 0, s, in, out, tw);
   }
-  // batch members per workgroup of the fused correlation when the stationary
-  // spectrum is shared by the batch
+  // Fused correlation strip pass. With a shared stationary spectrum a
+  // workgroup takes K batch members (default 4) on strips of G = groups x
+  // transforms-per-wave columns (default 4 groups); ga_plan_autotune picks
+  // both per plan.
   static constexpr int kCorrK = 4;
+  template <int GG, int K>
+  static void corr_fwd(const float2* A, long long a_stride, float2* buf, int batch, const float2* tw, hipStream_t s) {
+    using TT = Strip<N, GG>;
+    const int ns = (TT::C + GG - 1) / GG;
+    hipLaunchKernelGGL((k_strip_corr<N, GG, true, K>), dim3(ns, (batch + K - 1) / K), dim3(TT::THREADS), 0, s, A,
+                       a_stride, buf, buf, batch, tw);
+  }
+  template <int GG>
+  static void corr_fwd_k(int k, const float2* A, long long a_stride, float2* buf, int batch, const float2* tw,
+                         hipStream_t s) {
+    switch (k) {
+      case 1: corr_fwd<GG, 1>(A, a_stride, buf, batch, tw, s); break;
+      case 2: corr_fwd<GG, 2>(A, a_stride, buf, batch, tw, s); break;
+      case 8: corr_fwd<GG, 8>(A, a_stride, buf, batch, tw, s); break;
+      default: corr_fwd<GG, 4>(A, a_stride, buf, batch, tw, s); break;
+    }
+  }
+  // groups in {4, 8}, k in {1, 2, 4, 8}; k > 1 only with a shared spectrum
+  static void corr_fwd_tuned(int groups, int k, const float2* A, long long a_stride, float2* buf, int batch,
+                             const float2* tw, hipStream_t s) {
+    if (a_stride != 0 || batch == 1) k = 1;
+    if (groups == 8) corr_fwd_k<8 * ffts_per_wave<N>()>(k, A, a_stride, buf, batch, tw, s);
+    else corr_fwd_k<4 * ffts_per_wave<N>()>(k, A, a_stride, buf, batch, tw, s);
+  }
   static void strip_corr(bool fwd, const float2* A, long long a_stride, const float2* B, float2* out, int batch,
                          const float2* tw, hipStream_t s) {
-    if (fwd && a_stride == 0 && batch > 1) {
-      const int gy = (batch + kCorrK - 1) / kCorrK;
-      hipLaunchKernelGGL((k_strip_corr<N, G, true, kCorrK>), dim3(nstrips(), gy), dim3(T::THREADS), 0, s, A, a_stride,
-                         B, out, batch, tw);
+    if (fwd && B == out) {
+      corr_fwd_tuned(4, kCorrK, A, a_stride, out, batch, tw, s);
     } else if (fwd) {
       hipLaunchKernelGGL((k_strip_corr<N, G, true, 1>), dim3(nstrips(), batch), dim3(T::THREADS), 0, s, A, a_stride, B,
                          out, batch, tw);

@@ -2,6 +2,8 @@
 // The operations, layouts and error behaviour are documented in include/ga.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
@@ -225,7 +227,9 @@ ga_status ga_energy_fields(const ga_plan* plan, const float* d_Ahat, const float
     }
     {
       ProfScope ps(plan, GA_K_STRIP, stream);
-      Launch<N>::strip_corr(true, reinterpret_cast<const float2*>(d_Ahat), 0, tmp, tmp, batch, plan->d_tw, stream);
+      Launch<N>::corr_fwd_tuned(plan->tune_groups ? plan->tune_groups : 4,
+                                plan->tune_k ? plan->tune_k : Launch<N>::kCorrK, reinterpret_cast<const float2*>(d_Ahat),
+                                0, tmp, batch, plan->d_tw, stream);
     }
     ProfScope ps(plan, GA_K_PLANE_INV, stream);
     Launch<N>::plane_inv(tmp, d_E, scale, batch, plan->d_tw, stream);
@@ -330,6 +334,79 @@ ga_status ga_pose_local(const ga_plan* plan, const float* d_FA4, const float* d_
   });
   hipLaunchKernelGGL(k_reduce_partials, dim3(n_poses), dim3(64), 0, stream, (const double*)part, nblk, d_out7, 1.0);
   return launch_status();
+}
+
+ga_status ga_plan_autotune(ga_plan* plan, const float* d_Ahat, int32_t batch, void* d_work, size_t work_bytes,
+                           hipStream_t stream, float* h_us, int32_t n_us) {
+  if (!valid_stream_call(plan) || !d_Ahat || batch < 1 || batch > plan->max_batch || n_us < 0 || (n_us > 0 && !h_us))
+    return GA_EINVAL;
+  const int n = plan->n;
+  const size_t spec_b = spectrum_elems(n) * sizeof(float2);
+  const size_t tmp_b = (size_t)batch * spec_b;
+  if (!d_work || work_bytes < tmp_b) return GA_ENOMEM;
+  if (overlaps(d_work, tmp_b, d_Ahat, spec_b)) return GA_EINVAL;
+  float2* tmp = static_cast<float2*>(d_work);
+  const long long n4 = (long long)(tmp_b / sizeof(float4));
+  hipLaunchKernelGGL(k_zero4, dim3((unsigned)std::min<long long>((n4 + 255) / 256, 65535)), dim3(256), 0, stream,
+                     static_cast<float4*>(d_work), n4);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return GA_EDEVICE;
+  }
+  static constexpr int kGroups[2] = {4, 8}, kKs[4] = {1, 2, 4, 8};
+  float best = 0.f;
+  int best_g = 4, best_k = 4, idx = 0;
+  ga_status st = GA_OK;
+  for (int gi = 0; gi < 2 && st == GA_OK; ++gi) {
+    for (int ki = 0; ki < 4 && st == GA_OK; ++ki, ++idx) {
+      const int g = kGroups[gi], k = kKs[ki];
+      auto run = [&]() {
+        dispatch(n, [&]<int N>() {
+          Launch<N>::corr_fwd_tuned(g, k, reinterpret_cast<const float2*>(d_Ahat), 0, tmp, batch, plan->d_tw, stream);
+        });
+      };
+      run();  // warm-up
+      (void)hipEventRecord(e0, stream);
+      for (int r = 0; r < 3; ++r) run();
+      (void)hipEventRecord(e1, stream);
+      float ms = 0.f;
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        st = GA_EDEVICE;
+        break;
+      }
+      const float us = ms * 1000.f / 3.f;
+      if (idx < n_us) h_us[idx] = us;
+      if (idx == 0 || us < best) {
+        best = us;
+        best_g = g;
+        best_k = k;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != GA_OK) return st;
+  st = launch_status();
+  if (st != GA_OK) return st;
+  plan->tune_groups = best_g;
+  plan->tune_k = best_k;
+  return GA_OK;
+}
+
+ga_status ga_plan_set_tuning(ga_plan* plan, int32_t groups, int32_t k) {
+  if (!plan || !(groups == 0 || groups == 4 || groups == 8) || !(k == 0 || k == 1 || k == 2 || k == 4 || k == 8))
+    return GA_EINVAL;
+  plan->tune_groups = groups;
+  plan->tune_k = k;
+  return GA_OK;
+}
+
+ga_status ga_plan_get_tuning(const ga_plan* plan, int32_t* groups, int32_t* k) {
+  if (!plan || !groups || !k) return GA_EINVAL;
+  *groups = plan->tune_groups ? plan->tune_groups : 4;
+  *k = plan->tune_k ? plan->tune_k : 4;
+  return GA_OK;
 }
 
 ga_status ga_profile_enable(ga_plan* plan, int32_t enable) {

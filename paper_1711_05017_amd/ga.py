@@ -31,6 +31,7 @@ EXPORTS = [
     "ga_field_grad", "ga_pose_local", "ga_profile_enable", "ga_profile_read",
     "ga_server_create", "ga_server_destroy", "ga_pair_register", "ga_pair_release", "ga_submit", "ga_poll",
     "ga_server_get_stats", "ga_batch_create", "ga_batch_launch", "ga_batch_destroy",
+    "ga_plan_autotune", "ga_plan_set_tuning", "ga_plan_get_tuning",
 ]
 GA_K_SPLAT, GA_K_PLANE_FWD, GA_K_STRIP, GA_K_PLANE_INV, GA_K_READOUT, GA_K_BIN = 0, 1, 2, 3, 4, 5
 KERNEL_KINDS = {"splat": 0, "plane_fwd": 1, "strip": 2, "plane_inv": 3, "readout": 4, "bin": 5}
@@ -96,6 +97,10 @@ _SIGS = {
                                    ctypes.POINTER(ctypes.c_uint64)]),
     "ga_poll": (ctypes.c_int32, [_vp, ctypes.c_uint64, ctypes.POINTER(Result)]),
     "ga_server_get_stats": (ctypes.c_int32, [_vp, ctypes.POINTER(ServerStats)]),
+    "ga_plan_autotune": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, _vp, ctypes.c_size_t, _vp,
+                                          ctypes.POINTER(ctypes.c_float), ctypes.c_int32]),
+    "ga_plan_set_tuning": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int32]),
+    "ga_plan_get_tuning": (ctypes.c_int32, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "ga_batch_create": (ctypes.c_int32, [ctypes.POINTER(_vp), ctypes.POINTER(BatchItem), ctypes.c_int32]),
     "ga_batch_launch": (ctypes.c_int32, [_vp, _vp]),
     "ga_batch_destroy": (ctypes.c_int32, [_vp]),
@@ -203,6 +208,27 @@ class Plan:
     def workspace(self, op: int, batch: int = 1, n_items: int = 0, device=None) -> torch.Tensor:
         nbytes = load().ga_workspace_size(self._h, op, batch, n_items)
         return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device or "cuda")
+
+    TUNE_CANDIDATES = [(g, k) for g in (4, 8) for k in (1, 2, 4, 8)]
+
+    def autotune(self, Ahat: torch.Tensor, batch: int, work: Optional[torch.Tensor] = None, stream=None):
+        """Time the fused x-pass candidates (groups, members per workgroup) and
+        keep the fastest; returns (choice, {candidate: microseconds})."""
+        _need(Ahat, torch.complex64, _spec_elems(self.n), "Ahat")
+        if work is None:
+            work = torch.empty(int(batch) * _spec_elems(self.n) * 8, dtype=torch.uint8, device=Ahat.device)
+        us = (ctypes.c_float * 8)()
+        _check("ga_plan_autotune", load().ga_plan_autotune(self._h, _ptr(Ahat), int(batch), _ptr(work),
+                                                           int(work.numel()), _stream(stream), us, 8))
+        return self.tuning(), {c: round(us[i], 2) for i, c in enumerate(self.TUNE_CANDIDATES)}
+
+    def set_tuning(self, groups: int, k: int):
+        _check("ga_plan_set_tuning", load().ga_plan_set_tuning(self._h, int(groups), int(k)))
+
+    def tuning(self):
+        g, k = ctypes.c_int32(), ctypes.c_int32()
+        _check("ga_plan_get_tuning", load().ga_plan_get_tuning(self._h, ctypes.byref(g), ctypes.byref(k)))
+        return g.value, k.value
 
     def profile(self, enable: bool = True):
         """Start (and clear) or stop per-kernel event timing."""
