@@ -91,6 +91,9 @@ typedef int32_t ga_status;
 #define GA_OP_FIELD_GRAD 6
 #define GA_OP_POSE_LOCAL 7
 
+/* Plan flags. */
+#define GA_PLAN_AXIS_PASSES 1u /* separate-axis path at every grid edge */
+
 typedef struct ga_plan ga_plan;
 
 /* Text for a status code (static storage). */
@@ -106,7 +109,16 @@ int32_t ga_supported_n(int32_t n);
  * Plan for grid edge n on the current HIP device (Sec. 3.2: the transforms of
  * eq. 7a/7b on an n^3 grid). n must be even and of the form 2^a 3^b; see
  * ga_supported_n(). The plan owns the float32 twiddle table, computed in
- * float64 on the host. max_batch bounds the batch of later calls. flags: 0.
+ * float64 on the host. max_batch bounds the batch of later calls.
+ *
+ * Execution paths. For n <= 192 one x-plane of the spectrum fits in LDS and
+ * the transforms run in three HBM passes (splat + z + y per plane, x per
+ * strip of columns, y + z per plane). For n = 256, 384, 512, or with flags =
+ * GA_PLAN_AXIS_PASSES at any n, the separate-axis path runs instead: splat
+ * into real grids with float atomics, z transforms per row pair, y and x
+ * transforms per strip of columns (same results, more HBM passes; the C-ABI
+ * calls are unchanged, but ga_pose_local needs n <= 256 and the serving loop
+ * the plane path). flags: 0 or GA_PLAN_AXIS_PASSES.
  * On success *plan is set; release with ga_plan_destroy.
  */
 ga_status ga_plan_create(ga_plan** plan, int32_t n, int32_t max_batch, uint32_t flags);

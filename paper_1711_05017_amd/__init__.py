@@ -8,6 +8,7 @@ from . import ga  # noqa: F401
 from .ga import (  # noqa: F401
     GA_C2R,
     GA_FIELDS,
+    GA_PLAN_AXIS_PASSES,
     GA_R2C,
     GA_SERVE_LOCAL,
     GA_SERVE_SPECTRAL,

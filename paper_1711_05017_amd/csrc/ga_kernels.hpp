@@ -1211,6 +1211,166 @@ __global__ void __launch_bounds__(256) k_local_query(const QueryItem* __restrict
                                                                               red[3][tid];
 }
 
+// ---------------------------------------------------------------------------
+// Separate-axis path (grid edges whose x-plane does not fit in LDS, e.g.
+// 512^3, and any plan created with GA_PLAN_AXIS_PASSES): splat into a real
+// grid, z transforms per row pair, y and x transforms per strip of columns.
+// ---------------------------------------------------------------------------
+
+// Splat with global float atomics: one wavefront per sample, its bounding box
+// walked 64 voxels at a time. grid = (ceil(n_pts / 4), batch), block = 256.
+// out[(b * nch + c) * N^3 + (x * N + y) * N + z] must be zero beforehand;
+// channels u, yhat_x u, yhat_y u, yhat_z u.
+template <int N>
+__global__ void __launch_bounds__(256) k_splat_atomic(SplatParams p, int nch, float* __restrict__ out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long s = (long long)blockIdx.x * 4 + wave;
+  const int b = blockIdx.y;
+  if (s >= p.n_pts) return;  // uniform over the wavefront
+  double R[9];
+  load_rotation(p, b, R);
+  Placed q;
+  if (!place_sample<N>(p, R, s, q)) return;
+  const float w = __int_as_float(q.b.w);
+  if (w == 0.0f) return;
+  const float rho = q.a.w, fx = q.a.x, fy = q.a.y, fz = q.a.z;
+  const int lx = (int)ceilf(fx - rho), ly = (int)ceilf(fy - rho), lz = (int)ceilf(fz - rho);
+  const int ex = (int)floorf(fx + rho) - lx + 1, ey = (int)floorf(fy + rho) - ly + 1, ez = (int)floorf(fz + rho) - lz + 1;
+  const int eyz = ey * ez, V = ex * eyz;
+  const float r2 = rho * rho, inv2s2 = p.sig_c / r2;
+  const size_t n3 = (size_t)N * N * N;
+  float* base = out + (size_t)b * nch * n3;
+  for (int v = lane; v < V; v += 64) {
+    const int ox = v / eyz, rem = v - ox * eyz, oy = rem / ez, oz = rem - oy * ez;
+    const float dx = (float)(lx + ox) - fx, dy = (float)(ly + oy) - fy, dz = (float)(lz + oz) - fz;
+    const float d2 = dx * dx + dy * dy + dz * dz;
+    if (d2 < r2) {
+      const float val = w * (__expf(-d2 * inv2s2) - p.e0) * p.inv1me0;
+      const int xx = wrapn(q.b.x + lx + ox, N), yy = wrapn(q.b.y + ly + oy, N), zz = wrapn(q.b.z + lz + oz, N);
+      const size_t o = ((size_t)xx * N + yy) * N + zz;
+      atomicAdd(base + o, val);
+      if (nch == 4) {
+        atomicAdd(base + n3 + o, yhat(xx, N) * val);
+        atomicAdd(base + 2 * n3 + o, yhat(yy, N) * val);
+        atomicAdd(base + 3 * n3 + o, yhat(zz, N) * val);
+      }
+    }
+  }
+}
+
+// z transforms of real rows, two rows (y, y+1 of one plane) per complex
+// transform: out[(plane * N + y) * H + kz] for kz in [0, N/2]. Transform tr
+// of nrp = planes * N/2; 4 wavefronts per workgroup.
+template <int N> struct Rows {
+  static constexpr int H = N / 2 + 1;
+  static constexpr int L = lanes_per_fft<N>();
+  static constexpr int TPW = ffts_per_wave<N>();
+  static constexpr int PER_WG = 4 * TPW;
+  static constexpr int REG = N + 8;  // LDS slots per transform
+  // position p of a transform: XOR of the low 3 bits with bits 3-5 spreads
+  // the radix-strided stage patterns over bank pairs
+  __device__ __forceinline__ static int sw(int p) { return p ^ ((p >> 3) & 7); }
+};
+
+template <int N>
+__global__ void __launch_bounds__(256) k_rows_fwd(const float* __restrict__ in, float2* __restrict__ out, long long nrp,
+                                                  const float2* __restrict__ table) {
+  using RW = Rows<N>;
+  constexpr int L = RW::L, H = RW::H;
+  __shared__ float2 S[RW::PER_WG * RW::REG];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l = lane % L;
+  const int slot = wave * RW::TPW + lane / L;
+  const long long tr = (long long)blockIdx.x * RW::PER_WG + slot;
+  Twiddles<N> tw;
+  load_twiddles<N>(tw, table, l);
+  if (tr >= nrp) return;  // whole transforms only: every lane of a transform agrees
+  const long long plane = tr / (N / 2);
+  const int y0 = 2 * (int)(tr % (N / 2));
+  const float* r0 = in + ((size_t)plane * N + y0) * N;
+  float2* reg = S + slot * RW::REG;
+  auto at = [=](int pos) { return reg + RW::sw(pos); };
+  auto ld = [&](int pos) { return make_float2(r0[pos], r0[N + pos]); };
+  auto st = [&](int pos, float2 v) { *at(pos) = v; };
+  fft_at<N, -1>(l, tw, at, ld, st);
+  float2* o0 = out + ((size_t)plane * N + y0) * H;
+  for (int k = l; k < H; k += L) {
+    const float2 a = *at(k % N);
+    const float2 z = *at((N - k) % N);
+    o0[k] = make_float2(0.5f * (a.x + z.x), 0.5f * (a.y - z.y));
+    o0[H + k] = make_float2(0.5f * (a.y + z.y), -0.5f * (a.x - z.x));
+  }
+}
+
+// Inverse of k_rows_fwd: out[(plane * N + y) * N + z] = scale * (C2R of
+// row y's half spectrum), two rows per complex transform (imaginary parts at
+// kz = 0 and kz = N/2 dropped).
+template <int N>
+__global__ void __launch_bounds__(256) k_rows_inv(const float2* __restrict__ in, float* __restrict__ out, float scale,
+                                                  long long nrp, const float2* __restrict__ table) {
+  using RW = Rows<N>;
+  constexpr int L = RW::L, H = RW::H;
+  __shared__ float2 S[RW::PER_WG * RW::REG];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l = lane % L;
+  const int slot = wave * RW::TPW + lane / L;
+  const long long tr = (long long)blockIdx.x * RW::PER_WG + slot;
+  Twiddles<N> tw;
+  load_twiddles<N>(tw, table, l);
+  if (tr >= nrp) return;
+  const long long plane = tr / (N / 2);
+  const int y0 = 2 * (int)(tr % (N / 2));
+  const float2* a0 = in + ((size_t)plane * N + y0) * H;
+  const float2* b0 = a0 + H;
+  float2* reg = S + slot * RW::REG;
+  auto at = [=](int pos) { return reg + RW::sw(pos); };
+  auto ld = [&](int k) -> float2 {
+    if (k < H) {
+      float2 a = a0[k], bb = b0[k];
+      if (k == 0 || k == N / 2) {
+        a.y = 0.f;
+        bb.y = 0.f;
+      }
+      return make_float2(a.x - bb.y, a.y + bb.x);
+    }
+    const float2 a = a0[N - k], bb = b0[N - k];
+    return make_float2(a.x + bb.y, bb.x - a.y);
+  };
+  float* r0 = out + ((size_t)plane * N + y0) * N;
+  auto st = [&](int k, float2 v) {
+    r0[k] = v.x * scale;
+    r0[N + k] = v.y * scale;
+  };
+  fft_at<N, +1>(l, tw, at, ld, st);
+}
+
+// Transform along a strided axis, G columns per workgroup: element (pos, c)
+// of plane pl at pl * plane_stride + pos * stride + c, c < ncols. grid =
+// (ceil(ncols / G), planes). In place when in == out (each workgroup reads
+// all of its strip before writing it).
+template <int N, int G, int DIR>
+__global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_pencil_fft(const float2* in, float2* out, long long stride,
+                                                                     int ncols, long long plane_stride,
+                                                                     const float2* __restrict__ table) {
+  using T = Strip<N, G>;
+  __shared__ float2 S[T::SIZE];
+  Twiddles<N> tw;
+  load_twiddles<N>(tw, table, (threadIdx.x & 63) % T::L);
+  const size_t off = (size_t)blockIdx.y * (size_t)plane_stride;
+  const int c0 = blockIdx.x * G;
+  batched_copy<N * G, T::THREADS, float2>(
+      [&](int i) {
+        const int x = i / G, c = c0 + i % G;
+        return (c < ncols) ? in[off + (size_t)x * stride + c] : make_float2(0.f, 0.f);
+      },
+      [&](int i, float2 v) { S[T::idx(i / G, i % G)] = v; });
+  __syncthreads();
+  strip_fft<N, G, DIR>(S, tw);
+  __syncthreads();
+  for (int i = threadIdx.x; i < N * G; i += T::THREADS) {
+    const int x = i / G, g = i % G, c = c0 + g;
+    if (c < ncols) out[off + (size_t)x * stride + c] = S[T::idx(x, g)];
+  }
+}
+
 // Kernels without template parameters get internal linkage: the header is
 // included by more than one translation unit.
 namespace {

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <vector>
@@ -88,8 +89,9 @@ inline ga_status launch_status() {
 
 inline size_t spectrum_elems(int n) { return (size_t)n * n * (n / 2 + 1); }
 
-// Strip width per grid edge: four transforms-per-wave groups, i.e. 4 waves.
-template <int N> constexpr int strip_g() { return 4 * ffts_per_wave<N>(); }
+// Strip width per grid edge: four transforms-per-wave groups, i.e. 4 waves,
+// and at least 16 columns (128-byte runs of global memory per x row).
+template <int N> constexpr int strip_g() { return 4 * ffts_per_wave<N>() < 16 ? 16 : 4 * ffts_per_wave<N>(); }
 constexpr int kSingleG = 64;
 
 template <int N> struct Launch {
@@ -143,12 +145,19 @@ template <int N> struct Launch {
       default: corr_fwd<GG, 4>(A, a_stride, buf, batch, tw, s); break;
     }
   }
-  // groups in {4, 8}, k in {1, 2, 4, 8}; k > 1 only with a shared spectrum
+  // groups in {4, 8}, k in {1, 2, 4, 8}; k > 1 only with a shared spectrum.
+  // Above 256 (few transforms per wavefront, large register footprint) the
+  // strip keeps its default width and one member per workgroup.
+  static constexpr bool kTunable = N <= 256 && 4 * ffts_per_wave<N>() >= 16;
   static void corr_fwd_tuned(int groups, int k, const float2* A, long long a_stride, float2* buf, int batch,
                              const float2* tw, hipStream_t s) {
     if (a_stride != 0 || batch == 1) k = 1;
-    if (groups == 8) corr_fwd_k<8 * ffts_per_wave<N>()>(k, A, a_stride, buf, batch, tw, s);
-    else corr_fwd_k<4 * ffts_per_wave<N>()>(k, A, a_stride, buf, batch, tw, s);
+    if constexpr (!kTunable) {
+      corr_fwd<G, 1>(A, a_stride, buf, batch, tw, s);
+    } else {
+      if (groups == 8) corr_fwd_k<8 * ffts_per_wave<N>()>(k, A, a_stride, buf, batch, tw, s);
+      else corr_fwd_k<4 * ffts_per_wave<N>()>(k, A, a_stride, buf, batch, tw, s);
+    }
   }
   static void strip_corr(bool fwd, const float2* A, long long a_stride, const float2* B, float2* out, int batch,
                          const float2* tw, hipStream_t s) {
@@ -172,7 +181,77 @@ template <int N> struct Launch {
   }
 };
 
-// Calls f.template operator()<N>() for a supported N; returns false otherwise.
+// Whether one x-plane of edge N fits in LDS (plane path kernels exist).
+template <int N> constexpr bool plane_fits() { return N <= 192; }
+
+// Separate-axis path of a grid edge (see k_splat_atomic ... k_pencil_fft).
+template <int N> struct Axis {
+  using LN = Launch<N>;
+  static constexpr int G = strip_g<N>();
+  using T = Strip<N, G>;
+  static constexpr int H = N / 2 + 1;
+  // zeroed real grids [batch][nch][N^3], then the splat of every batch member
+  static void splat(const SplatParams& sp, int nch, float* out, int batch, hipStream_t s) {
+    const long long n4 = (long long)batch * nch * N * N * N / 4;
+    hipLaunchKernelGGL(k_zero4, dim3((unsigned)std::min<long long>((n4 + 255) / 256, 65535)), dim3(256), 0, s,
+                       reinterpret_cast<float4*>(out), n4);
+    if (sp.n_pts > 0)
+      hipLaunchKernelGGL(k_splat_atomic<N>, dim3((unsigned)((sp.n_pts + 3) / 4), batch), dim3(256), 0, s, sp, nch,
+                         out);
+  }
+  static void rows_fwd(const float* in, float2* out, long long planes, const float2* tw, hipStream_t s) {
+    const long long nrp = planes * (N / 2);
+    hipLaunchKernelGGL(k_rows_fwd<N>, dim3((unsigned)((nrp + Rows<N>::PER_WG - 1) / Rows<N>::PER_WG)), dim3(256), 0,
+                       s, in, out, nrp, tw);
+  }
+  static void rows_inv(const float2* in, float* out, float scale, long long planes, const float2* tw, hipStream_t s) {
+    const long long nrp = planes * (N / 2);
+    hipLaunchKernelGGL(k_rows_inv<N>, dim3((unsigned)((nrp + Rows<N>::PER_WG - 1) / Rows<N>::PER_WG)), dim3(256), 0,
+                       s, in, out, scale, nrp, tw);
+  }
+  // y transforms of every column of `planes` x-planes, in place
+  static void pencil_y(int dir, float2* buf, long long planes, const float2* tw, hipStream_t s) {
+    const dim3 grid((H + G - 1) / G, (unsigned)planes);
+    if (dir < 0)
+      hipLaunchKernelGGL((k_pencil_fft<N, G, -1>), grid, dim3(T::THREADS), 0, s, buf, buf, (long long)H, H,
+                         (long long)N * H, tw);
+    else
+      hipLaunchKernelGGL((k_pencil_fft<N, G, +1>), grid, dim3(T::THREADS), 0, s, buf, buf, (long long)H, H,
+                         (long long)N * H, tw);
+  }
+  // real grids -> half spectra with z and y transformed (x not yet)
+  static void zy_fwd(const float* in, float2* out, int batch, const float2* tw, hipStream_t s) {
+    rows_fwd(in, out, (long long)batch * N, tw, s);
+    pencil_y(-1, out, (long long)batch * N, tw, s);
+  }
+  // spectra with x already inverse-transformed -> real grids (y, z inverse)
+  static void yz_inv(float2* spec, float* out, float scale, int batch, const float2* tw, hipStream_t s) {
+    pencil_y(+1, spec, (long long)batch * N, tw, s);
+    rows_inv(spec, out, scale, (long long)batch * N, tw, s);
+  }
+};
+
+// Calls f.template operator()<N>() for a grid edge of the separate-axis
+// path (every supported edge); returns false otherwise.
+template <class F> bool dispatch_axis(int n, F&& f) {
+  switch (n) {
+    case 16: f.template operator()<16>(); return true;
+    case 24: f.template operator()<24>(); return true;
+    case 32: f.template operator()<32>(); return true;
+    case 48: f.template operator()<48>(); return true;
+    case 64: f.template operator()<64>(); return true;
+    case 96: f.template operator()<96>(); return true;
+    case 128: f.template operator()<128>(); return true;
+    case 192: f.template operator()<192>(); return true;
+    case 256: f.template operator()<256>(); return true;
+    case 384: f.template operator()<384>(); return true;
+    case 512: f.template operator()<512>(); return true;
+    default: return false;
+  }
+}
+
+// Calls f.template operator()<N>() for a grid edge whose x-plane fits in LDS
+// (the plane path); returns false otherwise.
 template <class F> bool dispatch(int n, F&& f) {
   switch (n) {
     case 16: f.template operator()<16>(); return true;
@@ -189,14 +268,20 @@ template <class F> bool dispatch(int n, F&& f) {
 
 inline int nstrips_of(int n) {
   int v = 0;
-  dispatch(n, [&]<int N>() { v = Launch<N>::nstrips(); });
+  dispatch_axis(n, [&]<int N>() { v = Launch<N>::nstrips(); });
   return v;
 }
 inline int nsingle_of(int n) {
   int v = 0;
-  dispatch(n, [&]<int N>() { v = Launch<N>::nsingle(); });
+  dispatch_axis(n, [&]<int N>() { v = Launch<N>::nsingle(); });
   return v;
 }
+// Whether a plan runs the separate-axis path (edges whose plane does not fit
+// in LDS, or GA_PLAN_AXIS_PASSES).
+inline bool plane_edge(int n) {
+  return dispatch(n, []<int N>() {});
+}
+inline bool axis_mode(const ga_plan* p) { return (p->flags & GA_PLAN_AXIS_PASSES) != 0 || !plane_edge(p->n); }
 
 // Whether the byte ranges [a, a + na) and [b, b + nb) overlap.
 inline bool overlaps(const void* a, size_t na, const void* b, size_t nb) {

@@ -36,13 +36,13 @@ const char* ga_status_str(ga_status s) {
 const char* ga_version(void) { return kVersion; }
 
 int32_t ga_supported_n(int32_t n) {
-  return dispatch(n, []<int N>() {}) ? 1 : 0;
+  return dispatch_axis(n, []<int N>() {}) ? 1 : 0;
 }
 
 ga_status ga_plan_create(ga_plan** plan, int32_t n, int32_t max_batch, uint32_t flags) {
   if (!plan) return GA_EINVAL;
   *plan = nullptr;
-  if (n < 8 || (n & 1) || max_batch < 1 || flags != 0) return GA_EINVAL;
+  if (n < 8 || (n & 1) || max_batch < 1 || (flags & ~GA_PLAN_AXIS_PASSES) != 0) return GA_EINVAL;
   if (!ga_supported_n(n)) return GA_EUNSUPPORTED;
   ga_plan* p = new (std::nothrow) ga_plan{};
   if (!p) return GA_ENOMEM;
@@ -90,7 +90,9 @@ size_t ga_workspace_size(const ga_plan* plan, int32_t op, int32_t batch, int64_t
   switch (op) {
     case GA_OP_FFT_C2R:
     case GA_OP_CORRELATE: return (size_t)batch * spec;
-    case GA_OP_ENERGY: return bin_offset(n, batch) + bin_bytes(n, batch, n_items);
+    case GA_OP_ENERGY:
+      if (axis_mode(plan)) return (size_t)batch * (spec + real);
+      return bin_offset(n, batch) + bin_bytes(n, batch, n_items);
     case GA_OP_FORCE_FIELDS: return 7 * spec + 7 * real;
     case GA_OP_FORCE_SINGLE: return (size_t)n_items * nsingle_of(n) * 7 * sizeof(double);
     case GA_OP_FIELD_GRAD: return 6 * spec + 3 * real;
@@ -109,11 +111,16 @@ ga_status ga_splat(const ga_plan* plan, const float* d_xyzr, const float* d_w, i
   if (h_c && !(std::isfinite(h_c[0]) && std::isfinite(h_c[1]) && std::isfinite(h_c[2]))) return GA_EINVAL;
   const int n = plan->n;
   const size_t n3 = (size_t)n * n * n;
+  SplatParams sp = make_splat(d_xyzr, d_w, n_pts, nullptr, h_R, h_c, sigma);
+  if (axis_mode(plan)) {
+    ProfScope ps(plan, GA_K_SPLAT, stream);
+    dispatch_axis(n, [&]<int N>() { Axis<N>::splat(sp, channels, d_grid, 1, stream); });
+    return launch_status();
+  }
   if (n_pts == 0) {
     (void)hipMemsetAsync(d_grid, 0, sizeof(float) * n3 * channels, stream);
     return launch_status();
   }
-  SplatParams sp = make_splat(d_xyzr, d_w, n_pts, nullptr, h_R, h_c, sigma);
   dispatch(n, [&]<int N>() {
     ProfScope ps(plan, GA_K_SPLAT, stream);
     hipLaunchKernelGGL(k_splat_real<N>, dim3(N), dim3(Plane<N>::THREADS), 0, stream, sp, channels, d_grid);
@@ -131,6 +138,32 @@ ga_status ga_fft3d(const ga_plan* plan, int32_t dir, const void* d_in, void* d_o
   if (overlaps(d_in, dir == GA_R2C ? real_b : spec_b, d_out, dir == GA_R2C ? spec_b : real_b)) return GA_EINVAL;
   if (dir == GA_C2R && (overlaps(d_work, work_bytes, d_in, spec_b) || overlaps(d_work, work_bytes, d_out, real_b)))
     return GA_EINVAL;
+  if (axis_mode(plan)) {
+    if (dir == GA_R2C) {
+      float2* out = static_cast<float2*>(d_out);
+      dispatch_axis(n, [&]<int N>() {
+        {
+          ProfScope ps(plan, GA_K_PLANE_FWD, stream);
+          Axis<N>::zy_fwd(static_cast<const float*>(d_in), out, batch, plan->d_tw, stream);
+        }
+        ProfScope ps(plan, GA_K_STRIP, stream);
+        Launch<N>::strip_fft(-1, out, out, batch, plan->d_tw, stream);
+      });
+    } else {
+      if (!d_work || work_bytes < ga_workspace_size(plan, GA_OP_FFT_C2R, batch, 0)) return GA_ENOMEM;
+      float2* tmp = static_cast<float2*>(d_work);
+      const float scale = (float)(1.0 / ((double)n * n * n));
+      dispatch_axis(n, [&]<int N>() {
+        {
+          ProfScope ps(plan, GA_K_STRIP, stream);
+          Launch<N>::strip_fft(+1, static_cast<const float2*>(d_in), tmp, batch, plan->d_tw, stream);
+        }
+        ProfScope ps(plan, GA_K_PLANE_INV, stream);
+        Axis<N>::yz_inv(tmp, static_cast<float*>(d_out), scale, batch, plan->d_tw, stream);
+      });
+    }
+    return launch_status();
+  }
   if (dir == GA_R2C) {
     float2* out = static_cast<float2*>(d_out);
     SplatParams sp = make_splat(nullptr, nullptr, 0, nullptr, nullptr, nullptr, 0.5f);
@@ -176,6 +209,18 @@ ga_status ga_correlate(const ga_plan* plan, const float* d_Ahat, int64_t a_strid
   }
   float2* tmp = static_cast<float2*>(d_work);
   const float scale = (float)(1.0 / ((double)n * n * n));
+  if (axis_mode(plan)) {
+    dispatch_axis(n, [&]<int N>() {
+      {
+        ProfScope ps(plan, GA_K_STRIP, stream);
+        Launch<N>::strip_corr(false, reinterpret_cast<const float2*>(d_Ahat), a_stride,
+                              reinterpret_cast<const float2*>(d_Bhat), tmp, batch, plan->d_tw, stream);
+      }
+      ProfScope ps(plan, GA_K_PLANE_INV, stream);
+      Axis<N>::yz_inv(tmp, d_E, scale, batch, plan->d_tw, stream);
+    });
+    return launch_status();
+  }
   dispatch(n, [&]<int N>() {
     {
       ProfScope ps(plan, GA_K_STRIP, stream);
@@ -207,6 +252,29 @@ ga_status ga_energy_fields(const ga_plan* plan, const float* d_Ahat, const float
   float2* tmp = static_cast<float2*>(d_work);
   const float scale = (float)(1.0 / ((double)n * n * n));
   SplatParams sp = make_splat(d_xyzr, d_w, n_pts, d_R, nullptr, h_c, sigma);
+  const int groups = plan->tune_groups ? plan->tune_groups : 4;
+  if (axis_mode(plan)) {
+    float* real = reinterpret_cast<float*>(static_cast<char*>(d_work) + (size_t)batch * spectrum_elems(n) * sizeof(float2));
+    dispatch_axis(n, [&]<int N>() {
+      const int k = plan->tune_k ? plan->tune_k : Launch<N>::kCorrK;
+      {
+        ProfScope ps(plan, GA_K_SPLAT, stream);
+        Axis<N>::splat(sp, 1, real, batch, stream);
+      }
+      {
+        ProfScope ps(plan, GA_K_PLANE_FWD, stream);
+        Axis<N>::zy_fwd(real, tmp, batch, plan->d_tw, stream);
+      }
+      {
+        ProfScope ps(plan, GA_K_STRIP, stream);
+        Launch<N>::corr_fwd_tuned(groups, k, reinterpret_cast<const float2*>(d_Ahat), 0, tmp, batch, plan->d_tw,
+                                  stream);
+      }
+      ProfScope ps(plan, GA_K_PLANE_INV, stream);
+      Axis<N>::yz_inv(tmp, d_E, scale, batch, plan->d_tw, stream);
+    });
+    return launch_status();
+  }
   char* bins = static_cast<char*>(d_work) + bin_offset(n, batch);
   Placed* rec = reinterpret_cast<Placed*>(bins);
   int* off = reinterpret_cast<int*>(bins + (size_t)batch * (size_t)n_pts * sizeof(Placed));
@@ -227,9 +295,8 @@ ga_status ga_energy_fields(const ga_plan* plan, const float* d_Ahat, const float
     }
     {
       ProfScope ps(plan, GA_K_STRIP, stream);
-      Launch<N>::corr_fwd_tuned(plan->tune_groups ? plan->tune_groups : 4,
-                                plan->tune_k ? plan->tune_k : Launch<N>::kCorrK, reinterpret_cast<const float2*>(d_Ahat),
-                                0, tmp, batch, plan->d_tw, stream);
+      Launch<N>::corr_fwd_tuned(groups, plan->tune_k ? plan->tune_k : Launch<N>::kCorrK,
+                                reinterpret_cast<const float2*>(d_Ahat), 0, tmp, batch, plan->d_tw, stream);
     }
     ProfScope ps(plan, GA_K_PLANE_INV, stream);
     Launch<N>::plane_inv(tmp, d_E, scale, batch, plan->d_tw, stream);
@@ -259,14 +326,21 @@ ga_status ga_force_torque(const ga_plan* plan, const float* d_Ahat, const float*
     float2* spec7 = static_cast<float2*>(d_work);
     float* fields7 = reinterpret_cast<float*>(spec7 + 7 * spectrum_elems(n));
     const float scale = (float)(1.0 / ((double)n * n * n));
-    dispatch(n, [&]<int N>() {
+    const bool ax = axis_mode(plan);
+    dispatch_axis(n, [&]<int N>() {
       {
         ProfScope ps(plan, GA_K_READOUT, stream);
         Launch<N>::ft_fields(A, B4, spec7, plan->d_tw, stream);
       }
       ProfScope ps(plan, GA_K_PLANE_INV, stream);
-      Launch<N>::plane_inv(spec7, fields7, scale, 7, plan->d_tw, stream);
+      if (ax) Axis<N>::yz_inv(spec7, fields7, scale, 7, plan->d_tw, stream);
     });
+    if (!ax) {
+      dispatch(n, [&]<int N>() {
+        ProfScope ps(plan, GA_K_PLANE_INV, stream);
+        Launch<N>::plane_inv(spec7, fields7, scale, 7, plan->d_tw, stream);
+      });
+    }
     ProfScope ps(plan, GA_K_READOUT, stream);
     const int threads = 256, total = n_poses * 7;
     hipLaunchKernelGGL(k_gather7, dim3((total + threads - 1) / threads), dim3(threads), 0, stream, fields7, n, d_t,
@@ -274,7 +348,7 @@ ga_status ga_force_torque(const ga_plan* plan, const float* d_Ahat, const float*
   } else {
     double* part = static_cast<double*>(d_work);
     ProfScope ps(plan, GA_K_READOUT, stream);
-    dispatch(n, [&]<int N>() { Launch<N>::single(A, B4, d_t, n_poses, part, plan->d_tw, stream); });
+    dispatch_axis(n, [&]<int N>() { Launch<N>::single(A, B4, d_t, n_poses, part, plan->d_tw, stream); });
     const double scale = 1.0 / ((double)n * n * n);
     hipLaunchKernelGGL(k_reduce_partials, dim3(n_poses), dim3(64), 0, stream, part, nsingle_of(n), d_out7, scale);
   }
@@ -296,13 +370,19 @@ ga_status ga_field_grad(const ga_plan* plan, const float* d_uA, const float* d_A
   float2* tmp = g3 + 3 * spec;
   float* real3 = reinterpret_cast<float*>(tmp + 3 * spec);
   const float scale = (float)(1.0 / ((double)n * n * n));
-  dispatch(n, [&]<int N>() {
+  const bool ax = axis_mode(plan);
+  dispatch_axis(n, [&]<int N>() {
     ProfScope ps(plan, GA_K_READOUT, stream);
     const int threads = 256;
     hipLaunchKernelGGL(k_grad_spectra<N>, dim3((unsigned)((spec + threads - 1) / threads)), dim3(threads), 0, stream,
                        reinterpret_cast<const float2*>(d_Ahat), g3);
     Launch<N>::strip_fft(+1, g3, tmp, 3, plan->d_tw, stream);
-    Launch<N>::plane_inv(tmp, real3, scale, 3, plan->d_tw, stream);
+    if constexpr (plane_fits<N>()) {
+      if (!ax) Launch<N>::plane_inv(tmp, real3, scale, 3, plan->d_tw, stream);
+      else Axis<N>::yz_inv(tmp, real3, scale, 3, plan->d_tw, stream);
+    } else {
+      Axis<N>::yz_inv(tmp, real3, scale, 3, plan->d_tw, stream);
+    }
     hipLaunchKernelGGL(k_pack4, dim3((unsigned)((n3 + threads - 1) / threads)), dim3(threads), 0, stream, d_uA,
                        (const float*)real3, reinterpret_cast<float4*>(d_FA4), (long long)n3);
   });
@@ -320,6 +400,7 @@ ga_status ga_pose_local(const ga_plan* plan, const float* d_FA4, const float* d_
   if (!d_work || work_bytes < ga_workspace_size(plan, GA_OP_POSE_LOCAL, n_poses, n_pts)) return GA_ENOMEM;
   if (overlaps(d_work, work_bytes, d_out7, sizeof(float) * 7 * (size_t)n_poses)) return GA_EINVAL;
   const int n = plan->n;
+  if (n > 256) return GA_EUNSUPPORTED;
   QueryItem* items = static_cast<QueryItem*>(d_work);
   double* part = reinterpret_cast<double*>(items + n_poses);
   const int nblk = nlocal_of(n_pts);
@@ -328,9 +409,11 @@ ga_status ga_pose_local(const ga_plan* plan, const float* d_FA4, const float* d_
   hipLaunchKernelGGL(k_make_items, dim3((n_poses + 63) / 64), dim3(64), 0, stream, items, n_poses,
                      reinterpret_cast<const float4*>(d_xyzr), d_w, (long long)n_pts,
                      reinterpret_cast<const float4*>(d_FA4), d_R, d_t, h_c[0], h_c[1], h_c[2], n);
-  dispatch(n, [&]<int N>() {
+  dispatch_axis(n, [&]<int N>() {
+    if constexpr (N <= 256) {
     hipLaunchKernelGGL(k_local_query<N>, dim3(nblk, n_poses), dim3(256), 0, stream, (const QueryItem*)items, part,
                        sp.sig_c, sp.e0, sp.inv1me0);
+    }
   });
   hipLaunchKernelGGL(k_reduce_partials, dim3(n_poses), dim3(64), 0, stream, (const double*)part, nblk, d_out7, 1.0);
   return launch_status();
@@ -362,7 +445,7 @@ ga_status ga_plan_autotune(ga_plan* plan, const float* d_Ahat, int32_t batch, vo
     for (int ki = 0; ki < 4 && st == GA_OK; ++ki, ++idx) {
       const int g = kGroups[gi], k = kKs[ki];
       auto run = [&]() {
-        dispatch(n, [&]<int N>() {
+        dispatch_axis(n, [&]<int N>() {
           Launch<N>::corr_fwd_tuned(g, k, reinterpret_cast<const float2*>(d_Ahat), 0, tmp, batch, plan->d_tw, stream);
         });
       };

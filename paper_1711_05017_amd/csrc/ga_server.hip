@@ -368,7 +368,7 @@ ga_status ga_server_destroy(ga_server* s) {
 ga_status ga_pair_register(ga_server* s, const ga_part* A, const ga_part* B, const float cB[3], int32_t n, float sigma,
                            uint32_t* pair_id) {
   if (!s || !pair_id || !cB || !valid_sigma(sigma)) return GA_EINVAL;
-  if (!ga_supported_n(n)) return GA_EUNSUPPORTED;
+  if (!plane_edge(n)) return GA_EUNSUPPORTED;  // served sizes use the plane path
   if (!host_part_ok(A, n, true) || !host_part_ok(B, n, false)) return GA_EINVAL;
   if (!(std::isfinite(cB[0]) && std::isfinite(cB[1]) && std::isfinite(cB[2]))) return GA_EINVAL;
   if (hipSetDevice(s->device) != hipSuccess) return GA_EDEVICE;

@@ -23,6 +23,7 @@ GA_FIELDS, GA_SINGLE = 0, 1
 GA_OP_FFT_C2R, GA_OP_CORRELATE, GA_OP_ENERGY, GA_OP_FORCE_FIELDS, GA_OP_FORCE_SINGLE = 1, 2, 3, 4, 5
 GA_OP_FIELD_GRAD, GA_OP_POSE_LOCAL = 6, 7
 GA_SERVE_LOCAL, GA_SERVE_SPECTRAL = 0, 1
+GA_PLAN_AXIS_PASSES = 1
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = [
@@ -193,10 +194,10 @@ def _samples(xyzr: torch.Tensor, w: torch.Tensor) -> int:
 class Plan:
     """A ga_plan for grid edge n on the current device."""
 
-    def __init__(self, n: int, max_batch: int = 1):
+    def __init__(self, n: int, max_batch: int = 1, flags: int = 0):
         lib = load()
         h = ctypes.c_void_p()
-        _check("ga_plan_create", lib.ga_plan_create(ctypes.byref(h), int(n), int(max_batch), 0))
+        _check("ga_plan_create", lib.ga_plan_create(ctypes.byref(h), int(n), int(max_batch), int(flags)))
         self._h = h
         self.n = int(n)
         self.max_batch = int(max_batch)
