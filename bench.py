@@ -202,6 +202,47 @@ def graph_leg(G, synth, np, torch, dev, reps=20):
     return out
 
 
+def c4_leg(G, synth, np, torch, dev, reps=3):
+    """The 512^3 workload: two parts of 50k samples, identity rotation, the
+    energy and 6 gradient fields over all translations, read at 10k poses.
+    Median over `reps` runs of each stage (HIP events), and peak memory."""
+    a = synth.config_c4()
+    n = a.n
+    plan = G.Plan(n, max_batch=4)
+    xa, wa = torch.from_numpy(a.A.xyzr).to(dev), torch.from_numpy(a.A.w).to(dev)
+    xb, wb = torch.from_numpy(a.B.xyzr).to(dev), torch.from_numpy(a.B.w).to(dev)
+    poses = torch.from_numpy(a.poses).to(dev)
+    uA = torch.empty((1, n, n, n), dtype=torch.float32, device=dev)
+    uB4 = torch.empty((4, n, n, n), dtype=torch.float32, device=dev)
+    Ahat = torch.empty((1, n, n, n // 2 + 1), dtype=torch.complex64, device=dev)
+    Bhat4 = torch.empty((4, n, n, n // 2 + 1), dtype=torch.complex64, device=dev)
+    work = plan.workspace(G.ga.GA_OP_FORCE_FIELDS, 1, len(a.poses), device=dev)
+    out = torch.empty((len(a.poses), 7), dtype=torch.float32, device=dev)
+    stages = {"splat_A": lambda: G.ga_splat(plan, xa, wa, sigma=a.sigma, out=uA),
+              "r2c_A": lambda: G.ga_fft3d(plan, G.GA_R2C, uA, out=Ahat),
+              "splat_B_4ch": lambda: G.ga_splat(plan, xb, wb, R=np.eye(3), c=a.cB, sigma=a.sigma, channels=4, out=uB4),
+              "r2c_B_4ch": lambda: G.ga_fft3d(plan, G.GA_R2C, uB4, out=Bhat4),
+              "fields7_and_readout": lambda: G.ga_force_torque(plan, Ahat, Bhat4, poses, G.GA_FIELDS, out=out,
+                                                               work=work)}
+    for f in stages.values():
+        f()
+    torch.cuda.synchronize()
+    ms = {}
+    for name, f in stages.items():
+        t = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            f()
+            e1.record()
+            e1.synchronize()
+            t.append(e0.elapsed_time(e1))
+        ms[name] = round(sorted(t)[len(t) // 2], 3)
+    return {"grid": n, "samples_per_part": int(a.A.n), "poses": int(len(a.poses)), "stage_ms": ms,
+            "total_ms": round(sum(ms.values()), 3),
+            "peak_device_GB": round(torch.cuda.max_memory_allocated() / 1e9, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -211,6 +252,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-c4", action="store_true")
     ap.add_argument("--serving-queries", type=int, default=100000)
     ap.add_argument("--serving-rate", type=float, default=16000.0)
     ap.add_argument("--serving-mode", choices=["local", "spectral"], default="local",
@@ -305,6 +347,8 @@ def main():
     }
     if not args.no_graph:
         out["graph"] = graph_leg(G, synth, np, torch, dev)
+    if not args.no_c4:
+        out["c4_512"] = c4_leg(G, synth, np, torch, dev)
     if not args.no_serving:
         out["serving"] = serving_leg(args.serving_queries, args.serving_rate, mode=args.serving_mode)
     if not args.no_cpu_baseline:
