@@ -34,6 +34,9 @@ from .core import (  # noqa: F401
     torque_field_cross,
     single_pose_sum,
     local_pose_sum,
+    lowpass_mask,
+    lowpass_coarse,
+    lowpass_energy,
     lattice_read,
     trilinear_read,
     pair_fields,

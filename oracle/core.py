@@ -372,6 +372,51 @@ def local_pose_sum(uA, uB, t):
 
 
 # ---------------------------------------------------------------------------
+# Low-pass filtering (Sec. 3.3: only m' << m low-frequency modes are kept)
+# ---------------------------------------------------------------------------
+
+def lowpass_mask(n, L):
+    """Half-spectrum mask [n, n, n/2+1] of the symmetric low-frequency box
+    |kappa(k_a)| <= L/2 - 1 on every axis (kappa = signed frequency index), a
+    set closed under k -> -k, so the kept modes stay Hermitian."""
+    kap = np.where(np.arange(n) < n / 2.0, np.arange(n), np.arange(n) - n)
+    keep = np.abs(kap) <= L // 2 - 1
+    kz = np.arange(n // 2 + 1) <= L // 2 - 1
+    return keep[:, None, None] & keep[None, :, None] & kz[None, None, :]
+
+
+def lowpass_coarse(H, L):
+    """The kept modes of an n-grid half spectrum H as an L-grid half spectrum
+    [L, L, L/2+1] (index L/2 on each axis and kz = L/2 are zero)."""
+    n = H.shape[0]
+    out = np.zeros((L, L, L // 2 + 1), dtype=np.complex128)
+    kp = np.arange(L)
+    kap = np.where(kp < L / 2.0, kp, kp - L)
+    ok = np.abs(kap) <= L // 2 - 1
+    src = kap % n
+    for i in np.nonzero(ok)[0]:
+        for j in np.nonzero(ok)[0]:
+            out[i, j, : L // 2] = H[src[i], src[j], : L // 2]
+    return out
+
+
+def lowpass_energy(Ahat, Bhat, L, ts):
+    """E_L(t) = n^-3 sum over the kept box of Ahat(k) conj(Bhat(k))
+    exp(+2 pi i k.t / n) at integer translations t (full spectra in)."""
+    n = Ahat.shape[0]
+    kap = np.where(np.arange(n) < n / 2.0, np.arange(n), np.arange(n) - n)
+    keep1 = np.abs(kap) <= L // 2 - 1
+    keep = keep1[:, None, None] & keep1[None, :, None] & keep1[None, None, :]
+    P = np.where(keep, Ahat * np.conj(Bhat), 0)
+    g = np.arange(n)
+    out = []
+    for t in np.asarray(np.rint(ts), dtype=np.int64).reshape(-1, 3):
+        idx = (g[:, None, None] * t[0] + g[None, :, None] * t[1] + g[None, None, :] * t[2]) % n
+        out.append(np.real(np.sum(P * _unit_root(n, idx, +1))) / float(n) ** 3)
+    return np.array(out)
+
+
+# ---------------------------------------------------------------------------
 # Pose readout (Sec. 2.4, force/torque at the current configuration)
 # ---------------------------------------------------------------------------
 

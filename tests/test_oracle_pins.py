@@ -496,6 +496,31 @@ def test_local_pose_sum_equals_lattice_fields(n):
         assert np.abs(s - ref).max() < 1e-10 * scale
 
 
+@pytest.mark.parametrize("k0,inside", [((1, 2, 1), True), ((3, -2, 1), True), ((4, 1, 1), False), ((1, 1, 6), False)])
+def test_lowpass_of_band_limited_waves(k0, inside):
+    """Sec. 3.3 low-pass filtering. Two waves cos(2 pi k0.p/n) and
+    cos(2 pi k0.p/n + phi): inside the box (|k0_a| <= L/2 - 1) the filtered
+    energy is the full closed form (n^3/2) cos(2 pi k0.t/n - phi); outside it
+    vanishes. On the coarse grid the kept modes give the same values at
+    t = t' n / L, and the mask is Hermitian-closed."""
+    n, L, phi = 16, 8, 0.7
+    g = np.arange(n, dtype=np.float64)
+    ph = 2 * np.pi * ((k0[0] * g[:, None, None] + k0[1] * g[None, :, None] + k0[2] * g[None, None, :]) % n) / n
+    a, b = np.cos(ph), np.cos(ph + phi)
+    Ah, Bh = O.fft3(a), O.fft3(b)
+    ts = [(0, 0, 0), (2, 4, 6), (6, 2, 10), (14, 8, 4)]
+    got = O.lowpass_energy(Ah, Bh, L, ts)
+    full = np.array([(n ** 3 / 2) * np.cos(2 * np.pi * np.dot(k0, t) / n - phi) for t in ts])
+    assert np.allclose(got, full if inside else 0 * full, atol=1e-9 * n ** 3)
+    # coarse grid: L^-3 IDFT_L of the kept product, times (L/n)^3, at t' = t L / n
+    PL = O.lowpass_coarse(O.rfft3(a), L) * np.conj(O.lowpass_coarse(O.rfft3(b), L))
+    EL = O.irfft3(PL) * (L / n) ** 3
+    coarse = [EL[t[0] * L // n, t[1] * L // n, t[2] * L // n] for t in ts]
+    assert np.allclose(coarse, got, atol=1e-9 * n ** 3)
+    m = O.lowpass_mask(n, L)
+    assert m[1, 2, 1] and not m[4, 0, 0] and not m[0, 0, 4] and m[n - 3, 3, 3] == m[3, n - 3, 3]
+
+
 def test_trilinear_read_is_exact_on_lattice_and_linear_between():
     n = 8
     f = np.random.default_rng(2).standard_normal((n, n, n))
