@@ -224,6 +224,27 @@ ga_status ga_pose_local(const ga_plan* plan, const float* d_FA4, const float* d_
                         float* d_out7, void* d_work, size_t work_bytes, hipStream_t stream);
 
 /*
+ * Low-pass filtering (Sec. 3.3): of the n-grid half spectra only the modes
+ * of the symmetric low-frequency box |kappa(k_a)| <= L/2 - 1 (kappa the signed
+ * frequency index, every axis) are kept, times `scale`; L even, 4 <= L <= n.
+ *   GA_LOWPASS_COARSE:  d_out = batch x [L][L][L/2+1], the kept modes on an L
+ *     grid (index L/2 of each axis zero). Correlated with a plan for edge L
+ *     (ga_correlate, ga_force_torque), with scale (L/n)^3 applied to one
+ *     operand, it gives the filtered energy at the coarse translations
+ *     t = t' n / L: E_L(t) = n^-3 sum_box Ahat conj(Bhat) exp(+2 pi i k.t/n);
+ *     forces and torques from the L plan are per coarse voxel, i.e. times
+ *     n / L of their per-voxel values, so multiply them by L / n.
+ *   GA_LOWPASS_ZEROPAD: d_out = batch x [n][n][n/2+1] with the dropped modes
+ *     zero (the zero padding of Sec. 4.3); any n-plan call then yields the
+ *     filtered fields at full resolution.
+ * d_in and d_out must not overlap. Errors: GA_EINVAL.
+ */
+#define GA_LOWPASS_COARSE 0u
+#define GA_LOWPASS_ZEROPAD 1u
+ga_status ga_lowpass(const ga_plan* plan, int32_t L, uint32_t mode, const float* d_in, float* d_out, int32_t batch,
+                     float scale, hipStream_t stream);
+
+/*
  * Autotuning of the fused correlation pass of ga_energy_fields (the x
  * transform, product with the shared stationary spectrum and inverse x
  * transform): candidates are the strip width (4 or 8 groups of transforms per

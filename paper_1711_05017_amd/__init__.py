@@ -8,6 +8,8 @@ from . import ga  # noqa: F401
 from .ga import (  # noqa: F401
     GA_C2R,
     GA_FIELDS,
+    GA_LOWPASS_COARSE,
+    GA_LOWPASS_ZEROPAD,
     GA_PLAN_AXIS_PASSES,
     GA_R2C,
     GA_SERVE_LOCAL,
@@ -22,6 +24,7 @@ from .ga import (  # noqa: F401
     ga_fft3d,
     ga_field_grad,
     ga_force_torque,
+    ga_lowpass,
     ga_pose_local,
     ga_splat,
     ga_supported_n,

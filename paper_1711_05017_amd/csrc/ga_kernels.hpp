@@ -1381,6 +1381,32 @@ __global__ void k_zero4(float4* __restrict__ p, long long n4) {
     p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
+// Low-pass filtering of half spectra (Sec. 3.3): modes with |kappa(k_a)| <=
+// L/2 - 1 on every axis are kept (times scale), the rest are dropped.
+// coarse = 1: out is [batch][L][L][L/2+1] (the kept modes on an L grid);
+// coarse = 0: out is [batch][n][n][n/2+1] with the dropped modes zero.
+// Grid-stride loop over the output elements.
+__global__ void k_lowpass(const float2* __restrict__ in, float2* __restrict__ out, int n, int L, int coarse,
+                          long long batch, float scale) {
+  const int hn = n / 2 + 1, m = coarse ? L : n, hm = m / 2 + 1;
+  const long long per = (long long)m * m * hm, total = batch * per;
+  const int lim = L / 2 - 1;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long b = e / per;
+    const long long r = e - b * per;
+    const int kz = (int)(r % hm), ky = (int)((r / hm) % m), kx = (int)(r / ((long long)hm * m));
+    const int ax = kx < m / 2 ? kx : kx - m, ay = ky < m / 2 ? ky : ky - m;  // signed frequencies
+    float2 v = make_float2(0.f, 0.f);
+    if (ax <= lim && ax >= -lim && ay <= lim && ay >= -lim && kz <= lim) {
+      const int sx = ax < 0 ? ax + n : ax, sy = ay < 0 ? ay + n : ay;
+      const float2 a = in[(size_t)b * n * n * hn + ((size_t)sx * n + sy) * hn + kz];
+      v = make_float2(a.x * scale, a.y * scale);
+    }
+    out[e] = v;
+  }
+}
+
 // Sum of the per-strip partials of each pose in a fixed order, times scale.
 // grid = n_poses, block = 64.
 __global__ void __launch_bounds__(64) k_reduce_partials(const double* __restrict__ part, int nblk, float* __restrict__ out7,

@@ -492,6 +492,23 @@ ga_status ga_plan_get_tuning(const ga_plan* plan, int32_t* groups, int32_t* k) {
   return GA_OK;
 }
 
+ga_status ga_lowpass(const ga_plan* plan, int32_t L, uint32_t mode, const float* d_in, float* d_out, int32_t batch,
+                     float scale, hipStream_t stream) {
+  if (!valid_stream_call(plan) || !d_in || !d_out || batch < 1 || !std::isfinite(scale)) return GA_EINVAL;
+  const int n = plan->n;
+  if (L < 4 || (L & 1) || L > n || (mode != GA_LOWPASS_COARSE && mode != GA_LOWPASS_ZEROPAD)) return GA_EINVAL;
+  const int m = (mode == GA_LOWPASS_COARSE) ? L : n;
+  const size_t in_b = (size_t)batch * spectrum_elems(n) * sizeof(float2);
+  const size_t out_b = (size_t)batch * spectrum_elems(m) * sizeof(float2);
+  if (overlaps(d_in, in_b, d_out, out_b)) return GA_EINVAL;
+  const long long total = (long long)batch * (long long)spectrum_elems(m);
+  const unsigned blocks = (unsigned)std::min<long long>((total + 255) / 256, 65535);
+  ProfScope ps(plan, GA_K_READOUT, stream);
+  hipLaunchKernelGGL(k_lowpass, dim3(blocks), dim3(256), 0, stream, reinterpret_cast<const float2*>(d_in),
+                     reinterpret_cast<float2*>(d_out), n, L, mode == GA_LOWPASS_COARSE ? 1 : 0, (long long)batch, scale);
+  return launch_status();
+}
+
 ga_status ga_profile_enable(ga_plan* plan, int32_t enable) {
   if (!plan) return GA_EINVAL;
   prof_drain(plan);

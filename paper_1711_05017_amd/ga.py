@@ -24,6 +24,7 @@ GA_OP_FFT_C2R, GA_OP_CORRELATE, GA_OP_ENERGY, GA_OP_FORCE_FIELDS, GA_OP_FORCE_SI
 GA_OP_FIELD_GRAD, GA_OP_POSE_LOCAL = 6, 7
 GA_SERVE_LOCAL, GA_SERVE_SPECTRAL = 0, 1
 GA_PLAN_AXIS_PASSES = 1
+GA_LOWPASS_COARSE, GA_LOWPASS_ZEROPAD = 0, 1
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = [
@@ -32,7 +33,7 @@ EXPORTS = [
     "ga_field_grad", "ga_pose_local", "ga_profile_enable", "ga_profile_read",
     "ga_server_create", "ga_server_destroy", "ga_pair_register", "ga_pair_release", "ga_submit", "ga_poll",
     "ga_server_get_stats", "ga_batch_create", "ga_batch_launch", "ga_batch_destroy",
-    "ga_plan_autotune", "ga_plan_set_tuning", "ga_plan_get_tuning",
+    "ga_plan_autotune", "ga_plan_set_tuning", "ga_plan_get_tuning", "ga_lowpass",
 ]
 GA_K_SPLAT, GA_K_PLANE_FWD, GA_K_STRIP, GA_K_PLANE_INV, GA_K_READOUT, GA_K_BIN = 0, 1, 2, 3, 4, 5
 KERNEL_KINDS = {"splat": 0, "plane_fwd": 1, "strip": 2, "plane_inv": 3, "readout": 4, "bin": 5}
@@ -98,6 +99,8 @@ _SIGS = {
                                    ctypes.POINTER(ctypes.c_uint64)]),
     "ga_poll": (ctypes.c_int32, [_vp, ctypes.c_uint64, ctypes.POINTER(Result)]),
     "ga_server_get_stats": (ctypes.c_int32, [_vp, ctypes.POINTER(ServerStats)]),
+    "ga_lowpass": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_uint32, _vp, _vp, ctypes.c_int32, ctypes.c_float,
+                                    _vp]),
     "ga_plan_autotune": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, _vp, ctypes.c_size_t, _vp,
                                           ctypes.POINTER(ctypes.c_float), ctypes.c_int32]),
     "ga_plan_set_tuning": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int32]),
@@ -385,6 +388,22 @@ def ga_pose_local(plan: Plan, FA4: torch.Tensor, xyzr: torch.Tensor, w: torch.Te
     st = load().ga_pose_local(plan.handle, _ptr(FA4), _ptr(xyzr), _ptr(w), m, _ptr(R), _host_f32(c, 3), float(sigma),
                               _ptr(t), n_poses, _ptr(out), _ptr(work), int(work.numel()), _stream(stream))
     _check("ga_pose_local", st)
+    return out
+
+
+def ga_lowpass(plan: Plan, X: torch.Tensor, L: int, mode: int = GA_LOWPASS_COARSE, scale: float = 1.0,
+               out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Keep the low-frequency box |kappa| <= L/2 - 1 of n-grid half spectra X
+    ([batch,] n, n, n/2+1): on an L grid (coarse) or zero-padded at n."""
+    n = plan.n
+    batch = X.shape[0] if X.dim() == 4 else 1
+    _need(X, torch.complex64, batch * _spec_elems(n), "X", exact=True)
+    m = int(L) if mode == GA_LOWPASS_COARSE else n
+    if out is None:
+        out = torch.empty((batch, m, m, m // 2 + 1), dtype=torch.complex64, device=X.device)
+    _need(out, torch.complex64, batch * _spec_elems(m), "out")
+    _check("ga_lowpass", load().ga_lowpass(plan.handle, int(L), int(mode), _ptr(X), _ptr(out), int(batch), float(scale),
+                                           _stream(stream)))
     return out
 
 
