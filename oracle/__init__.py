@@ -34,6 +34,8 @@ from .core import (  # noqa: F401
     torque_field_cross,
     single_pose_sum,
     local_pose_sum,
+    spectral_rotate,
+    spectral_rotate4,
     lowpass_mask,
     lowpass_coarse,
     lowpass_energy,

@@ -372,6 +372,48 @@ def local_pose_sum(uA, uB, t):
 
 
 # ---------------------------------------------------------------------------
+# Spectral rotation (Sec. 3.2, step 1: the moving part's spectra interpolated
+# trilinearly over the rotated frequency grid R^T omega)
+# ---------------------------------------------------------------------------
+
+def spectral_rotate(X, R):
+    """X_R(k) = X(R^T kappa(k)) by trilinear interpolation over the full
+    spectrum X [n, n, n] (signed frequencies kappa; corners with a component
+    beyond n/2 in magnitude contribute zero). For a density u about the grid
+    origin, X_R approximates the spectrum of u o R^T."""
+    n = X.shape[0]
+    R = np.asarray(R, dtype=np.float64).reshape(3, 3)
+    kap = np.where(np.arange(n) < n / 2.0, np.arange(n), np.arange(n) - n).astype(np.float64)
+    K = np.stack(np.meshgrid(kap, kap, kap, indexing="ij"), -1)  # [n, n, n, 3]
+    Q = K @ R  # rows: (R^T kappa)^T = kappa^T R
+    f = np.floor(Q)
+    a = Q - f
+    f = f.astype(np.int64)
+    out = np.zeros(X.shape, dtype=np.complex128)
+    for dx in (0, 1):
+        for dy in (0, 1):
+            for dz in (0, 1):
+                c = f + np.array([dx, dy, dz])
+                w = (np.where(dx, a[..., 0], 1 - a[..., 0]) * np.where(dy, a[..., 1], 1 - a[..., 1]) *
+                     np.where(dz, a[..., 2], 1 - a[..., 2]))
+                inside = np.all(np.abs(c) <= n // 2, axis=-1)
+                v = X[c[..., 0] % n, c[..., 1] % n, c[..., 2] % n]
+                out += np.where(inside, w * v, 0)
+    return out
+
+
+def spectral_rotate4(X4, R):
+    """The 4 channels (u, yhat_x u, yhat_y u, yhat_z u) of the moving part: the
+    density spectrum is interpolated at R^T kappa, the moment spectra as a
+    vector, M_R(k) = R M(R^T kappa(k)) (the moment density of the rotated part
+    is p u(R^T p) = R (R^T p) u(R^T p))."""
+    R = np.asarray(R, dtype=np.float64).reshape(3, 3)
+    I = [spectral_rotate(X4[c], R) for c in range(4)]
+    M = [sum(R[a, b] * I[1 + b] for b in range(3)) for a in range(3)]
+    return np.stack([I[0], *M])
+
+
+# ---------------------------------------------------------------------------
 # Low-pass filtering (Sec. 3.3: only m' << m low-frequency modes are kept)
 # ---------------------------------------------------------------------------
 
@@ -474,8 +516,10 @@ def pair_fields(A_xyzr, A_w, B_xyzr, B_w, R, cB, n, sigma=0.5, want_torque=True,
 
 
 def rel_l2(got, ref):
-    """||got - ref||_2 / ||ref||_2 over all elements."""
-    got = np.asarray(got, dtype=np.float64)
-    ref = np.asarray(ref, dtype=np.float64)
+    """||got - ref||_2 / ||ref||_2 over all elements (complex values compared
+    as complex numbers)."""
+    cplx = np.iscomplexobj(got) or np.iscomplexobj(ref)
+    got = np.asarray(got, dtype=np.complex128 if cplx else np.float64)
+    ref = np.asarray(ref, dtype=np.complex128 if cplx else np.float64)
     den = np.linalg.norm(ref.ravel())
     return float(np.linalg.norm((got - ref).ravel()) / (den if den > 0 else 1.0))

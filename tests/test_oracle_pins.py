@@ -496,6 +496,58 @@ def test_local_pose_sum_equals_lattice_fields(n):
         assert np.abs(s - ref).max() < 1e-10 * scale
 
 
+def _cube_rotations():
+    mats = []
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product((1, -1), repeat=3):
+            Q = np.zeros((3, 3))
+            for i in range(3):
+                Q[i, perm[i]] = signs[i]
+            if np.linalg.det(Q) > 0:
+                mats.append(Q)
+    return mats
+
+
+def _rotate_grid(u, Q):
+    """u'(p) = u(Q^T p) on the lattice (signed coordinates mod n), exact for
+    a cube rotation Q."""
+    n = u.shape[0]
+    s = np.where(np.arange(n) < n / 2.0, np.arange(n), np.arange(n) - n)
+    P = np.stack(np.meshgrid(s, s, s, indexing="ij"), -1)
+    src = (P @ Q).astype(np.int64) % n  # Q^T p as rows
+    return u[src[..., 0], src[..., 1], src[..., 2]]
+
+
+def test_spectral_rotation_identity_and_cube_rotations_are_exact():
+    """Sec. 3.2 step 1. R = I returns the spectrum; for each of the 24 cube
+    rotations Q, R^T kappa is a lattice point, so the interpolated spectra are
+    exactly the spectra of the rotated grid (density and moment channels)."""
+    n = 12
+    A, B = _small_pair(n, seed=71, npts=30, conf=2.5)
+    u = O.splat(O.place(B.xyzr[:, :3], np.eye(3), B.ref_point()), B.xyzr[:, 3], B.w, n)
+    X4 = np.stack([O.fft3(u)] + [O.fft3(m) for m in O.moment_channels(u)])
+    assert np.allclose(O.spectral_rotate(X4[0], np.eye(3)), X4[0], atol=1e-12 * np.abs(X4[0]).max())
+    for Q in _cube_rotations()[1::3]:
+        ur = _rotate_grid(u, Q)
+        ref = np.stack([O.fft3(ur)] + [O.fft3(m) for m in O.moment_channels(ur)])
+        got = O.spectral_rotate4(X4, Q)
+        assert np.abs(got - ref).max() < 1e-9 * np.abs(ref).max(), Q
+
+
+def test_spectral_rotation_approximates_resplat():
+    """For a general rotation the interpolated spectrum approximates the
+    spectrum of the re-splatted rotated part (loose: trilinear interpolation
+    of a spectrum whose support is a few voxels wide)."""
+    n = 24
+    B = synth.random_part(81, n, 30, 2.0, 3.0, conf_radius=2.0)
+    c = B.ref_point()
+    u0 = O.splat(O.place(B.xyzr[:, :3], np.eye(3), c), B.xyzr[:, 3], B.w, n)
+    R = synth.shoemake_rotations(82, 1)[0]
+    uR = O.splat(O.place(B.xyzr[:, :3], R, c), B.xyzr[:, 3], B.w, n)
+    got = O.spectral_rotate(O.fft3(u0), R)
+    assert O.rel_l2(got, O.fft3(uR)) < 0.25
+
+
 @pytest.mark.parametrize("k0,inside", [((1, 2, 1), True), ((3, -2, 1), True), ((4, 1, 1), False), ((1, 1, 6), False)])
 def test_lowpass_of_band_limited_waves(k0, inside):
     """Sec. 3.3 low-pass filtering. Two waves cos(2 pi k0.p/n) and
@@ -529,3 +581,10 @@ def test_trilinear_read_is_exact_on_lattice_and_linear_between():
     assert mid[0] == pytest.approx(0.5 * (f[1, 2, 7] + f[2, 2, 7]))
     wrap = O.trilinear_read(f, [[7.25, 0.0, 0.0]])
     assert wrap[0] == pytest.approx(0.75 * f[7, 0, 0] + 0.25 * f[0, 0, 0])
+
+
+def test_rel_l2_compares_complex_values():
+    """A mismatch only in imaginary parts must show."""
+    a = np.array([1 + 1j, 2 - 1j])
+    assert O.rel_l2(a, a) == 0.0
+    assert O.rel_l2(a.real + 0j, a) > 0.4
