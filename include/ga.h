@@ -224,6 +224,23 @@ ga_status ga_pose_local(const ga_plan* plan, const float* d_FA4, const float* d_
                         float* d_out7, void* d_work, size_t work_bytes, hipStream_t stream);
 
 /*
+ * Spectral rotation (Sec. 3.2, step 1): instead of re-splatting the rotated
+ * part, its resident spectra are interpolated trilinearly over the rotated
+ * frequency grid: out_b(k) = X(R_b^T kappa(k)), kappa the signed frequency
+ * (the Nyquist index n/2 taken as -n/2 on every axis),
+ * X(-k) = conj X(k) for negative kz, zero beyond |component| = n/2. With
+ * channels = 4 (u, yhat_x u, yhat_y u, yhat_z u of the part about the grid
+ * origin, e.g. ga_splat with R = I and c = its reference point) the moment
+ * channels rotate as a vector: M_R(k) = R_b M(R_b^T kappa). d_in: channels
+ * half spectra; d_R: batch x 9 rotations (device, row-major); d_out: batch x
+ * channels half spectra, usable by ga_correlate and ga_force_torque. An
+ * approximation of the re-splatted spectra (exact for R = I and the 24
+ * rotations of the cube). Errors: GA_EINVAL (channels not 1 or 4, overlaps).
+ */
+ga_status ga_spectral_rotate(const ga_plan* plan, const float* d_in, int32_t channels, const float* d_R, int32_t batch,
+                             float* d_out, hipStream_t stream);
+
+/*
  * Low-pass filtering (Sec. 3.3): of the n-grid half spectra only the modes
  * of the symmetric low-frequency box |kappa(k_a)| <= L/2 - 1 (kappa the signed
  * frequency index, every axis) are kept, times `scale`; L even, 4 <= L <= n.

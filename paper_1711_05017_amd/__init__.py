@@ -25,6 +25,7 @@ from .ga import (  # noqa: F401
     ga_field_grad,
     ga_force_torque,
     ga_lowpass,
+    ga_spectral_rotate,
     ga_pose_local,
     ga_splat,
     ga_supported_n,

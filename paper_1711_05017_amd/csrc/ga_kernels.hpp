@@ -1381,6 +1381,71 @@ __global__ void k_zero4(float4* __restrict__ p, long long n4) {
     p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
+// Value of a real grid's spectrum at signed integer frequency (a, b, c) from
+// its half spectrum X [n][n][n/2+1]: X(-k) = conj X(k) supplies c < 0; zero
+// beyond the band (|component| > n/2).
+__device__ __forceinline__ float2 spec_at(const float2* __restrict__ X, int n, int a, int b, int c) {
+  const int h = n / 2;
+  if (a > h || a < -h || b > h || b < -h || c > h || c < -h) return make_float2(0.f, 0.f);
+  if (c < 0) {
+    a = -a;
+    b = -b;
+    c = -c;
+    const float2 v = X[((size_t)((a + n) % n) * n + (size_t)((b + n) % n)) * (h + 1) + c];
+    return make_float2(v.x, -v.y);
+  }
+  return X[((size_t)((a + n) % n) * n + (size_t)((b + n) % n)) * (h + 1) + c];
+}
+
+// Spectral rotation (Sec. 3.2, step 1): out_b(k) = X(R_b^T kappa(k)) by
+// trilinear interpolation; with nch = 4 (u, yhat_x u, yhat_y u, yhat_z u) the
+// moment channels rotate as a vector, M_R(k) = R M(R^T kappa). in: nch half
+// spectra of the unrotated part about the grid origin; out: batch x nch half
+// spectra. Grid-stride loop over batch x half-spectrum elements.
+__global__ void k_spectral_rotate(const float2* __restrict__ in, int nch, const float* __restrict__ Rm, int n,
+                                  long long batch, float2* __restrict__ out) {
+  const int hn = n / 2 + 1;
+  const long long spec = (long long)n * n * hn, total = batch * spec;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long b = e / spec, r = e - b * spec;
+    const int kz = (int)(r % hn), ky = (int)((r / hn) % n), kx = (int)(r / ((long long)hn * n));
+    // signed frequencies; the Nyquist index n/2 is taken as -n/2 on every axis
+    const double k0 = kx < n / 2 ? kx : kx - n, k1 = ky < n / 2 ? ky : ky - n, k2 = kz < n / 2 ? kz : kz - n;
+    double R[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) R[i] = (double)Rm[b * 9 + i];
+    // q = R^T kappa
+    const double q0 = R[0] * k0 + R[3] * k1 + R[6] * k2;
+    const double q1 = R[1] * k0 + R[4] * k1 + R[7] * k2;
+    const double q2 = R[2] * k0 + R[5] * k1 + R[8] * k2;
+    const double f0 = floor(q0), f1 = floor(q1), f2 = floor(q2);
+    const float a0 = (float)(q0 - f0), a1 = (float)(q1 - f1), a2 = (float)(q2 - f2);
+    const int i0 = (int)f0, i1 = (int)f1, i2 = (int)f2;
+    float2 acc[4] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int dx = c >> 2, dy = (c >> 1) & 1, dz = c & 1;
+      const float w = (dx ? a0 : 1.f - a0) * (dy ? a1 : 1.f - a1) * (dz ? a2 : 1.f - a2);
+      if (w == 0.f) continue;
+      for (int ch = 0; ch < nch; ++ch) {
+        const float2 v = spec_at(in + (size_t)ch * spec, n, i0 + dx, i1 + dy, i2 + dz);
+        acc[ch].x += w * v.x;
+        acc[ch].y += w * v.y;
+      }
+    }
+    float2* o = out + (size_t)b * nch * spec + r;
+    o[0] = acc[0];
+    if (nch == 4) {
+      for (int a = 0; a < 3; ++a) {
+        const float ra = (float)R[3 * a], rb = (float)R[3 * a + 1], rc = (float)R[3 * a + 2];
+        o[(size_t)(1 + a) * spec] = make_float2(ra * acc[1].x + rb * acc[2].x + rc * acc[3].x,
+                                                ra * acc[1].y + rb * acc[2].y + rc * acc[3].y);
+      }
+    }
+  }
+}
+
 // Low-pass filtering of half spectra (Sec. 3.3): modes with |kappa(k_a)| <=
 // L/2 - 1 on every axis are kept (times scale), the rest are dropped.
 // coarse = 1: out is [batch][L][L][L/2+1] (the kept modes on an L grid);

@@ -492,6 +492,23 @@ ga_status ga_plan_get_tuning(const ga_plan* plan, int32_t* groups, int32_t* k) {
   return GA_OK;
 }
 
+ga_status ga_spectral_rotate(const ga_plan* plan, const float* d_in, int32_t channels, const float* d_R, int32_t batch,
+                             float* d_out, hipStream_t stream) {
+  if (!valid_stream_call(plan) || !d_in || !d_R || !d_out || batch < 1 || (channels != 1 && channels != 4))
+    return GA_EINVAL;
+  const int n = plan->n;
+  const size_t spec_b = spectrum_elems(n) * sizeof(float2);
+  if (overlaps(d_in, channels * spec_b, d_out, (size_t)batch * channels * spec_b) ||
+      overlaps(d_R, sizeof(float) * 9 * (size_t)batch, d_out, (size_t)batch * channels * spec_b))
+    return GA_EINVAL;
+  const long long total = (long long)batch * (long long)spectrum_elems(n);
+  const unsigned blocks = (unsigned)std::min<long long>((total + 255) / 256, 65535);
+  ProfScope ps(plan, GA_K_READOUT, stream);
+  hipLaunchKernelGGL(k_spectral_rotate, dim3(blocks), dim3(256), 0, stream, reinterpret_cast<const float2*>(d_in),
+                     (int)channels, d_R, n, (long long)batch, reinterpret_cast<float2*>(d_out));
+  return launch_status();
+}
+
 ga_status ga_lowpass(const ga_plan* plan, int32_t L, uint32_t mode, const float* d_in, float* d_out, int32_t batch,
                      float scale, hipStream_t stream) {
   if (!valid_stream_call(plan) || !d_in || !d_out || batch < 1 || !std::isfinite(scale)) return GA_EINVAL;

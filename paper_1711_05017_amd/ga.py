@@ -34,6 +34,7 @@ EXPORTS = [
     "ga_server_create", "ga_server_destroy", "ga_pair_register", "ga_pair_release", "ga_submit", "ga_poll",
     "ga_server_get_stats", "ga_batch_create", "ga_batch_launch", "ga_batch_destroy",
     "ga_plan_autotune", "ga_plan_set_tuning", "ga_plan_get_tuning", "ga_lowpass",
+    "ga_spectral_rotate",
 ]
 GA_K_SPLAT, GA_K_PLANE_FWD, GA_K_STRIP, GA_K_PLANE_INV, GA_K_READOUT, GA_K_BIN = 0, 1, 2, 3, 4, 5
 KERNEL_KINDS = {"splat": 0, "plane_fwd": 1, "strip": 2, "plane_inv": 3, "readout": 4, "bin": 5}
@@ -99,6 +100,7 @@ _SIGS = {
                                    ctypes.POINTER(ctypes.c_uint64)]),
     "ga_poll": (ctypes.c_int32, [_vp, ctypes.c_uint64, ctypes.POINTER(Result)]),
     "ga_server_get_stats": (ctypes.c_int32, [_vp, ctypes.POINTER(ServerStats)]),
+    "ga_spectral_rotate": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp]),
     "ga_lowpass": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_uint32, _vp, _vp, ctypes.c_int32, ctypes.c_float,
                                     _vp]),
     "ga_plan_autotune": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, _vp, ctypes.c_size_t, _vp,
@@ -388,6 +390,24 @@ def ga_pose_local(plan: Plan, FA4: torch.Tensor, xyzr: torch.Tensor, w: torch.Te
     st = load().ga_pose_local(plan.handle, _ptr(FA4), _ptr(xyzr), _ptr(w), m, _ptr(R), _host_f32(c, 3), float(sigma),
                               _ptr(t), n_poses, _ptr(out), _ptr(work), int(work.numel()), _stream(stream))
     _check("ga_pose_local", st)
+    return out
+
+
+def ga_spectral_rotate(plan: Plan, X: torch.Tensor, R: torch.Tensor, out: Optional[torch.Tensor] = None,
+                       stream=None) -> torch.Tensor:
+    """Spectra of the part rotated by each R (trilinear interpolation at
+    R^T omega). X: [channels, n, n, n/2+1] with channels 1 or 4; R: [batch, 9]
+    (or [batch, 3, 3]); returns [batch, channels, n, n, n/2+1]."""
+    n = plan.n
+    ch = X.shape[0] if X.dim() == 4 else 1
+    _need(X, torch.complex64, ch * _spec_elems(n), "X", exact=True)
+    batch = int(R.shape[0])
+    _need(R, torch.float32, 9 * batch, "R", exact=True)
+    if out is None:
+        out = torch.empty((batch, ch, n, n, n // 2 + 1), dtype=torch.complex64, device=X.device)
+    _need(out, torch.complex64, batch * ch * _spec_elems(n), "out")
+    _check("ga_spectral_rotate", load().ga_spectral_rotate(plan.handle, _ptr(X), ch, _ptr(R), batch, _ptr(out),
+                                                           _stream(stream)))
     return out
 
 
