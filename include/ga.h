@@ -224,6 +224,25 @@ ga_status ga_pose_local(const ga_plan* plan, const float* d_FA4, const float* d_
                         float* d_out7, void* d_work, size_t work_bytes, hipStream_t stream);
 
 /*
+ * Field tables for motion restricted to a set of orientations (Sec. 4.3:
+ * with the orientation fixed the correlation is precomputed once and read
+ * at every frame). ga_field_table writes, for each orientation o, the 7
+ * fields (E, F_x, F_y, F_z, tau_x, tau_y, tau_z over all translations, as
+ * ga_force_torque GA_FIELDS) to d_tables + o * 7 * n^3 (float32 [o][7][x][y][z],
+ * 28 n^3 bytes per orientation). d_Bhat4: n_orient x 4 half spectra of the
+ * moving part at each orientation (ga_splat + ga_fft3d, or
+ * ga_spectral_rotate); workspace 7 * n^2 (n/2+1) * 8 bytes.
+ * ga_field_table_query reads query q's fields trilinearly at d_t[q]
+ * (periodic, voxel units) in the table of orientation d_orient[q] (int32,
+ * device): d_out7 = n_q x 7. An orientation index outside [0, n_orient)
+ * gives NaN for that query. Errors: GA_EINVAL, GA_ENOMEM (workspace).
+ */
+ga_status ga_field_table(const ga_plan* plan, const float* d_Ahat, const float* d_Bhat4, int32_t n_orient,
+                         float* d_tables, void* d_work, size_t work_bytes, hipStream_t stream);
+ga_status ga_field_table_query(const ga_plan* plan, const float* d_tables, int32_t n_orient, const int32_t* d_orient,
+                               const float* d_t, int32_t n_q, float* d_out7, hipStream_t stream);
+
+/*
  * Spectral rotation (Sec. 3.2, step 1): instead of re-splatting the rotated
  * part, its resident spectra are interpolated trilinearly over the rotated
  * frequency grid: out_b(k) = X(R_b^T kappa(k)), kappa the signed frequency

@@ -22,6 +22,8 @@ from .ga import (  # noqa: F401
     ga_correlate,
     ga_energy_fields,
     ga_fft3d,
+    ga_field_table,
+    ga_field_table_query,
     ga_field_grad,
     ga_force_torque,
     ga_lowpass,

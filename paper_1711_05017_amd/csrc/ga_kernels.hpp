@@ -1446,6 +1446,42 @@ __global__ void k_spectral_rotate(const float2* __restrict__ in, int nch, const 
   }
 }
 
+// Queries of precomputed field tables: query q reads the 7 fields of
+// orientation orient[q] (tables + orient * 7 * n^3) trilinearly at t[q]
+// (periodic). An orientation index outside [0, n_orient) gives NaN outputs.
+__global__ void k_table_query(const float* __restrict__ tables, int n, int n_orient, const int* __restrict__ orient,
+                              const float* __restrict__ poses, int n_q, float* __restrict__ out7) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_q * 7) return;
+  const int q = i / 7, o = i % 7;
+  const int ori = orient[q];
+  if (ori < 0 || ori >= n_orient) {
+    out7[q * 7 + o] = __int_as_float(0x7fc00000);
+    return;
+  }
+  const size_t n3 = (size_t)n * n * n;
+  const float* f = tables + ((size_t)ori * 7 + o) * n3;
+  float a[3];
+  int i0[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float t = poses[q * 3 + d];
+    const float fl = floorf(t);
+    a[d] = t - fl;
+    long long m = (long long)fl % n;
+    i0[d] = (int)(m < 0 ? m + n : m);
+  }
+  float acc = 0.f;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int dx = c >> 2, dy = (c >> 1) & 1, dz = c & 1;
+    const float w = (dx ? a[0] : 1.f - a[0]) * (dy ? a[1] : 1.f - a[1]) * (dz ? a[2] : 1.f - a[2]);
+    const int ix = (i0[0] + dx) % n, iy = (i0[1] + dy) % n, iz = (i0[2] + dz) % n;
+    acc += w * f[((size_t)ix * n + iy) * n + iz];
+  }
+  out7[q * 7 + o] = acc;
+}
+
 // Low-pass filtering of half spectra (Sec. 3.3): modes with |kappa(k_a)| <=
 // L/2 - 1 on every axis are kept (times scale), the rest are dropped.
 // coarse = 1: out is [batch][L][L][L/2+1] (the kept modes on an L grid);

@@ -492,6 +492,53 @@ ga_status ga_plan_get_tuning(const ga_plan* plan, int32_t* groups, int32_t* k) {
   return GA_OK;
 }
 
+ga_status ga_field_table(const ga_plan* plan, const float* d_Ahat, const float* d_Bhat4, int32_t n_orient,
+                         float* d_tables, void* d_work, size_t work_bytes, hipStream_t stream) {
+  if (!valid_stream_call(plan) || !d_Ahat || !d_Bhat4 || !d_tables || n_orient < 1) return GA_EINVAL;
+  const int n = plan->n;
+  const size_t spec = spectrum_elems(n), n3 = (size_t)n * n * n;
+  if (!d_work || work_bytes < 7 * spec * sizeof(float2)) return GA_ENOMEM;
+  const size_t tab_b = (size_t)n_orient * 7 * n3 * sizeof(float);
+  if (overlaps(d_work, work_bytes, d_tables, tab_b) || overlaps(d_work, work_bytes, d_Ahat, spec * 8) ||
+      overlaps(d_work, work_bytes, d_Bhat4, (size_t)n_orient * 4 * spec * 8) ||
+      overlaps(d_tables, tab_b, d_Ahat, spec * 8) || overlaps(d_tables, tab_b, d_Bhat4, (size_t)n_orient * 4 * spec * 8))
+    return GA_EINVAL;
+  const float2* A = reinterpret_cast<const float2*>(d_Ahat);
+  float2* spec7 = static_cast<float2*>(d_work);
+  const float scale = (float)(1.0 / ((double)n * n * n));
+  const bool ax = axis_mode(plan);
+  for (int o = 0; o < n_orient; ++o) {
+    const float2* B4 = reinterpret_cast<const float2*>(d_Bhat4) + (size_t)o * 4 * spec;
+    float* fields7 = d_tables + (size_t)o * 7 * n3;
+    dispatch_axis(n, [&]<int N>() {
+      {
+        ProfScope ps(plan, GA_K_READOUT, stream);
+        Launch<N>::ft_fields(A, B4, spec7, plan->d_tw, stream);
+      }
+      ProfScope ps(plan, GA_K_PLANE_INV, stream);
+      if constexpr (plane_fits<N>()) {
+        if (!ax) Launch<N>::plane_inv(spec7, fields7, scale, 7, plan->d_tw, stream);
+        else Axis<N>::yz_inv(spec7, fields7, scale, 7, plan->d_tw, stream);
+      } else {
+        Axis<N>::yz_inv(spec7, fields7, scale, 7, plan->d_tw, stream);
+      }
+    });
+  }
+  return launch_status();
+}
+
+ga_status ga_field_table_query(const ga_plan* plan, const float* d_tables, int32_t n_orient, const int32_t* d_orient,
+                               const float* d_t, int32_t n_q, float* d_out7, hipStream_t stream) {
+  if (!valid_stream_call(plan) || !d_tables || n_orient < 1 || n_q < 0 || (n_q > 0 && (!d_orient || !d_t || !d_out7)))
+    return GA_EINVAL;
+  if (n_q == 0) return GA_OK;
+  const int threads = 256, total = n_q * 7;
+  ProfScope ps(plan, GA_K_READOUT, stream);
+  hipLaunchKernelGGL(k_table_query, dim3((total + threads - 1) / threads), dim3(threads), 0, stream, d_tables,
+                     plan->n, (int)n_orient, d_orient, d_t, (int)n_q, d_out7);
+  return launch_status();
+}
+
 ga_status ga_spectral_rotate(const ga_plan* plan, const float* d_in, int32_t channels, const float* d_R, int32_t batch,
                              float* d_out, hipStream_t stream) {
   if (!valid_stream_call(plan) || !d_in || !d_R || !d_out || batch < 1 || (channels != 1 && channels != 4))

@@ -34,7 +34,7 @@ EXPORTS = [
     "ga_server_create", "ga_server_destroy", "ga_pair_register", "ga_pair_release", "ga_submit", "ga_poll",
     "ga_server_get_stats", "ga_batch_create", "ga_batch_launch", "ga_batch_destroy",
     "ga_plan_autotune", "ga_plan_set_tuning", "ga_plan_get_tuning", "ga_lowpass",
-    "ga_spectral_rotate",
+    "ga_spectral_rotate", "ga_field_table", "ga_field_table_query",
 ]
 GA_K_SPLAT, GA_K_PLANE_FWD, GA_K_STRIP, GA_K_PLANE_INV, GA_K_READOUT, GA_K_BIN = 0, 1, 2, 3, 4, 5
 KERNEL_KINDS = {"splat": 0, "plane_fwd": 1, "strip": 2, "plane_inv": 3, "readout": 4, "bin": 5}
@@ -100,6 +100,8 @@ _SIGS = {
                                    ctypes.POINTER(ctypes.c_uint64)]),
     "ga_poll": (ctypes.c_int32, [_vp, ctypes.c_uint64, ctypes.POINTER(Result)]),
     "ga_server_get_stats": (ctypes.c_int32, [_vp, ctypes.POINTER(ServerStats)]),
+    "ga_field_table": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int32, _vp, _vp, ctypes.c_size_t, _vp]),
+    "ga_field_table_query": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32, _vp, _vp]),
     "ga_spectral_rotate": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp]),
     "ga_lowpass": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_uint32, _vp, _vp, ctypes.c_int32, ctypes.c_float,
                                     _vp]),
@@ -390,6 +392,40 @@ def ga_pose_local(plan: Plan, FA4: torch.Tensor, xyzr: torch.Tensor, w: torch.Te
     st = load().ga_pose_local(plan.handle, _ptr(FA4), _ptr(xyzr), _ptr(w), m, _ptr(R), _host_f32(c, 3), float(sigma),
                               _ptr(t), n_poses, _ptr(out), _ptr(work), int(work.numel()), _stream(stream))
     _check("ga_pose_local", st)
+    return out
+
+
+def ga_field_table(plan: Plan, Ahat: torch.Tensor, Bhat4: torch.Tensor, out: Optional[torch.Tensor] = None,
+                   work: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """The 7 fields per orientation: Bhat4 [n_orient, 4, n, n, n/2+1] (or
+    [4, ...] for one) -> tables [n_orient, 7, n, n, n]."""
+    n = plan.n
+    n_orient = Bhat4.shape[0] if Bhat4.dim() == 5 else 1
+    _need(Ahat, torch.complex64, _spec_elems(n), "Ahat")
+    _need(Bhat4, torch.complex64, n_orient * 4 * _spec_elems(n), "Bhat4", exact=True)
+    if out is None:
+        out = torch.empty((n_orient, 7, n, n, n), dtype=torch.float32, device=Bhat4.device)
+    _need(out, torch.float32, n_orient * 7 * n ** 3, "out")
+    if work is None:
+        work = torch.empty(7 * _spec_elems(n) * 8, dtype=torch.uint8, device=Bhat4.device)
+    _check("ga_field_table", load().ga_field_table(plan.handle, _ptr(Ahat), _ptr(Bhat4), n_orient, _ptr(out),
+                                                   _ptr(work), int(work.numel()), _stream(stream)))
+    return out
+
+
+def ga_field_table_query(plan: Plan, tables: torch.Tensor, orient: torch.Tensor, t: torch.Tensor,
+                         out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    n = plan.n
+    n_orient = int(tables.shape[0])
+    _need(tables, torch.float32, n_orient * 7 * n ** 3, "tables", exact=True)
+    n_q = int(t.shape[0])
+    _need(t, torch.float32, 3 * n_q, "t", exact=True)
+    _need(orient, torch.int32, n_q, "orient", exact=True)
+    if out is None:
+        out = torch.empty((n_q, 7), dtype=torch.float32, device=t.device)
+    _need(out, torch.float32, 7 * n_q, "out")
+    _check("ga_field_table_query", load().ga_field_table_query(plan.handle, _ptr(tables), n_orient, _ptr(orient),
+                                                               _ptr(t), n_q, _ptr(out), _stream(stream)))
     return out
 
 

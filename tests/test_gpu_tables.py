@@ -1,0 +1,63 @@
+"""GPU parity of field tables for restricted orientations (Sec. 4.3): the 7
+fields per orientation against the oracle's, read at lattice and fractional
+translations by queries that mix orientations."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+FIELD_TOL = 1e-5
+FORCE_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def G():
+    import paper_1711_05017_amd as pkg
+
+    pkg.lib()
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    return pkg
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def test_field_tables_match_oracle(G):
+    n = 32
+    A = synth.random_part(4000, n, 200, 1.0, 3.0, conf_radius=n / 4)
+    B = synth.random_part(4001, n, 120, 1.0, 3.0, conf_radius=n / 6)
+    cB = B.ref_point()
+    rots = np.stack([np.eye(3, dtype=np.float32), *synth.shoemake_rotations(4002, 2)]).astype(np.float32)
+    plan = G.Plan(n, max_batch=4)
+    Ahat = G.ga_fft3d(plan, G.GA_R2C, G.ga_splat(plan, _dev(A.xyzr), _dev(A.w)))[0].contiguous()
+    B4 = torch.stack([G.ga_fft3d(plan, G.GA_R2C, G.ga_splat(plan, _dev(B.xyzr), _dev(B.w), R=R, c=cB, channels=4))
+                      for R in rots]).contiguous()
+    tables = G.ga_field_table(plan, Ahat, B4)
+    assert tables.shape == (3, 7, n, n, n)
+    fields = []
+    for R in rots:
+        d = O.pair_fields(A.xyzr, A.w, B.xyzr, B.w, R, cB, n)
+        fields.append(np.concatenate([d["E"][None], d["F"], d["tau"]]))
+    for o in range(3):
+        assert O.rel_l2(tables[o, 0].cpu().numpy(), fields[o][0]) < FIELD_TOL
+        assert O.rel_l2(tables[o, 1:4].cpu().numpy(), fields[o][1:4]) < FORCE_TOL
+        assert O.rel_l2(tables[o, 4:7].cpu().numpy(), fields[o][4:7]) < FORCE_TOL
+    rng = np.random.default_rng(5)
+    nq = 60
+    orient = rng.integers(0, 3, nq).astype(np.int32)
+    t = (n / 2 + rng.uniform(-6, 6, (nq, 3))).astype(np.float32)
+    t[:20] = np.round(t[:20])
+    got = G.ga_field_table_query(plan, tables, _dev(orient), _dev(t)).cpu().numpy()
+    ref = np.stack([O.trilinear_read(fields[o], t[q:q + 1])[:, 0] for q, o in enumerate(orient)])
+    assert O.rel_l2(got[:, 0], ref[:, 0]) < FIELD_TOL
+    assert O.rel_l2(got[:, 1:4], ref[:, 1:4]) < FORCE_TOL
+    assert O.rel_l2(got[:, 4:7], ref[:, 4:7]) < FORCE_TOL
+    bad = G.ga_field_table_query(plan, tables, _dev(np.array([-1, 3, 1], np.int32)), _dev(t[:3])).cpu().numpy()
+    assert np.all(np.isnan(bad[:2])) and np.all(np.isfinite(bad[2]))
