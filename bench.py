@@ -340,7 +340,9 @@ def main():
         "path_GBps_algorithmic": round(step_bytes * args.steps / wall / 1e9, 1),
         "kernel_ms": {k: round(v, 4) for k, v in kern.items()},
         "autotune": {"strip_groups": tuned[0], "members_per_workgroup": tuned[1],
-                     "candidates_us": {f"{g}x{k}": v for (g, k), v in tune_us.items()}},
+                     "xcd_aware_grid": tuned[2] == 1,
+                     "candidates_us": {f"{'xcd' if x == 1 else 'plain'}/{g}x{k}": v
+                                       for (g, k, x), v in tune_us.items()}},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": counter_traffic(dom),
                      "algorithmic_bytes_per_launch": abytes[dom]},

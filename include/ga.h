@@ -283,23 +283,26 @@ ga_status ga_lowpass(const ga_plan* plan, int32_t L, uint32_t mode, const float*
 /*
  * Autotuning of the fused correlation pass of ga_energy_fields (the x
  * transform, product with the shared stationary spectrum and inverse x
- * transform): candidates are the strip width (4 or 8 groups of transforms per
- * wavefront, i.e. 4 or 8 wavefronts per workgroup) and the number of batch
- * members a workgroup takes in turn while keeping its stationary-spectrum
- * elements in registers (1, 2, 4, 8). Each candidate runs once plus three
- * timed times on d_work (zeroed first; at least batch * n^2 (n/2+1) * 8
- * bytes, the first part of a GA_OP_ENERGY workspace) against d_Ahat; the
- * fastest is kept in the plan and used by later ga_energy_fields calls. The
- * call synchronises `stream`. h_us (may be null when n_us = 0) receives up to
- * n_us per-launch times in microseconds, in the order (4,1) (4,2) (4,4) (4,8)
- * (8,1) (8,2) (8,4) (8,8). ga_plan_set_tuning restores a stored choice
- * (0 = default: 4 groups, 4 members); ga_plan_get_tuning reports the one in
- * use. Not for graph capture.
+ * transform). Candidates: the strip width (groups = 4 or 8 groups of
+ * transforms per wavefront, i.e. 4 or 8 wavefronts per workgroup), the
+ * number of batch members k a workgroup takes in turn while keeping its
+ * stationary-spectrum elements in registers (1, 2, 4, 8), and the grid
+ * mapping xcd: 1 = XCD-aware (the member groups of one strip run back to
+ * back on one XCD, whose L2 then serves the shared spectrum), 2 = plain.
+ * Each candidate runs once plus three timed times on d_work (zeroed first;
+ * at least batch * n^2 (n/2+1) * 8 bytes, the first part of a GA_OP_ENERGY
+ * workspace) against d_Ahat; the fastest is kept in the plan and used by
+ * later ga_energy_fields calls. The call synchronises `stream`. h_us (may be
+ * null when n_us = 0) receives up to n_us per-launch times in microseconds,
+ * in the order xcd (1, 2) x groups (4, 8) x k (1, 2, 4, 8), k fastest.
+ * ga_plan_set_tuning restores a stored choice (0 = default: 4 groups, 4
+ * members, plain grid); ga_plan_get_tuning reports the one in use. Not for
+ * graph capture.
  */
 ga_status ga_plan_autotune(ga_plan* plan, const float* d_Ahat, int32_t batch, void* d_work, size_t work_bytes,
                            hipStream_t stream, float* h_us, int32_t n_us);
-ga_status ga_plan_set_tuning(ga_plan* plan, int32_t groups, int32_t k);
-ga_status ga_plan_get_tuning(const ga_plan* plan, int32_t* groups, int32_t* k);
+ga_status ga_plan_set_tuning(ga_plan* plan, int32_t groups, int32_t k, int32_t xcd);
+ga_status ga_plan_get_tuning(const ga_plan* plan, int32_t* groups, int32_t* k, int32_t* xcd);
 
 /*
  * Batched execution as one graph launch (Sec. 3.2: the energy field of many

@@ -794,16 +794,29 @@ __global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_fft(const floa
 // thread keeps its elements of A in registers, so A is read once per K
 // members. B and out may be the same buffer (the fused path works in place),
 // so neither is declared __restrict__.
+// xcd_m > 0 selects a one-dimensional, XCD-aware grid: workgroups are
+// dispatched round-robin over the 8 XCDs (each with its own L2), so
+// workgroup id runs on XCD id % 8; the xcd_m member groups of one strip are
+// given consecutive ids on the same XCD (strip (id / 8 / xcd_m) * 8 + id % 8,
+// group (id / 8) % xcd_m), and the strip of A they share stays in that L2.
 template <int N, int G, bool FWD, int K = 1>
 __global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_corr(const float2* __restrict__ A, long long a_stride,
                                                                      const float2* B, float2* out, int batch,
-                                                                     const float2* __restrict__ table) {
+                                                                     int xcd_m, const float2* __restrict__ table) {
   using T = Strip<N, G>;
   constexpr int IT = (N * G + T::THREADS - 1) / T::THREADS;  // strip elements per thread
+  constexpr int NSTRIPS = (T::C + G - 1) / G;
+  int sx = blockIdx.x, my = blockIdx.y;
+  if (xcd_m > 0) {
+    const int slot = (int)(blockIdx.x >> 3);
+    my = slot % xcd_m;
+    sx = (slot / xcd_m) * 8 + (int)(blockIdx.x & 7);
+    if (sx >= NSTRIPS) return;  // whole workgroup
+  }
   __shared__ float2 S[T::SIZE];
   Twiddles<N> tw;
   load_twiddles<N>(tw, table, (threadIdx.x & 63) % T::L);
-  const int c0 = blockIdx.x * G;
+  const int c0 = sx * G;
   auto a_at = [&](const float2* Ab, int i) {
     const int x = i / G, c = c0 + i % G;
     return (c < T::C) ? Ab[(size_t)x * T::C + c] : make_float2(0.f, 0.f);
@@ -818,7 +831,7 @@ __global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_corr(const flo
   }
 #pragma unroll 1
   for (int kk = 0; kk < K; ++kk) {
-    const int b = blockIdx.y * K + kk;
+    const int b = my * K + kk;
     if (b >= batch) break;  // uniform over the workgroup
     const size_t boff = (size_t)b * N * T::C;
     const float2* Ab = A + (size_t)b * (size_t)a_stride;

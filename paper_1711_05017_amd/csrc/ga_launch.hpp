@@ -29,9 +29,11 @@ struct ga_plan {
   mutable double prof_ms[GA_K_COUNT] = {};
   mutable long long prof_count[GA_K_COUNT] = {};
   // fused x pass of ga_energy_fields: strip width in transform groups (4 or
-  // 8) and batch members per workgroup (1, 2, 4, 8); 0 = default
+  // 8), batch members per workgroup (1, 2, 4, 8) and the XCD-aware grid
+  // (1 on, 2 off); 0 = default (4, 4, off)
   int tune_groups = 0;
   int tune_k = 0;
+  int tune_xcd = 0;
 };
 
 namespace ga_detail {
@@ -129,46 +131,51 @@ template <int N> struct Launch {
   // both per plan.
   static constexpr int kCorrK = 4;
   template <int GG, int K>
-  static void corr_fwd(const float2* A, long long a_stride, float2* buf, int batch, const float2* tw, hipStream_t s) {
+  static void corr_fwd(const float2* A, long long a_stride, float2* buf, int batch, bool xcd, const float2* tw,
+                       hipStream_t s) {
     using TT = Strip<N, GG>;
-    const int ns = (TT::C + GG - 1) / GG;
-    hipLaunchKernelGGL((k_strip_corr<N, GG, true, K>), dim3(ns, (batch + K - 1) / K), dim3(TT::THREADS), 0, s, A,
-                       a_stride, buf, buf, batch, tw);
+    const int ns = (TT::C + GG - 1) / GG, m = (batch + K - 1) / K;
+    if (xcd)
+      hipLaunchKernelGGL((k_strip_corr<N, GG, true, K>), dim3((unsigned)(((ns + 7) / 8) * 8 * m)), dim3(TT::THREADS), 0,
+                         s, A, a_stride, buf, buf, batch, m, tw);
+    else
+      hipLaunchKernelGGL((k_strip_corr<N, GG, true, K>), dim3(ns, m), dim3(TT::THREADS), 0, s, A, a_stride, buf, buf,
+                         batch, 0, tw);
   }
   template <int GG>
-  static void corr_fwd_k(int k, const float2* A, long long a_stride, float2* buf, int batch, const float2* tw,
-                         hipStream_t s) {
+  static void corr_fwd_k(int k, const float2* A, long long a_stride, float2* buf, int batch, bool xcd,
+                         const float2* tw, hipStream_t s) {
     switch (k) {
-      case 1: corr_fwd<GG, 1>(A, a_stride, buf, batch, tw, s); break;
-      case 2: corr_fwd<GG, 2>(A, a_stride, buf, batch, tw, s); break;
-      case 8: corr_fwd<GG, 8>(A, a_stride, buf, batch, tw, s); break;
-      default: corr_fwd<GG, 4>(A, a_stride, buf, batch, tw, s); break;
+      case 1: corr_fwd<GG, 1>(A, a_stride, buf, batch, xcd, tw, s); break;
+      case 2: corr_fwd<GG, 2>(A, a_stride, buf, batch, xcd, tw, s); break;
+      case 8: corr_fwd<GG, 8>(A, a_stride, buf, batch, xcd, tw, s); break;
+      default: corr_fwd<GG, 4>(A, a_stride, buf, batch, xcd, tw, s); break;
     }
   }
   // groups in {4, 8}, k in {1, 2, 4, 8}; k > 1 only with a shared spectrum.
   // Above 256 (few transforms per wavefront, large register footprint) the
   // strip keeps its default width and one member per workgroup.
   static constexpr bool kTunable = N <= 256 && 4 * ffts_per_wave<N>() >= 16;
-  static void corr_fwd_tuned(int groups, int k, const float2* A, long long a_stride, float2* buf, int batch,
+  static void corr_fwd_tuned(int groups, int k, bool xcd, const float2* A, long long a_stride, float2* buf, int batch,
                              const float2* tw, hipStream_t s) {
     if (a_stride != 0 || batch == 1) k = 1;
     if constexpr (!kTunable) {
-      corr_fwd<G, 1>(A, a_stride, buf, batch, tw, s);
+      corr_fwd<G, 1>(A, a_stride, buf, batch, xcd, tw, s);
     } else {
-      if (groups == 8) corr_fwd_k<8 * ffts_per_wave<N>()>(k, A, a_stride, buf, batch, tw, s);
-      else corr_fwd_k<4 * ffts_per_wave<N>()>(k, A, a_stride, buf, batch, tw, s);
+      if (groups == 8) corr_fwd_k<8 * ffts_per_wave<N>()>(k, A, a_stride, buf, batch, xcd, tw, s);
+      else corr_fwd_k<4 * ffts_per_wave<N>()>(k, A, a_stride, buf, batch, xcd, tw, s);
     }
   }
   static void strip_corr(bool fwd, const float2* A, long long a_stride, const float2* B, float2* out, int batch,
                          const float2* tw, hipStream_t s) {
     if (fwd && B == out) {
-      corr_fwd_tuned(4, kCorrK, A, a_stride, out, batch, tw, s);
+      corr_fwd_tuned(4, kCorrK, false, A, a_stride, out, batch, tw, s);
     } else if (fwd) {
       hipLaunchKernelGGL((k_strip_corr<N, G, true, 1>), dim3(nstrips(), batch), dim3(T::THREADS), 0, s, A, a_stride, B,
-                         out, batch, tw);
+                         out, batch, 0, tw);
     } else {
       hipLaunchKernelGGL((k_strip_corr<N, G, false, 1>), dim3(nstrips(), batch), dim3(T::THREADS), 0, s, A, a_stride,
-                         B, out, batch, tw);
+                         B, out, batch, 0, tw);
     }
   }
   static void ft_fields(const float2* A, const float2* B4, float2* out7, const float2* tw, hipStream_t s) {

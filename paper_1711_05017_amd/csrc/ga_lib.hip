@@ -267,7 +267,8 @@ ga_status ga_energy_fields(const ga_plan* plan, const float* d_Ahat, const float
       }
       {
         ProfScope ps(plan, GA_K_STRIP, stream);
-        Launch<N>::corr_fwd_tuned(groups, k, reinterpret_cast<const float2*>(d_Ahat), 0, tmp, batch, plan->d_tw,
+        Launch<N>::corr_fwd_tuned(groups, k, plan->tune_xcd == 1, reinterpret_cast<const float2*>(d_Ahat), 0, tmp,
+                                  batch, plan->d_tw,
                                   stream);
       }
       ProfScope ps(plan, GA_K_PLANE_INV, stream);
@@ -295,7 +296,7 @@ ga_status ga_energy_fields(const ga_plan* plan, const float* d_Ahat, const float
     }
     {
       ProfScope ps(plan, GA_K_STRIP, stream);
-      Launch<N>::corr_fwd_tuned(groups, plan->tune_k ? plan->tune_k : Launch<N>::kCorrK,
+      Launch<N>::corr_fwd_tuned(groups, plan->tune_k ? plan->tune_k : Launch<N>::kCorrK, plan->tune_xcd == 1,
                                 reinterpret_cast<const float2*>(d_Ahat), 0, tmp, batch, plan->d_tw, stream);
     }
     ProfScope ps(plan, GA_K_PLANE_INV, stream);
@@ -437,16 +438,18 @@ ga_status ga_plan_autotune(ga_plan* plan, const float* d_Ahat, int32_t batch, vo
     if (e0) (void)hipEventDestroy(e0);
     return GA_EDEVICE;
   }
-  static constexpr int kGroups[2] = {4, 8}, kKs[4] = {1, 2, 4, 8};
+  static constexpr int kGroups[2] = {4, 8}, kKs[4] = {1, 2, 4, 8}, kX[2] = {1, 2};
   float best = 0.f;
-  int best_g = 4, best_k = 4, idx = 0;
+  int best_g = 4, best_k = 4, best_x = 1, idx = 0;
   ga_status st = GA_OK;
+  for (int xi = 0; xi < 2 && st == GA_OK; ++xi)
   for (int gi = 0; gi < 2 && st == GA_OK; ++gi) {
     for (int ki = 0; ki < 4 && st == GA_OK; ++ki, ++idx) {
-      const int g = kGroups[gi], k = kKs[ki];
+      const int g = kGroups[gi], k = kKs[ki], x = kX[xi];
       auto run = [&]() {
         dispatch_axis(n, [&]<int N>() {
-          Launch<N>::corr_fwd_tuned(g, k, reinterpret_cast<const float2*>(d_Ahat), 0, tmp, batch, plan->d_tw, stream);
+          Launch<N>::corr_fwd_tuned(g, k, x == 1, reinterpret_cast<const float2*>(d_Ahat), 0, tmp, batch, plan->d_tw,
+                                    stream);
         });
       };
       run();  // warm-up
@@ -464,6 +467,7 @@ ga_status ga_plan_autotune(ga_plan* plan, const float* d_Ahat, int32_t batch, vo
         best = us;
         best_g = g;
         best_k = k;
+        best_x = x;
       }
     }
   }
@@ -474,21 +478,25 @@ ga_status ga_plan_autotune(ga_plan* plan, const float* d_Ahat, int32_t batch, vo
   if (st != GA_OK) return st;
   plan->tune_groups = best_g;
   plan->tune_k = best_k;
+  plan->tune_xcd = best_x;
   return GA_OK;
 }
 
-ga_status ga_plan_set_tuning(ga_plan* plan, int32_t groups, int32_t k) {
-  if (!plan || !(groups == 0 || groups == 4 || groups == 8) || !(k == 0 || k == 1 || k == 2 || k == 4 || k == 8))
+ga_status ga_plan_set_tuning(ga_plan* plan, int32_t groups, int32_t k, int32_t xcd) {
+  if (!plan || !(groups == 0 || groups == 4 || groups == 8) || !(k == 0 || k == 1 || k == 2 || k == 4 || k == 8) ||
+      !(xcd == 0 || xcd == 1 || xcd == 2))
     return GA_EINVAL;
   plan->tune_groups = groups;
   plan->tune_k = k;
+  plan->tune_xcd = xcd;
   return GA_OK;
 }
 
-ga_status ga_plan_get_tuning(const ga_plan* plan, int32_t* groups, int32_t* k) {
-  if (!plan || !groups || !k) return GA_EINVAL;
+ga_status ga_plan_get_tuning(const ga_plan* plan, int32_t* groups, int32_t* k, int32_t* xcd) {
+  if (!plan || !groups || !k || !xcd) return GA_EINVAL;
   *groups = plan->tune_groups ? plan->tune_groups : 4;
   *k = plan->tune_k ? plan->tune_k : 4;
+  *xcd = plan->tune_xcd ? plan->tune_xcd : 2;
   return GA_OK;
 }
 

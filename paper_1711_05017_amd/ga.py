@@ -107,8 +107,9 @@ _SIGS = {
                                     _vp]),
     "ga_plan_autotune": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, _vp, ctypes.c_size_t, _vp,
                                           ctypes.POINTER(ctypes.c_float), ctypes.c_int32]),
-    "ga_plan_set_tuning": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int32]),
-    "ga_plan_get_tuning": (ctypes.c_int32, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "ga_plan_set_tuning": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "ga_plan_get_tuning": (ctypes.c_int32, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_int32)]),
     "ga_batch_create": (ctypes.c_int32, [ctypes.POINTER(_vp), ctypes.POINTER(BatchItem), ctypes.c_int32]),
     "ga_batch_launch": (ctypes.c_int32, [_vp, _vp]),
     "ga_batch_destroy": (ctypes.c_int32, [_vp]),
@@ -217,26 +218,29 @@ class Plan:
         nbytes = load().ga_workspace_size(self._h, op, batch, n_items)
         return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device or "cuda")
 
-    TUNE_CANDIDATES = [(g, k) for g in (4, 8) for k in (1, 2, 4, 8)]
+    TUNE_CANDIDATES = [(g, k, x) for x in (1, 2) for g in (4, 8) for k in (1, 2, 4, 8)]
 
     def autotune(self, Ahat: torch.Tensor, batch: int, work: Optional[torch.Tensor] = None, stream=None):
-        """Time the fused x-pass candidates (groups, members per workgroup) and
-        keep the fastest; returns (choice, {candidate: microseconds})."""
+        """Time the fused x-pass candidates (groups, members per workgroup,
+        XCD-aware grid 1 / plain 2) and keep the fastest; returns (choice,
+        {candidate: microseconds})."""
         _need(Ahat, torch.complex64, _spec_elems(self.n), "Ahat")
         if work is None:
             work = torch.empty(int(batch) * _spec_elems(self.n) * 8, dtype=torch.uint8, device=Ahat.device)
-        us = (ctypes.c_float * 8)()
+        nc = len(self.TUNE_CANDIDATES)
+        us = (ctypes.c_float * nc)()
         _check("ga_plan_autotune", load().ga_plan_autotune(self._h, _ptr(Ahat), int(batch), _ptr(work),
-                                                           int(work.numel()), _stream(stream), us, 8))
+                                                           int(work.numel()), _stream(stream), us, nc))
         return self.tuning(), {c: round(us[i], 2) for i, c in enumerate(self.TUNE_CANDIDATES)}
 
-    def set_tuning(self, groups: int, k: int):
-        _check("ga_plan_set_tuning", load().ga_plan_set_tuning(self._h, int(groups), int(k)))
+    def set_tuning(self, groups: int, k: int, xcd: int = 0):
+        _check("ga_plan_set_tuning", load().ga_plan_set_tuning(self._h, int(groups), int(k), int(xcd)))
 
     def tuning(self):
-        g, k = ctypes.c_int32(), ctypes.c_int32()
-        _check("ga_plan_get_tuning", load().ga_plan_get_tuning(self._h, ctypes.byref(g), ctypes.byref(k)))
-        return g.value, k.value
+        g, k, x = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check("ga_plan_get_tuning", load().ga_plan_get_tuning(self._h, ctypes.byref(g), ctypes.byref(k),
+                                                               ctypes.byref(x)))
+        return g.value, k.value, x.value
 
     def profile(self, enable: bool = True):
         """Start (and clear) or stop per-kernel event timing."""

@@ -373,17 +373,19 @@ def test_every_tuning_candidate_matches_oracle(G, n, npts, nrot):
     Ahat = G.ga_fft3d(plan, G.GA_R2C, G.ga_splat(plan, _dev(A.xyzr), _dev(A.w)))[0].contiguous()
     refs = [O.pair_fields(A.xyzr, A.w, B.xyzr, B.w, rots[r], cB, n, want_torque=False)["E"] for r in range(nrot)]
     R = _dev(rots.reshape(nrot, 9).astype(np.float32))
-    for g, k in G.Plan.TUNE_CANDIDATES:
-        plan.set_tuning(g, k)
-        assert plan.tuning() == (g, k)
+    for g, k, x in G.Plan.TUNE_CANDIDATES:
+        plan.set_tuning(g, k, x)
+        assert plan.tuning() == (g, k, x)
         E = G.ga_energy_fields(plan, Ahat, _dev(B.xyzr), _dev(B.w), R, cB).cpu().numpy()
         for r in range(nrot):
             assert O.rel_l2(E[r], refs[r]) < FIELD_TOL, (g, k, r)
     choice, times = plan.autotune(Ahat, nrot)
-    assert choice in G.Plan.TUNE_CANDIDATES and len(times) == 8 and all(t > 0 for t in times.values())
+    assert choice in G.Plan.TUNE_CANDIDATES and len(times) == 16 and all(t > 0 for t in times.values())
     E = G.ga_energy_fields(plan, Ahat, _dev(B.xyzr), _dev(B.w), R, cB).cpu().numpy()
     assert O.rel_l2(E[0], refs[0]) < FIELD_TOL
     with pytest.raises(G.GaError):
         plan.set_tuning(3, 4)
     with pytest.raises(G.GaError):
         plan.set_tuning(4, 3)
+    with pytest.raises(G.GaError):
+        plan.set_tuning(4, 4, 3)
