@@ -39,6 +39,10 @@ from .core import (  # noqa: F401
     lowpass_mask,
     lowpass_coarse,
     lowpass_energy,
+    affinity_weights,
+    reflect_spectrum,
+    score_direct,
+    score_fft,
     lattice_read,
     trilinear_read,
     pair_fields,

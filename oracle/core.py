@@ -459,6 +459,47 @@ def lowpass_energy(Ahat, Bhat, L, ts):
 
 
 # ---------------------------------------------------------------------------
+# Complex affinities (Sec. 2.3: complex kernel with signed coefficients for
+# interior and exterior query points; eq. 3 and eq. 5 with the reflection of
+# the moving part, which for complex functions is not a conjugation)
+# ---------------------------------------------------------------------------
+
+def affinity_weights(exterior, penalty):
+    """Imaginary-channel weight of each skeleton sample: +lambda1 = +1 on the
+    interior skeleton, -lambda2 = -penalty on the exterior one (penalty factor
+    lambda2/lambda1). Near the skeleton the complex kernel's value is close to
+    purely imaginary with the sign of the side, so the affinity is
+    i (u_int - penalty u_ext)."""
+    exterior = np.asarray(exterior, dtype=bool)
+    return np.where(exterior, -float(penalty), 1.0)
+
+
+def reflect_spectrum(X):
+    """X(-k) on the torus: the spectrum of the reflection x(-p) (the reflection
+    commutes with the transform, eq. 4a)."""
+    n = X.shape[0]
+    neg = (-np.arange(n)) % n
+    return X[np.ix_(neg, neg, neg)]
+
+
+def score_direct(rho1, rho2, ts):
+    """f_SC(t) = sum_p rho1(p) rho2((p - t) mod N) at the given integer
+    translations: eq. 3, the convolution of rho1 with the reflection of rho2,
+    for complex affinities (no conjugate anywhere)."""
+    ts = np.asarray(np.rint(ts), dtype=np.int64).reshape(-1, 3)
+    out = np.empty(ts.shape[0], dtype=np.complex128)
+    for i, t in enumerate(ts):
+        out[i] = np.sum(rho1 * np.roll(rho2, tuple(int(v) for v in t), axis=(0, 1, 2)))
+    return out
+
+
+def score_fft(rho1, rho2, method="fft"):
+    """f_SC = IFFT(FFT(rho1)(k) FFT(rho2)(-k)) with complex transforms
+    (eq. 5: the spectrum of the reflected part is the reflected spectrum)."""
+    return ifft3(fft3(rho1, -1, method) * reflect_spectrum(fft3(rho2, -1, method)), method)
+
+
+# ---------------------------------------------------------------------------
 # Pose readout (Sec. 2.4, force/torque at the current configuration)
 # ---------------------------------------------------------------------------
 

@@ -31,8 +31,8 @@ import numpy as np
 
 # Thickness factor used by the paper for its experiments (Sec. 4, sigma = 0.5).
 SIGMA = 0.5
-# Penalty factor lambda2/lambda1 used by the paper (Sec. 4.1); the weight an
-# exterior skeleton sample would carry is -1/PENALTY.
+# Penalty factor lambda2/lambda1 used by the paper (Sec. 4.1): an interior
+# skeleton sample carries +1, an exterior one -PENALTY (complex affinities).
 PENALTY = 3.0
 
 

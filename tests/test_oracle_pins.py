@@ -588,3 +588,78 @@ def test_rel_l2_compares_complex_values():
     a = np.array([1 + 1j, 2 - 1j])
     assert O.rel_l2(a, a) == 0.0
     assert O.rel_l2(a.real + 0j, a) > 0.4
+
+
+# ---------------------------------------------------------------------------
+# Complex affinities: the score function with the reflection of the moving
+# part (eq. 3, eq. 5), and the signs of interior/exterior overlaps (Sec. 2.3)
+# ---------------------------------------------------------------------------
+
+def _complex_grid(rng, n):
+    return rng.standard_normal((n, n, n)) + 1j * rng.standard_normal((n, n, n))
+
+
+def _all_translations(n):
+    g = np.arange(n)
+    return np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+
+
+@pytest.mark.parametrize("n", [4, 6])
+def test_score_fft_equals_direct_sum_for_complex_affinities(n):
+    rng = np.random.default_rng(40 + n)
+    r1, r2 = _complex_grid(rng, n), _complex_grid(rng, n)
+    brute = O.score_direct(r1, r2, _all_translations(n)).reshape(n, n, n)
+    assert O.rel_l2(O.score_fft(r1, r2), brute) < 1e-13
+    assert O.rel_l2(O.score_fft(r1, r2, method="direct"), brute) < 1e-13
+    # conjugating the complex partner's spectrum instead of reflecting it is
+    # a different function
+    conj_route = O.ifft3(O.fft3(r1) * np.conj(O.fft3(r2)))
+    assert O.rel_l2(conj_route, brute) > 0.1
+
+
+def test_score_splits_into_real_correlations():
+    """rho = a + i b on each side: Re f = a1*a2 - b1*b2, Im f = a1*b2 + b1*a2
+    with * the real correlation, computed here by brute force."""
+    n = 6
+    rng = np.random.default_rng(7)
+    a1, b1, a2, b2 = (rng.standard_normal((n, n, n)) for _ in range(4))
+    f = O.score_fft(a1 + 1j * b1, a2 + 1j * b2)
+    C = O.correlate_brute_field
+    assert O.rel_l2(f.real, C(a1, a2) - C(b1, b2)) < 1e-13
+    assert O.rel_l2(f.imag, C(a1, b2) + C(b1, a2)) < 1e-13
+
+
+def test_score_of_real_and_imaginary_affinities():
+    """Real affinities: the reflection is the conjugate, f = the real
+    correlation. Purely imaginary ones (the skeleton reading): Re f is minus
+    the correlation of the imaginary parts and Im f vanishes."""
+    n = 8
+    rng = np.random.default_rng(9)
+    u1, u2 = rng.standard_normal((n, n, n)), rng.standard_normal((n, n, n))
+    E = O.correlate_fft(u1, u2)
+    f = O.score_fft(u1 + 0j, u2 + 0j)
+    assert O.rel_l2(f.real, E) < 1e-13 and np.abs(f.imag).max() < 1e-12 * np.abs(E).max()
+    g = O.score_fft(1j * u1, 1j * u2)
+    assert O.rel_l2(g.real, -E) < 1e-13 and np.abs(g.imag).max() < 1e-12 * np.abs(E).max()
+
+
+def test_interior_exterior_overlaps_reward_fit_and_penalise_collision():
+    """One skeleton sample per part, overlapping at t = (8, 8, 8): interior
+    against exterior scores positive, interior against interior and exterior
+    against exterior negative, the latter penalty^2 times stronger."""
+    n, pen = 16, 3.0
+    yA = np.array([[8.0, 8.0, 8.0]])
+    yB = np.zeros((1, 3))
+    r = np.array([2.0])
+    t = [[8, 8, 8]]
+
+    def rho(y, ext):
+        return 1j * O.splat(y, r, O.affinity_weights([ext], pen), n, 0.5)
+
+    s = {(ea, eb): O.score_direct(rho(yA, ea), rho(yB, eb), t)[0] for ea in (False, True) for eb in (False, True)}
+    assert s[(False, True)].real > 0 and s[(True, False)].real > 0
+    assert s[(False, False)].real < 0 and s[(True, True)].real < 0
+    assert s[(True, True)].real == pytest.approx(pen ** 2 * s[(False, False)].real, rel=1e-12)
+    assert s[(False, True)].real == pytest.approx(-pen * s[(False, False)].real, rel=1e-12)
+    assert all(abs(v.imag) < 1e-12 * abs(v.real) for v in s.values())
+    assert list(O.affinity_weights([False, True, False], pen)) == [1.0, -pen, 1.0]
