@@ -243,6 +243,68 @@ def c4_leg(G, synth, np, torch, dev, reps=3):
             "peak_device_GB": round(torch.cuda.max_memory_allocated() / 1e9, 2)}
 
 
+def next_rows_leg(G, synth, np, torch, dev, reps=20):
+    """The widened rows at 128^3 (parts of the 128^3 batched workload): low-pass
+    filtering of the 4 moving-part spectra to the 16^3 box (coarse grid and
+    zero-padded), spectral rotation of the 4 spectra by 16 rotations, the
+    complex-affinity score (Re and Im) of 16 moving parts, and 100k trilinear
+    queries of 4 orientation field tables. Average microseconds per call
+    (HIP events on the calling stream over `reps` calls) and algorithmic bytes
+    per call, with GB/s against the 8 TB/s HBM peak."""
+    a = synth.config_c3(16)
+    n, nb = a.n, 16
+    H = n * n * (n // 2 + 1)
+    plan = G.Plan(n, max_batch=nb)
+    xa, wa = torch.from_numpy(a.A.xyzr).to(dev), torch.from_numpy(a.A.w).to(dev)
+    xb, wb = torch.from_numpy(a.B.xyzr).to(dev), torch.from_numpy(a.B.w).to(dev)
+    Ahat = G.ga_fft3d(plan, G.GA_R2C, G.ga_splat(plan, xa, wa, sigma=a.sigma))[0].contiguous()
+    Bhat4 = G.ga_fft3d(plan, G.GA_R2C, G.ga_splat(plan, xb, wb, R=np.eye(3), c=a.cB, sigma=a.sigma, channels=4))
+    R = torch.from_numpy(np.ascontiguousarray(a.rotations.reshape(nb, 9))).to(dev)
+    L = 16
+    kept = (L - 1) ** 2 * (L // 2)
+    coarse_out = torch.empty((4, L, L, L // 2 + 1), dtype=torch.complex64, device=dev)
+    pad_out = torch.empty_like(Bhat4)
+    rot_out = torch.empty((nb, 4, n, n, n // 2 + 1), dtype=torch.complex64, device=dev)
+    A2 = torch.stack([Ahat, Bhat4[1]]).contiguous()
+    B2 = Bhat4[None, :2].expand(nb, 2, n, n, n // 2 + 1).contiguous()
+    score_out = torch.empty((nb, 2, n, n, n), dtype=torch.float32, device=dev)
+    score_work = plan.workspace(G.ga.GA_OP_SCORE, nb, 2, device=dev)
+    n_orient, n_q = 4, 100000
+    tables = G.ga_field_table(plan, Ahat, Bhat4[None].expand(n_orient, 4, n, n, n // 2 + 1).contiguous())
+    rng = np.random.default_rng(7)
+    orient = torch.from_numpy(rng.integers(0, n_orient, n_q).astype(np.int32)).to(dev)
+    tq = torch.from_numpy(rng.uniform(0, n, (n_q, 3)).astype(np.float32)).to(dev)
+    q_out = torch.empty((n_q, 7), dtype=torch.float32, device=dev)
+    ops = {
+        "f1_lowpass_coarse_4ch": (lambda: G.ga_lowpass(plan, Bhat4, L, G.GA_LOWPASS_COARSE, out=coarse_out),
+                                  4 * 8 * (kept + L * L * (L // 2 + 1))),
+        "f1_lowpass_zeropad_4ch": (lambda: G.ga_lowpass(plan, Bhat4, L, G.GA_LOWPASS_ZEROPAD, out=pad_out),
+                                   4 * 8 * (kept + H)),
+        "f2_spectral_rotate_4ch_x16": (lambda: G.ga_spectral_rotate(plan, Bhat4, R, out=rot_out),
+                                       4 * 8 * H + nb * 4 * 8 * H),
+        "f3_score_re_im_x16": (lambda: G.ga_score(plan, A2, B2, out=score_out, work=score_work),
+                               2 * 8 * H + nb * (2 * 8 * H + 2 * 8 * H) + nb * 2 * (8 * H + 4 * n ** 3)),
+        "f4_table_query_100k": (lambda: G.ga_field_table_query(plan, tables, orient, tq, out=q_out),
+                                n_q * (16 + 8 * 7 * 4 + 7 * 4)),
+    }
+    out = {"grid": n, "lowpass_L": L, "orientations": n_orient}
+    for name, (f, nbytes) in ops.items():
+        for _ in range(3):
+            f()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            f()
+        e1.record()
+        e1.synchronize()
+        us = e0.elapsed_time(e1) * 1000.0 / reps
+        gbps = nbytes / (us * 1e-6) / 1e9
+        out[name] = {"us": round(us, 1), "algorithmic_bytes": int(nbytes), "GBps": round(gbps, 1),
+                     "hbm_frac": round(gbps / HBM_PEAK_GBPS, 4)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,6 +315,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-c4", action="store_true")
+    ap.add_argument("--no-next", action="store_true", help="skip the low-pass / rotation / score / table leg")
     ap.add_argument("--serving-queries", type=int, default=100000)
     ap.add_argument("--serving-rate", type=float, default=16000.0)
     ap.add_argument("--serving-mode", choices=["local", "spectral"], default="local",
@@ -351,6 +414,8 @@ def main():
         out["graph"] = graph_leg(G, synth, np, torch, dev)
     if not args.no_c4:
         out["c4_512"] = c4_leg(G, synth, np, torch, dev)
+    if not args.no_next:
+        out["next_rows"] = next_rows_leg(G, synth, np, torch, dev)
     if not args.no_serving:
         out["serving"] = serving_leg(args.serving_queries, args.serving_rate, mode=args.serving_mode)
     if not args.no_cpu_baseline:

@@ -90,6 +90,7 @@ typedef int32_t ga_status;
 #define GA_OP_FORCE_SINGLE 5
 #define GA_OP_FIELD_GRAD 6
 #define GA_OP_POSE_LOCAL 7
+#define GA_OP_SCORE 8
 
 /* Plan flags. */
 #define GA_PLAN_AXIS_PASSES 1u /* separate-axis path at every grid edge */
@@ -128,7 +129,8 @@ int32_t ga_plan_n(const ga_plan* plan);
 /* Workspace bytes that operation `op` needs for `batch` fields (or poses for
  * GA_OP_POSE_LOCAL); n_items is the number of skeleton samples for
  * GA_OP_ENERGY and GA_OP_POSE_LOCAL and the number of poses for
- * GA_OP_FORCE_SINGLE (ignored otherwise). 0 for an unknown op. */
+ * GA_OP_FORCE_SINGLE, and the number of parts (1 or 2) for GA_OP_SCORE
+ * (ignored otherwise). 0 for an unknown op. */
 size_t ga_workspace_size(const ga_plan* plan, int32_t op, int32_t batch, int64_t n_items);
 
 /*
@@ -164,6 +166,30 @@ ga_status ga_fft3d(const ga_plan* plan, int32_t dir, const void* d_in, void* d_o
  */
 ga_status ga_correlate(const ga_plan* plan, const float* d_Ahat, int64_t a_stride, const float* d_Bhat,
                        int32_t batch, float* d_E, void* d_work, size_t work_bytes, hipStream_t stream);
+
+/* Parts of the complex score (ga_score). */
+#define GA_SCORE_RE 1u
+#define GA_SCORE_IM 2u
+
+/*
+ * Score function of complex affinities (Sec. 2.3: complex kernel with signed
+ * coefficients for interior and exterior query points; eq. 3 and eq. 5 with
+ * the reflection of the moving part). For rho_1 = a_1 + i b_1 and
+ * rho_2,b = a_2 + i b_2 (each channel a real density, e.g. from ga_splat
+ * with its own weights), f_b(t) = sum_p rho_1(p) rho_2,b(p - t), with no
+ * conjugate. From the half spectra of the four real channels:
+ *   Re f = C2R(A_a conj(B_a) - A_b conj(B_b)),
+ *   Im f = C2R(A_a conj(B_b) + A_b conj(B_a)).
+ * d_A2: the two half spectra (A_a, then A_b) of the stationary affinity,
+ * read with a stride of a_stride spectrum elements between batch members
+ * (0 = one pair for the whole batch). d_B2: batch x 2 half spectra (B_a,
+ * B_b). parts: GA_SCORE_RE, GA_SCORE_IM, or both (Re before Im). d_out:
+ * batch x nparts real n^3 grids. Workspace: GA_OP_SCORE with
+ * n_items = nparts. GA_EINVAL for parts outside 1..3, a negative stride or
+ * overlapping buffers; GA_ENOMEM for a short workspace.
+ */
+ga_status ga_score(const ga_plan* plan, const float* d_A2, int64_t a_stride, const float* d_B2, int32_t batch,
+                   uint32_t parts, float* d_out, void* d_work, size_t work_bytes, hipStream_t stream);
 
 /*
  * The whole field path for many rotations of the moving part in one call

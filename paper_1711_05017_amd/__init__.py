@@ -12,6 +12,8 @@ from .ga import (  # noqa: F401
     GA_LOWPASS_ZEROPAD,
     GA_PLAN_AXIS_PASSES,
     GA_R2C,
+    GA_SCORE_IM,
+    GA_SCORE_RE,
     GA_SERVE_LOCAL,
     GA_SERVE_SPECTRAL,
     GA_SINGLE,
@@ -29,6 +31,7 @@ from .ga import (  # noqa: F401
     ga_lowpass,
     ga_spectral_rotate,
     ga_pose_local,
+    ga_score,
     ga_splat,
     ga_supported_n,
 )

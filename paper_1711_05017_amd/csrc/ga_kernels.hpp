@@ -871,6 +871,49 @@ __global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_corr(const flo
   }
 }
 
+// Score function of complex affinities (eq. 3 and eq. 5 with the reflection
+// of the moving part, no conjugate): with rho = a + i b on each side and
+// A_a, A_b, B_a, B_b the half spectra of the real channels, the product
+// F{rho_1}(k) F{rho_2}(-k) splits into two Hermitian spectra,
+//   Re: A_a conj(B_a) - A_b conj(B_b),   Im: A_a conj(B_b) + A_b conj(B_a),
+// each followed here by the inverse x FFT. A2 = (A_a, A_b) at a stride of
+// a_stride elements per batch member; B2 = batch x (B_a, B_b); out = batch x
+// nparts spectra. grid = (nstrips, batch, nparts); the workgroup's part is
+// Re when blockIdx.z + first == 0, Im otherwise.
+template <int N, int G>
+__global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_score(const float2* __restrict__ A2,
+                                                                      long long a_stride,
+                                                                      const float2* __restrict__ B2,
+                                                                      float2* __restrict__ out, int first,
+                                                                      const float2* __restrict__ table) {
+  using T = Strip<N, G>;
+  __shared__ float2 S[T::SIZE];
+  Twiddles<N> tw;
+  load_twiddles<N>(tw, table, (threadIdx.x & 63) % T::L);
+  const size_t spec = (size_t)N * T::C;
+  const int b = blockIdx.y;
+  const bool re = (first + (int)blockIdx.z) == 0;
+  const float2* Aa = A2 + (size_t)b * (size_t)a_stride;
+  const float2* Ab = Aa + spec;
+  const float2* Ba = B2 + (size_t)b * 2 * spec;
+  const float2* Bb = Ba + spec;
+  const int c0 = blockIdx.x * G;
+  batched_copy<N * G, T::THREADS, float2>(
+      [&](int i) {
+        const int x = i / G, c = c0 + i % G;
+        if (c >= T::C) return make_float2(0.f, 0.f);
+        const size_t e = (size_t)x * T::C + c;
+        const float2 aa = Aa[e], ab = Ab[e], ba = Ba[e], bb = Bb[e];
+        const float2 p = cmulc(aa, re ? ba : bb), q = cmulc(ab, re ? bb : ba);
+        return re ? make_float2(p.x - q.x, p.y - q.y) : make_float2(p.x + q.x, p.y + q.y);
+      },
+      [&](int i, float2 v) { S[T::idx(i / G, i % G)] = v; });
+  __syncthreads();
+  strip_fft<N, G, +1>(S, tw);
+  __syncthreads();
+  strip_store<N, G>(S, out + ((size_t)b * gridDim.z + blockIdx.z) * spec, c0);
+}
+
 // kappa(k)/N for a half-spectrum index: k for k < N/2, k - N above, 0 at N/2.
 template <int N>
 __device__ __forceinline__ float omega_of(int k) {

@@ -178,6 +178,12 @@ template <int N> struct Launch {
                          B, out, batch, 0, tw);
     }
   }
+  // complex score: nparts = 1 or 2 product spectra per member from part `first`
+  static void strip_score(const float2* A2, long long a_stride, const float2* B2, float2* out, int batch, int first,
+                          int nparts, const float2* tw, hipStream_t s) {
+    hipLaunchKernelGGL((k_strip_score<N, G>), dim3(nstrips(), batch, nparts), dim3(T::THREADS), 0, s, A2, a_stride,
+                       B2, out, first, tw);
+  }
   static void ft_fields(const float2* A, const float2* B4, float2* out7, const float2* tw, hipStream_t s) {
     hipLaunchKernelGGL((k_strip_ft_fields<N, G>), dim3(nstrips(), 7), dim3(T::THREADS), 0, s, A, B4, out7, tw);
   }

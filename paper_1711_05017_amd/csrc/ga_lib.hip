@@ -96,6 +96,7 @@ size_t ga_workspace_size(const ga_plan* plan, int32_t op, int32_t batch, int64_t
     case GA_OP_FORCE_FIELDS: return 7 * spec + 7 * real;
     case GA_OP_FORCE_SINGLE: return (size_t)n_items * nsingle_of(n) * 7 * sizeof(double);
     case GA_OP_FIELD_GRAD: return 6 * spec + 3 * real;
+    case GA_OP_SCORE: return (n_items >= 1 && n_items <= 2) ? (size_t)batch * (size_t)n_items * spec : 0;
     case GA_OP_POSE_LOCAL:
       return (size_t)batch * sizeof(QueryItem) + (size_t)batch * nlocal_of(n_items) * 7 * sizeof(double);
     default: return 0;
@@ -229,6 +230,51 @@ ga_status ga_correlate(const ga_plan* plan, const float* d_Ahat, int64_t a_strid
     }
     ProfScope ps(plan, GA_K_PLANE_INV, stream);
     Launch<N>::plane_inv(tmp, d_E, scale, batch, plan->d_tw, stream);
+  });
+  return launch_status();
+}
+
+ga_status ga_score(const ga_plan* plan, const float* d_A2, int64_t a_stride, const float* d_B2, int32_t batch,
+                   uint32_t parts, float* d_out, void* d_work, size_t work_bytes, hipStream_t stream) {
+  if (!valid_stream_call(plan) || !d_A2 || !d_B2 || !d_out || batch < 1 || batch > plan->max_batch || a_stride < 0 ||
+      parts < 1 || parts > (GA_SCORE_RE | GA_SCORE_IM))
+    return GA_EINVAL;
+  const int nparts = (parts == (GA_SCORE_RE | GA_SCORE_IM)) ? 2 : 1;
+  const int first = (parts == GA_SCORE_IM) ? 1 : 0;
+  if (!d_work || work_bytes < ga_workspace_size(plan, GA_OP_SCORE, batch, nparts)) return GA_ENOMEM;
+  const int n = plan->n;
+  const size_t spec_e = spectrum_elems(n);
+  {
+    const size_t b_b = (size_t)batch * 2 * spec_e * sizeof(float2);
+    const size_t a_b = (size_t)((batch - 1) * a_stride + 2 * (int64_t)spec_e) * sizeof(float2);
+    const size_t out_b = (size_t)batch * nparts * n * n * n * sizeof(float);
+    if (overlaps(d_out, out_b, d_B2, b_b) || overlaps(d_out, out_b, d_A2, a_b) ||
+        overlaps(d_work, work_bytes, d_out, out_b) || overlaps(d_work, work_bytes, d_B2, b_b) ||
+        overlaps(d_work, work_bytes, d_A2, a_b))
+      return GA_EINVAL;
+  }
+  float2* tmp = static_cast<float2*>(d_work);
+  const float2* A2 = reinterpret_cast<const float2*>(d_A2);
+  const float2* B2 = reinterpret_cast<const float2*>(d_B2);
+  const float scale = (float)(1.0 / ((double)n * n * n));
+  if (axis_mode(plan)) {
+    dispatch_axis(n, [&]<int N>() {
+      {
+        ProfScope ps(plan, GA_K_STRIP, stream);
+        Launch<N>::strip_score(A2, a_stride, B2, tmp, batch, first, nparts, plan->d_tw, stream);
+      }
+      ProfScope ps(plan, GA_K_PLANE_INV, stream);
+      Axis<N>::yz_inv(tmp, d_out, scale, batch * nparts, plan->d_tw, stream);
+    });
+    return launch_status();
+  }
+  dispatch(n, [&]<int N>() {
+    {
+      ProfScope ps(plan, GA_K_STRIP, stream);
+      Launch<N>::strip_score(A2, a_stride, B2, tmp, batch, first, nparts, plan->d_tw, stream);
+    }
+    ProfScope ps(plan, GA_K_PLANE_INV, stream);
+    Launch<N>::plane_inv(tmp, d_out, scale, batch * nparts, plan->d_tw, stream);
   });
   return launch_status();
 }

@@ -21,7 +21,8 @@ GA_OK, GA_PENDING = 0, 1
 GA_R2C, GA_C2R = -1, 1
 GA_FIELDS, GA_SINGLE = 0, 1
 GA_OP_FFT_C2R, GA_OP_CORRELATE, GA_OP_ENERGY, GA_OP_FORCE_FIELDS, GA_OP_FORCE_SINGLE = 1, 2, 3, 4, 5
-GA_OP_FIELD_GRAD, GA_OP_POSE_LOCAL = 6, 7
+GA_OP_FIELD_GRAD, GA_OP_POSE_LOCAL, GA_OP_SCORE = 6, 7, 8
+GA_SCORE_RE, GA_SCORE_IM = 1, 2
 GA_SERVE_LOCAL, GA_SERVE_SPECTRAL = 0, 1
 GA_PLAN_AXIS_PASSES = 1
 GA_LOWPASS_COARSE, GA_LOWPASS_ZEROPAD = 0, 1
@@ -34,7 +35,7 @@ EXPORTS = [
     "ga_server_create", "ga_server_destroy", "ga_pair_register", "ga_pair_release", "ga_submit", "ga_poll",
     "ga_server_get_stats", "ga_batch_create", "ga_batch_launch", "ga_batch_destroy",
     "ga_plan_autotune", "ga_plan_set_tuning", "ga_plan_get_tuning", "ga_lowpass",
-    "ga_spectral_rotate", "ga_field_table", "ga_field_table_query",
+    "ga_spectral_rotate", "ga_field_table", "ga_field_table_query", "ga_score",
 ]
 GA_K_SPLAT, GA_K_PLANE_FWD, GA_K_STRIP, GA_K_PLANE_INV, GA_K_READOUT, GA_K_BIN = 0, 1, 2, 3, 4, 5
 KERNEL_KINDS = {"splat": 0, "plane_fwd": 1, "strip": 2, "plane_inv": 3, "readout": 4, "bin": 5}
@@ -82,6 +83,8 @@ _SIGS = {
     "ga_splat": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_float, ctypes.c_int32, _vp, _vp]),
     "ga_fft3d": (ctypes.c_int32, [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32, _vp, ctypes.c_size_t, _vp]),
     "ga_correlate": (ctypes.c_int32, [_vp, _vp, ctypes.c_int64, _vp, ctypes.c_int32, _vp, _vp, ctypes.c_size_t, _vp]),
+    "ga_score": (ctypes.c_int32, [_vp, _vp, ctypes.c_int64, _vp, ctypes.c_int32, ctypes.c_uint32, _vp, _vp,
+                                  ctypes.c_size_t, _vp]),
     "ga_energy_fields": (ctypes.c_int32, [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_float, ctypes.c_int32,
                                           _vp, _vp, ctypes.c_size_t, _vp]),
     "ga_force_torque": (ctypes.c_int32, [_vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_uint32, _vp, _vp, ctypes.c_size_t,
@@ -320,6 +323,31 @@ def ga_correlate(plan: Plan, Ahat: torch.Tensor, Bhat: torch.Tensor, a_stride: O
     st = load().ga_correlate(plan.handle, _ptr(Ahat), int(a_stride), _ptr(Bhat), int(batch), _ptr(out), _ptr(work),
                              int(work.numel()), _stream(stream))
     _check("ga_correlate", st)
+    return out
+
+
+def ga_score(plan: Plan, A2: torch.Tensor, B2: torch.Tensor, parts: int = GA_SCORE_RE | GA_SCORE_IM,
+             a_stride: Optional[int] = None, out: Optional[torch.Tensor] = None, work=None,
+             stream=None) -> torch.Tensor:
+    """Score of complex affinities: A2 = the 2 half spectra (real channel,
+    imaginary channel) of the stationary part, [2, n, n, n/2+1] (or one pair
+    per member, [batch, 2, ...]); B2 = [batch, 2, n, n, n/2+1]. Returns
+    [batch, nparts, n, n, n] (Re before Im)."""
+    n = plan.n
+    batch = B2.shape[0] if B2.dim() == 5 else 1
+    nparts = 2 if parts == (GA_SCORE_RE | GA_SCORE_IM) else 1
+    if a_stride is None:
+        a_stride = 0 if (A2.dim() == 4 or A2.shape[0] == 1) else 2 * _spec_elems(n)
+    _need(B2, torch.complex64, batch * 2 * _spec_elems(n), "B2", exact=True)
+    _need(A2, torch.complex64, a_stride * (batch - 1) + 2 * _spec_elems(n), "A2")
+    if out is None:
+        out = torch.empty((batch, nparts, n, n, n), dtype=torch.float32, device=B2.device)
+    _need(out, torch.float32, batch * nparts * n ** 3, "out")
+    if work is None:
+        work = plan.workspace(GA_OP_SCORE, batch, nparts, device=B2.device)
+    st = load().ga_score(plan.handle, _ptr(A2), int(a_stride), _ptr(B2), int(batch), int(parts), _ptr(out),
+                         _ptr(work), int(work.numel()), _stream(stream))
+    _check("ga_score", st)
     return out
 
 

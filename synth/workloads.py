@@ -41,7 +41,8 @@ class Part:
     """Skeleton samples of one part, in voxel units of its own grid frame."""
 
     xyzr: np.ndarray  # float32 [n, 4]: ball centre (x, y, z) and ball radius r
-    w: np.ndarray  # float32 [n]: signed weight (+1 interior skeleton)
+    w: np.ndarray  # float32 [n]: signed weight (+1 interior skeleton, -PENALTY exterior)
+    exterior: np.ndarray = None  # bool [n]: sample lies on the exterior skeleton (None: all interior)
 
     @property
     def n(self) -> int:
@@ -188,10 +189,13 @@ def config_c1() -> Assembly:
     return Assembly("C1", n, A, B, B.ref_point(), _identity(), poses)
 
 
-def config_c2(n_poses: int = 1000) -> Assembly:
+def config_c2(n_poses: int = 1000, exterior: bool = False) -> Assembly:
     """128^3 peg-in-hole: hole = 8 rods (r = 2) on a ring of radius 6.5 around
     the z axis (clearance 0.5 to the peg), peg = one axis polyline of 400
-    points (r = 4). The hole is stationary, the peg moves."""
+    points (r = 4). The hole is stationary, the peg moves. With exterior=True
+    the hole's axis is added to A as an exterior skeleton polyline (400
+    points, r = 4.5, the free radius inside the ring of rods) with weight
+    -PENALTY: the guidance "valley" that the inserted peg fills."""
     n = 128
     c = n / 2.0
     length = 48.0
@@ -202,6 +206,11 @@ def config_c2(n_poses: int = 1000) -> Assembly:
         xyz = np.stack([np.full(400, c + 6.5 * np.cos(ang)), np.full(400, c + 6.5 * np.sin(ang)), z], 1)
         rods.append(np.concatenate([xyz, np.full((400, 1), 2.0)], 1))
     A = Part(np.concatenate(rods).astype(np.float32), np.ones(3200, np.float32))
+    if exterior:
+        axis = np.stack([np.full(400, c), np.full(400, c), z, np.full(400, 6.5 - 2.0)], 1)
+        A = Part(np.concatenate([A.xyzr, axis]).astype(np.float32),
+                 np.concatenate([A.w, np.full(400, -PENALTY)]).astype(np.float32),
+                 np.concatenate([np.zeros(3200, bool), np.ones(400, bool)]))
     peg = np.stack([np.full(400, c), np.full(400, c), z, np.full(400, 4.0)], 1)
     B = Part(peg.astype(np.float32), np.ones(400, np.float32))
     rng = np.random.default_rng(np.random.PCG64(203))

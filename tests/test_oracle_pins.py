@@ -663,3 +663,29 @@ def test_interior_exterior_overlaps_reward_fit_and_penalise_collision():
     assert s[(False, True)].real == pytest.approx(-pen * s[(False, False)].real, rel=1e-12)
     assert all(abs(v.imag) < 1e-12 * abs(v.real) for v in s.values())
     assert list(O.affinity_weights([False, True, False], pen)) == [1.0, -pen, 1.0]
+
+
+def test_generator_weights_follow_the_affinity_reading():
+    a = synth.config_c2(4, exterior=True)
+    assert np.array_equal(a.A.w, O.affinity_weights(a.A.exterior, synth.PENALTY).astype(np.float32))
+
+
+def test_hole_axis_exterior_skeleton_makes_the_inserted_pose_the_unique_best_score():
+    """Peg-in-hole at 128^3 (zero-clearance kernels: the peg's balls end 0.5
+    voxel short of the rods'). With interior skeletons only, Re f is 0 on a
+    flat plateau of millions of translations around the insertion; with the
+    hole's axis as an exterior skeleton, the inserted pose (peg axis on the
+    hole axis, c_B at the centre) is the strict maximum."""
+    a = synth.config_c2(4, exterior=True)
+    n = a.n
+    yB = O.place(a.B.xyzr[:, :3], np.eye(3, dtype=np.float32), a.cB)
+    rhoB = 1j * O.splat(yB, a.B.xyzr[:, 3], a.B.w, n, a.sigma)
+    f = O.score_fft(1j * O.splat(a.A.xyzr[:, :3], a.A.xyzr[:, 3], a.A.w, n, a.sigma), rhoB).real
+    best = np.unravel_index(np.argmax(f), f.shape)
+    assert best == (64, 64, 64)
+    others = f.copy()
+    others[best] = -np.inf
+    assert f[best] > others.max() > 0
+    m = ~a.A.exterior
+    f0 = O.score_fft(1j * O.splat(a.A.xyzr[m, :3], a.A.xyzr[m, 3], a.A.w[m], n, a.sigma), rhoB).real
+    assert abs(f0[64, 64, 64]) < 1e-9 and f0.max() < 1e-9 and (f0 > -1e-9).sum() > 10 ** 6
