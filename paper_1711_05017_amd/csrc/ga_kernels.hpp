@@ -878,40 +878,77 @@ __global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_corr(const flo
 //   Re: A_a conj(B_a) - A_b conj(B_b),   Im: A_a conj(B_b) + A_b conj(B_a),
 // each followed here by the inverse x FFT. A2 = (A_a, A_b) at a stride of
 // a_stride elements per batch member; B2 = batch x (B_a, B_b); out = batch x
-// nparts spectra. grid = (nstrips, batch, nparts); the workgroup's part is
-// Re when blockIdx.z + first == 0, Im otherwise.
-template <int N, int G>
+// nparts spectra.
+// BOTH = false: grid = (nstrips, batch, nparts), one part per workgroup (Re
+// when blockIdx.z + first == 0, Im otherwise). BOTH = true: grid = (nstrips,
+// batch), a workgroup reads the four spectra once and produces Re and Im:
+// the Im products wait in registers while Re is transformed in LDS.
+template <int N, int G, bool BOTH>
 __global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_score(const float2* __restrict__ A2,
                                                                       long long a_stride,
                                                                       const float2* __restrict__ B2,
                                                                       float2* __restrict__ out, int first,
                                                                       const float2* __restrict__ table) {
   using T = Strip<N, G>;
+  constexpr int IT = (N * G + T::THREADS - 1) / T::THREADS;  // strip elements per thread
   __shared__ float2 S[T::SIZE];
   Twiddles<N> tw;
   load_twiddles<N>(tw, table, (threadIdx.x & 63) % T::L);
   const size_t spec = (size_t)N * T::C;
   const int b = blockIdx.y;
-  const bool re = (first + (int)blockIdx.z) == 0;
   const float2* Aa = A2 + (size_t)b * (size_t)a_stride;
   const float2* Ab = Aa + spec;
   const float2* Ba = B2 + (size_t)b * 2 * spec;
   const float2* Bb = Ba + spec;
   const int c0 = blockIdx.x * G;
-  batched_copy<N * G, T::THREADS, float2>(
-      [&](int i) {
-        const int x = i / G, c = c0 + i % G;
-        if (c >= T::C) return make_float2(0.f, 0.f);
+  if constexpr (BOTH) {
+    float2 ireg[IT];
+#pragma unroll
+    for (int u = 0; u < IT; ++u) {
+      const int i = threadIdx.x + u * T::THREADS;
+      const int x = i / G, c = c0 + i % G;
+      float2 re = make_float2(0.f, 0.f), im = make_float2(0.f, 0.f);
+      if (i < N * G && c < T::C) {
         const size_t e = (size_t)x * T::C + c;
         const float2 aa = Aa[e], ab = Ab[e], ba = Ba[e], bb = Bb[e];
-        const float2 p = cmulc(aa, re ? ba : bb), q = cmulc(ab, re ? bb : ba);
-        return re ? make_float2(p.x - q.x, p.y - q.y) : make_float2(p.x + q.x, p.y + q.y);
-      },
-      [&](int i, float2 v) { S[T::idx(i / G, i % G)] = v; });
-  __syncthreads();
-  strip_fft<N, G, +1>(S, tw);
-  __syncthreads();
-  strip_store<N, G>(S, out + ((size_t)b * gridDim.z + blockIdx.z) * spec, c0);
+        const float2 p = cmulc(aa, ba), q = cmulc(ab, bb), r = cmulc(aa, bb), t = cmulc(ab, ba);
+        re = make_float2(p.x - q.x, p.y - q.y);
+        im = make_float2(r.x + t.x, r.y + t.y);
+      }
+      if (i < N * G) S[T::idx(x, i % G)] = re;
+      ireg[u] = im;
+    }
+    __syncthreads();
+    strip_fft<N, G, +1>(S, tw);
+    __syncthreads();
+    strip_store<N, G>(S, out + (size_t)b * 2 * spec, c0);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < IT; ++u) {
+      const int i = threadIdx.x + u * T::THREADS;
+      if (i < N * G) S[T::idx(i / G, i % G)] = ireg[u];
+    }
+    __syncthreads();
+    strip_fft<N, G, +1>(S, tw);
+    __syncthreads();
+    strip_store<N, G>(S, out + ((size_t)b * 2 + 1) * spec, c0);
+  } else {
+    const bool re = (first + (int)blockIdx.z) == 0;
+    batched_copy<N * G, T::THREADS, float2>(
+        [&](int i) {
+          const int x = i / G, c = c0 + i % G;
+          if (c >= T::C) return make_float2(0.f, 0.f);
+          const size_t e = (size_t)x * T::C + c;
+          const float2 aa = Aa[e], ab = Ab[e], ba = Ba[e], bb = Bb[e];
+          const float2 p = cmulc(aa, re ? ba : bb), q = cmulc(ab, re ? bb : ba);
+          return re ? make_float2(p.x - q.x, p.y - q.y) : make_float2(p.x + q.x, p.y + q.y);
+        },
+        [&](int i, float2 v) { S[T::idx(i / G, i % G)] = v; });
+    __syncthreads();
+    strip_fft<N, G, +1>(S, tw);
+    __syncthreads();
+    strip_store<N, G>(S, out + ((size_t)b * gridDim.z + blockIdx.z) * spec, c0);
+  }
 }
 
 // kappa(k)/N for a half-spectrum index: k for k < N/2, k - N above, 0 at N/2.
@@ -1427,50 +1464,52 @@ __global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_pencil_fft(const flo
   }
 }
 
-// Kernels without template parameters get internal linkage: the header is
-// included by more than one translation unit.
-namespace {
-
-// Zero n4 float4 values (grid-stride loop).
-__global__ void k_zero4(float4* __restrict__ p, long long n4) {
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (long long)gridDim.x * blockDim.x)
-    p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-}
-
 // Value of a real grid's spectrum at signed integer frequency (a, b, c) from
-// its half spectrum X [n][n][n/2+1]: X(-k) = conj X(k) supplies c < 0; zero
-// beyond the band (|component| > n/2).
-__device__ __forceinline__ float2 spec_at(const float2* __restrict__ X, int n, int a, int b, int c) {
-  const int h = n / 2;
+// its half spectrum X [N][N][N/2+1]: X(-k) = conj X(k) supplies c < 0; zero
+// beyond the band (|component| > N/2).
+template <int N>
+__device__ __forceinline__ float2 spec_at(const float2* __restrict__ X, int a, int b, int c) {
+  constexpr int h = N / 2;
   if (a > h || a < -h || b > h || b < -h || c > h || c < -h) return make_float2(0.f, 0.f);
-  if (c < 0) {
+  const bool mirror = c < 0;
+  if (mirror) {
     a = -a;
     b = -b;
     c = -c;
-    const float2 v = X[((size_t)((a + n) % n) * n + (size_t)((b + n) % n)) * (h + 1) + c];
-    return make_float2(v.x, -v.y);
   }
-  return X[((size_t)((a + n) % n) * n + (size_t)((b + n) % n)) * (h + 1) + c];
+  a += (a < 0) ? N : 0;
+  b += (b < 0) ? N : 0;
+  const float2 v = X[((size_t)a * N + (size_t)b) * (h + 1) + c];
+  return mirror ? make_float2(v.x, -v.y) : v;
 }
 
 // Spectral rotation (Sec. 3.2, step 1): out_b(k) = X(R_b^T kappa(k)) by
 // trilinear interpolation; with nch = 4 (u, yhat_x u, yhat_y u, yhat_z u) the
 // moment channels rotate as a vector, M_R(k) = R M(R^T kappa). in: nch half
 // spectra of the unrotated part about the grid origin; out: batch x nch half
-// spectra. Grid-stride loop over batch x half-spectrum elements.
-__global__ void k_spectral_rotate(const float2* __restrict__ in, int nch, const float* __restrict__ Rm, int n,
-                                  long long batch, float2* __restrict__ out) {
-  const int hn = n / 2 + 1;
-  const long long spec = (long long)n * n * hn, total = batch * spec;
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (long long)gridDim.x * blockDim.x) {
-    const long long b = e / spec, r = e - b * spec;
-    const int kz = (int)(r % hn), ky = (int)((r / hn) % n), kx = (int)(r / ((long long)hn * n));
-    // signed frequencies; the Nyquist index n/2 is taken as -n/2 on every axis
-    const double k0 = kx < n / 2 ? kx : kx - n, k1 = ky < n / 2 ? ky : ky - n, k2 = kz < n / 2 ? kz : kz - n;
+// spectra. A workgroup (256 threads) owns a tile of 2 (kx) x 8 (ky) x 16 (kz)
+// outputs, so that the trilinear corners it gathers form a compact rotated
+// block of the input (cache-friendly) and its stores are 128-byte rows.
+// grid = (tiles, min(batch, 65535)); the y dimension strides over the batch.
+template <int N>
+__global__ void __launch_bounds__(256) k_spectral_rotate(const float2* __restrict__ in, int nch,
+                                                         const float* __restrict__ Rm, int batch,
+                                                         float2* __restrict__ out) {
+  constexpr int HN = N / 2 + 1, TZ = 16, TY = 8, TX = 2;
+  constexpr int NTZ = (HN + TZ - 1) / TZ, NTY = N / TY;
+  constexpr size_t SPEC = (size_t)N * N * HN;
+  const int t = blockIdx.x;
+  const int kz = (t % NTZ) * TZ + (int)(threadIdx.x & 15);
+  const int ky = ((t / NTZ) % NTY) * TY + (int)((threadIdx.x >> 4) & 7);
+  const int kx = (t / (NTZ * NTY)) * TX + (int)(threadIdx.x >> 7);
+  if (kz >= HN) return;  // no barrier below
+  const size_t r = ((size_t)kx * N + ky) * HN + kz;
+  // signed frequencies; the Nyquist index N/2 is taken as -N/2 on every axis
+  const double k0 = kx < N / 2 ? kx : kx - N, k1 = ky < N / 2 ? ky : ky - N, k2 = kz < N / 2 ? kz : kz - N;
+  for (int b = blockIdx.y; b < batch; b += gridDim.y) {
     double R[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) R[i] = (double)Rm[b * 9 + i];
+    for (int i = 0; i < 9; ++i) R[i] = (double)Rm[(size_t)b * 9 + i];
     // q = R^T kappa
     const double q0 = R[0] * k0 + R[3] * k1 + R[6] * k2;
     const double q1 = R[1] * k0 + R[4] * k1 + R[7] * k2;
@@ -1485,21 +1524,31 @@ __global__ void k_spectral_rotate(const float2* __restrict__ in, int nch, const 
       const float w = (dx ? a0 : 1.f - a0) * (dy ? a1 : 1.f - a1) * (dz ? a2 : 1.f - a2);
       if (w == 0.f) continue;
       for (int ch = 0; ch < nch; ++ch) {
-        const float2 v = spec_at(in + (size_t)ch * spec, n, i0 + dx, i1 + dy, i2 + dz);
+        const float2 v = spec_at<N>(in + (size_t)ch * SPEC, i0 + dx, i1 + dy, i2 + dz);
         acc[ch].x += w * v.x;
         acc[ch].y += w * v.y;
       }
     }
-    float2* o = out + (size_t)b * nch * spec + r;
+    float2* o = out + (size_t)b * nch * SPEC + r;
     o[0] = acc[0];
     if (nch == 4) {
       for (int a = 0; a < 3; ++a) {
         const float ra = (float)R[3 * a], rb = (float)R[3 * a + 1], rc = (float)R[3 * a + 2];
-        o[(size_t)(1 + a) * spec] = make_float2(ra * acc[1].x + rb * acc[2].x + rc * acc[3].x,
+        o[(size_t)(1 + a) * SPEC] = make_float2(ra * acc[1].x + rb * acc[2].x + rc * acc[3].x,
                                                 ra * acc[1].y + rb * acc[2].y + rc * acc[3].y);
       }
     }
   }
+}
+
+// Kernels without template parameters get internal linkage: the header is
+// included by more than one translation unit.
+namespace {
+
+// Zero n4 float4 values (grid-stride loop).
+__global__ void k_zero4(float4* __restrict__ p, long long n4) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (long long)gridDim.x * blockDim.x)
+    p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 // Queries of precomputed field tables: query q reads the 7 fields of

@@ -179,10 +179,18 @@ template <int N> struct Launch {
     }
   }
   // complex score: nparts = 1 or 2 product spectra per member from part `first`
+  // (both parts from one read of the spectra where the Im products fit in
+  // registers: at most 16 strip elements per thread, and power-of-two edges,
+  // whose transforms hold fewer registers than the radix-3 ones)
   static void strip_score(const float2* A2, long long a_stride, const float2* B2, float2* out, int batch, int first,
                           int nparts, const float2* tw, hipStream_t s) {
-    hipLaunchKernelGGL((k_strip_score<N, G>), dim3(nstrips(), batch, nparts), dim3(T::THREADS), 0, s, A2, a_stride,
-                       B2, out, first, tw);
+    constexpr int IT = (N * G + T::THREADS - 1) / T::THREADS;
+    if (nparts == 2 && IT <= 16 && (N & (N - 1)) == 0)
+      hipLaunchKernelGGL((k_strip_score<N, G, true>), dim3(nstrips(), batch), dim3(T::THREADS), 0, s, A2, a_stride,
+                         B2, out, 0, tw);
+    else
+      hipLaunchKernelGGL((k_strip_score<N, G, false>), dim3(nstrips(), batch, nparts), dim3(T::THREADS), 0, s, A2,
+                         a_stride, B2, out, first, tw);
   }
   static void ft_fields(const float2* A, const float2* B4, float2* out7, const float2* tw, hipStream_t s) {
     hipLaunchKernelGGL((k_strip_ft_fields<N, G>), dim3(nstrips(), 7), dim3(T::THREADS), 0, s, A, B4, out7, tw);

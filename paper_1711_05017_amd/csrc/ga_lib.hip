@@ -602,11 +602,13 @@ ga_status ga_spectral_rotate(const ga_plan* plan, const float* d_in, int32_t cha
   if (overlaps(d_in, channels * spec_b, d_out, (size_t)batch * channels * spec_b) ||
       overlaps(d_R, sizeof(float) * 9 * (size_t)batch, d_out, (size_t)batch * channels * spec_b))
     return GA_EINVAL;
-  const long long total = (long long)batch * (long long)spectrum_elems(n);
-  const unsigned blocks = (unsigned)std::min<long long>((total + 255) / 256, 65535);
   ProfScope ps(plan, GA_K_READOUT, stream);
-  hipLaunchKernelGGL(k_spectral_rotate, dim3(blocks), dim3(256), 0, stream, reinterpret_cast<const float2*>(d_in),
-                     (int)channels, d_R, n, (long long)batch, reinterpret_cast<float2*>(d_out));
+  dispatch_axis(n, [&]<int N>() {
+    constexpr int tiles = (N / 2) * (N / 8) * ((N / 2 + 1 + 15) / 16);  // 2 x 8 x 16 outputs per workgroup
+    hipLaunchKernelGGL(k_spectral_rotate<N>, dim3(tiles, (unsigned)std::min(batch, 65535)), dim3(256), 0, stream,
+                       reinterpret_cast<const float2*>(d_in), (int)channels, d_R, (int)batch,
+                       reinterpret_cast<float2*>(d_out));
+  });
   return launch_status();
 }
 
