@@ -1483,61 +1483,174 @@ __device__ __forceinline__ float2 spec_at(const float2* __restrict__ X, int a, i
   return mirror ? make_float2(v.x, -v.y) : v;
 }
 
+// Trilinear interpolation of X at q (signed frequency coordinates, corner
+// indices i0 + {0, 1}, weights from the fractions a): the corner loop shared
+// by both rotation kernels. at(ix, iy, iz) returns the value at a corner.
+template <class At>
+__device__ __forceinline__ float2 trilinear_at(const int* i0, const float* a, At at) {
+  float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int dx = c >> 2, dy = (c >> 1) & 1, dz = c & 1;
+    const float w = (dx ? a[0] : 1.f - a[0]) * (dy ? a[1] : 1.f - a[1]) * (dz ? a[2] : 1.f - a[2]);
+    if (w == 0.f) continue;
+    const float2 v = at(i0[0] + dx, i0[1] + dy, i0[2] + dz);
+    acc.x += w * v.x;
+    acc.y += w * v.y;
+  }
+  return acc;
+}
+
+// q = R^T kappa in float64, split into the lower corner and the fractions.
+__device__ __forceinline__ void rotate_frequency(const double* R, double k0, double k1, double k2, int* i0, float* a) {
+  const double q[3] = {R[0] * k0 + R[3] * k1 + R[6] * k2, R[1] * k0 + R[4] * k1 + R[7] * k2,
+                       R[2] * k0 + R[5] * k1 + R[8] * k2};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double f = floor(q[d]);
+    a[d] = (float)(q[d] - f);
+    i0[d] = (int)f;
+  }
+}
+
+// The moment channels rotate as a vector: o[1 + a] = sum_b R[a][b] acc[1 + b].
+__device__ __forceinline__ void store_rotated(float2* o, size_t spec, int nch, const double* R, const float2* acc) {
+  o[0] = acc[0];
+  if (nch == 4) {
+    for (int a = 0; a < 3; ++a) {
+      const float ra = (float)R[3 * a], rb = (float)R[3 * a + 1], rc = (float)R[3 * a + 2];
+      o[(size_t)(1 + a) * spec] = make_float2(ra * acc[1].x + rb * acc[2].x + rc * acc[3].x,
+                                              ra * acc[1].y + rb * acc[2].y + rc * acc[3].y);
+    }
+  }
+}
+
 // Spectral rotation (Sec. 3.2, step 1): out_b(k) = X(R_b^T kappa(k)) by
 // trilinear interpolation; with nch = 4 (u, yhat_x u, yhat_y u, yhat_z u) the
 // moment channels rotate as a vector, M_R(k) = R M(R^T kappa). in: nch half
 // spectra of the unrotated part about the grid origin; out: batch x nch half
-// spectra. A workgroup (256 threads) owns a tile of 2 (kx) x 8 (ky) x 16 (kz)
-// outputs, so that the trilinear corners it gathers form a compact rotated
-// block of the input (cache-friendly) and its stores are 128-byte rows.
-// grid = (tiles, min(batch, 65535)); the y dimension strides over the batch.
+// spectra. The signed frequency of index N/2 is -N/2 on every axis.
+//
+// A workgroup (256 threads) owns an 8 x 8 x 8 tile of outputs, two per
+// thread. Per rotation it bounds the tile's preimage R^T kappa (a rotated
+// cube), loads that box of each channel into LDS with rows along kz (coalesced
+// reads, spec_at supplying the mirrored half and the zero band edge), and
+// interpolates from LDS. Corners outside the box (possible only through
+// rounding at the box edge) are read from global memory. Needs N/2 divisible by 8 (signed frequencies contiguous in
+// every tile). grid = (tiles, min(batch, 65535)).
 template <int N>
 __global__ void __launch_bounds__(256) k_spectral_rotate(const float2* __restrict__ in, int nch,
                                                          const float* __restrict__ Rm, int batch,
                                                          float2* __restrict__ out) {
-  constexpr int HN = N / 2 + 1, TZ = 16, TY = 8, TX = 2;
+  constexpr int HN = N / 2 + 1, T = 8, NT = N / T, NTZ = (HN + T - 1) / T;
+  constexpr int BOX = 17;  // largest box edge: floor(7 sqrt(3)) + 2 = 14, with room for rounding
+  constexpr size_t SPEC = (size_t)N * N * HN;
+  static_assert((N / 2) % T == 0, "tiles must not straddle the sign change of the frequencies");
+  __shared__ float2 box[BOX * BOX * BOX];
+  const int t = blockIdx.x, tid = threadIdx.x;
+  const int tz = t % NTZ, ty = (t / NTZ) % NT, tx = t / (NTZ * NT);
+  auto signed_k = [](int k) { return k < N / 2 ? k : k - N; };
+  // signed frequency range of the tile per axis (kz beyond HN does not exist)
+  const int klo[3] = {signed_k(tx * T), signed_k(ty * T), signed_k(tz * T)};
+  const int kz_last = min(tz * T + T - 1, HN - 1);
+  const int khi[3] = {klo[0] + T - 1, klo[1] + T - 1, signed_k(tz * T) + (kz_last - tz * T)};
+  // this thread's two outputs
+  int kk[2][3];
+  bool valid[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int o = tid + 256 * j;
+    kk[j][0] = tx * T + (o >> 6);
+    kk[j][1] = ty * T + ((o >> 3) & 7);
+    kk[j][2] = tz * T + (o & 7);
+    valid[j] = kk[j][2] < HN;
+  }
+  for (int b = blockIdx.y; b < batch; b += gridDim.y) {
+    double R[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) R[i] = (double)Rm[(size_t)b * 9 + i];
+    // integer box holding every corner: [lo, lo + ext) per axis
+    int lo[3], ext[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      double qmin = 0.0, qmax = 0.0;
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        const double r = R[3 * e + d], u = r * klo[e], v = r * khi[e];
+        qmin += fmin(u, v);
+        qmax += fmax(u, v);
+      }
+      lo[d] = (int)floor(qmin);
+      ext[d] = min((int)floor(qmax) + 2 - lo[d], BOX);
+    }
+    const int ez = ext[2], eyz = ext[1] * ext[2], etot = ext[0] * eyz;
+    const float inv_ez = 1.0f / (float)ez, inv_ey = 1.0f / (float)ext[1];
+    int i0[2][3];
+    float a[2][3];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      rotate_frequency(R, signed_k(kk[j][0]), signed_k(kk[j][1]), signed_k(kk[j][2]), i0[j], a[j]);
+    float2 acc[2][4];
+    for (int ch = 0; ch < nch; ++ch) {
+      const float2* X = in + (size_t)ch * SPEC;
+      __syncthreads();  // previous readers of the box are done
+      for (int i = tid; i < etot; i += 256) {
+        // i < 17^3 < 2^16: (i + 1/2) / e rounds down to the exact quotient
+        const int r = (int)(((float)i + 0.5f) * inv_ez), iz = i - r * ez;
+        const int ix = (int)(((float)r + 0.5f) * inv_ey), iy = r - ix * ext[1];
+        box[i] = spec_at<N>(X, lo[0] + ix, lo[1] + iy, lo[2] + iz);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        if (!valid[j]) continue;
+        acc[j][ch] = trilinear_at(i0[j], a[j], [&](int x, int y, int z) {
+          const int ux = x - lo[0], uy = y - lo[1], uz = z - lo[2];
+          if ((unsigned)ux < (unsigned)ext[0] && (unsigned)uy < (unsigned)ext[1] && (unsigned)uz < (unsigned)ez)
+            return box[ux * eyz + uy * ez + uz];
+          return spec_at<N>(X, x, y, z);
+        });
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (!valid[j]) continue;
+      const size_t r = ((size_t)kk[j][0] * N + kk[j][1]) * HN + kk[j][2];
+      store_rotated(out + (size_t)b * nch * SPEC + r, SPEC, nch, R, acc[j]);
+    }
+  }
+}
+
+// The same rotation with every corner gathered from global memory: grid
+// edges whose N/2 is not a multiple of 8. A workgroup takes 2 (kx) x 8 (ky) x
+// 16 (kz) outputs. grid = (tiles, min(batch, 65535)).
+template <int N>
+__global__ void __launch_bounds__(256) k_spectral_rotate_gather(const float2* __restrict__ in, int nch,
+                                                                const float* __restrict__ Rm, int batch,
+                                                                float2* __restrict__ out) {
+  constexpr int HN = N / 2 + 1, TZ = 16, TY = 8;
   constexpr int NTZ = (HN + TZ - 1) / TZ, NTY = N / TY;
   constexpr size_t SPEC = (size_t)N * N * HN;
   const int t = blockIdx.x;
   const int kz = (t % NTZ) * TZ + (int)(threadIdx.x & 15);
   const int ky = ((t / NTZ) % NTY) * TY + (int)((threadIdx.x >> 4) & 7);
-  const int kx = (t / (NTZ * NTY)) * TX + (int)(threadIdx.x >> 7);
+  const int kx = (t / (NTZ * NTY)) * 2 + (int)(threadIdx.x >> 7);
   if (kz >= HN) return;  // no barrier below
   const size_t r = ((size_t)kx * N + ky) * HN + kz;
-  // signed frequencies; the Nyquist index N/2 is taken as -N/2 on every axis
   const double k0 = kx < N / 2 ? kx : kx - N, k1 = ky < N / 2 ? ky : ky - N, k2 = kz < N / 2 ? kz : kz - N;
   for (int b = blockIdx.y; b < batch; b += gridDim.y) {
     double R[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) R[i] = (double)Rm[(size_t)b * 9 + i];
-    // q = R^T kappa
-    const double q0 = R[0] * k0 + R[3] * k1 + R[6] * k2;
-    const double q1 = R[1] * k0 + R[4] * k1 + R[7] * k2;
-    const double q2 = R[2] * k0 + R[5] * k1 + R[8] * k2;
-    const double f0 = floor(q0), f1 = floor(q1), f2 = floor(q2);
-    const float a0 = (float)(q0 - f0), a1 = (float)(q1 - f1), a2 = (float)(q2 - f2);
-    const int i0 = (int)f0, i1 = (int)f1, i2 = (int)f2;
-    float2 acc[4] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int dx = c >> 2, dy = (c >> 1) & 1, dz = c & 1;
-      const float w = (dx ? a0 : 1.f - a0) * (dy ? a1 : 1.f - a1) * (dz ? a2 : 1.f - a2);
-      if (w == 0.f) continue;
-      for (int ch = 0; ch < nch; ++ch) {
-        const float2 v = spec_at<N>(in + (size_t)ch * SPEC, i0 + dx, i1 + dy, i2 + dz);
-        acc[ch].x += w * v.x;
-        acc[ch].y += w * v.y;
-      }
+    int i0[3];
+    float a[3];
+    rotate_frequency(R, k0, k1, k2, i0, a);
+    float2 acc[4];
+    for (int ch = 0; ch < nch; ++ch) {
+      const float2* X = in + (size_t)ch * SPEC;
+      acc[ch] = trilinear_at(i0, a, [&](int x, int y, int z) { return spec_at<N>(X, x, y, z); });
     }
-    float2* o = out + (size_t)b * nch * SPEC + r;
-    o[0] = acc[0];
-    if (nch == 4) {
-      for (int a = 0; a < 3; ++a) {
-        const float ra = (float)R[3 * a], rb = (float)R[3 * a + 1], rc = (float)R[3 * a + 2];
-        o[(size_t)(1 + a) * SPEC] = make_float2(ra * acc[1].x + rb * acc[2].x + rc * acc[3].x,
-                                                ra * acc[1].y + rb * acc[2].y + rc * acc[3].y);
-      }
-    }
+    store_rotated(out + (size_t)b * nch * SPEC + r, SPEC, nch, R, acc);
   }
 }
 

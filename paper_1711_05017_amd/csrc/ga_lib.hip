@@ -604,10 +604,19 @@ ga_status ga_spectral_rotate(const ga_plan* plan, const float* d_in, int32_t cha
     return GA_EINVAL;
   ProfScope ps(plan, GA_K_READOUT, stream);
   dispatch_axis(n, [&]<int N>() {
-    constexpr int tiles = (N / 2) * (N / 8) * ((N / 2 + 1 + 15) / 16);  // 2 x 8 x 16 outputs per workgroup
-    hipLaunchKernelGGL(k_spectral_rotate<N>, dim3(tiles, (unsigned)std::min(batch, 65535)), dim3(256), 0, stream,
-                       reinterpret_cast<const float2*>(d_in), (int)channels, d_R, (int)batch,
-                       reinterpret_cast<float2*>(d_out));
+    const dim3 block(256);
+    const auto in = reinterpret_cast<const float2*>(d_in);
+    const auto out = reinterpret_cast<float2*>(d_out);
+    const unsigned nb = (unsigned)std::min(batch, 65535);
+    if constexpr ((N / 2) % 8 == 0) {
+      constexpr int tiles = (N / 8) * (N / 8) * ((N / 2 + 1 + 7) / 8);  // 8 x 8 x 8 outputs per workgroup
+      hipLaunchKernelGGL(k_spectral_rotate<N>, dim3(tiles, nb), block, 0, stream, in, (int)channels, d_R,
+                         (int)batch, out);
+    } else {
+      constexpr int tiles = (N / 2) * (N / 8) * ((N / 2 + 1 + 15) / 16);  // 2 x 8 x 16 outputs per workgroup
+      hipLaunchKernelGGL(k_spectral_rotate_gather<N>, dim3(tiles, nb), block, 0, stream, in, (int)channels, d_R,
+                         (int)batch, out);
+    }
   });
   return launch_status();
 }

@@ -28,7 +28,7 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-@pytest.mark.parametrize("n", [24, 32])
+@pytest.mark.parametrize("n", [24, 32, 64, 96])
 def test_spectral_rotation_matches_oracle(G, n):
     A = synth.random_part(3000 + n, n, 150, 1.0, 3.0, conf_radius=n / 4)
     B = synth.random_part(3100 + n, n, 80, 1.0, 2.5, conf_radius=n / 8)
@@ -54,3 +54,22 @@ def test_spectral_rotation_matches_oracle(G, n):
         assert O.rel_l2(Erot[b], Eres[b]) < 0.35  # interpolation of the spectrum approximates the re-splat
     with pytest.raises(G.GaError):  # two channels
         G.ga_spectral_rotate(plan, X4[:2].contiguous(), _dev(rots.reshape(-1, 9)))
+
+
+def test_spectral_rotation_128_and_batch_stride(G):
+    """128^3 (many LDS tiles per axis) with a batch larger than the rotations
+    used by the oracle check: every member must equal its own rotation."""
+    n = 128
+    B = synth.random_part(3400, n, 300, 1.0, 4.0, conf_radius=n / 6)
+    cB = B.ref_point()
+    rots = synth.shoemake_rotations(3401, 5).astype(np.float32)
+    plan = G.Plan(n, max_batch=8)
+    X4 = G.ga_fft3d(plan, G.GA_R2C, G.ga_splat(plan, _dev(B.xyzr), _dev(B.w), R=np.eye(3), c=cB, channels=4))
+    got = G.ga_spectral_rotate(plan, X4, _dev(rots.reshape(-1, 9))).cpu().numpy()
+    one = G.ga_spectral_rotate(plan, X4, _dev(rots[3:4].reshape(-1, 9))).cpu().numpy()
+    assert np.array_equal(one[0], got[3])
+    u = O.splat(O.place(B.xyzr[:, :3], np.eye(3), cB), B.xyzr[:, 3], B.w, n)
+    F4 = np.stack([O.fft3(u)] + [O.fft3(m) for m in O.moment_channels(u)])
+    ref = O.spectral_rotate4(F4, rots[3])[:, :, :, : n // 2 + 1]
+    for ch in range(4):
+        assert O.rel_l2(got[3, ch], ref[ch]) < FIELD_TOL, ch
