@@ -331,6 +331,26 @@ ga_status ga_plan_set_tuning(ga_plan* plan, int32_t groups, int32_t k, int32_t x
 ga_status ga_plan_get_tuning(const ga_plan* plan, int32_t* groups, int32_t* k, int32_t* xcd);
 
 /*
+ * Overlapped execution of ga_energy_fields on the plane path (grid edges up
+ * to 192). chunks = 1 (the default): every pass on the caller's stream.
+ * chunks = 2 or 4: the batch is split into that many parts (whole workgroups
+ * of the fused x pass), and each part's whole pipeline (binning, pass 1,
+ * fused x pass, pass 3) runs on the caller's stream or on a second stream
+ * owned by the plan (default priority), alternately. The parts on the two
+ * streams run side by side: each stream fills the other's kernel tails and
+ * launch gaps (measured faster than holding pass 1 of a part back until
+ * pass 1 of the previous part is done). The second stream starts after an event on the caller's
+ * stream and the call ends with the caller's stream waiting on it: results
+ * and workspace reuse keep the caller's stream order. Calls on a capturing stream run with one
+ * stream. The first call with chunks > 1 creates the plan's stream and
+ * events on the plan's device. The fields are those of chunks = 1 up to the
+ * order of float atomic additions in the splat. GA_EINVAL for other values;
+ * GA_EDEVICE if the stream or events cannot be created.
+ */
+ga_status ga_plan_set_overlap(ga_plan* plan, int32_t chunks);
+int32_t ga_plan_get_overlap(const ga_plan* plan);
+
+/*
  * Batched execution as one graph launch (Sec. 3.2: the energy field of many
  * relative rotations per frame). A batch is a list of items, each one
  * stationary spectrum against `batch` rotations of one moving part on the

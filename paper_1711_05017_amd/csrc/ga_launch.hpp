@@ -34,6 +34,13 @@ struct ga_plan {
   int tune_groups = 0;
   int tune_k = 0;
   int tune_xcd = 0;
+  // overlapped ga_energy_fields (ga_plan_set_overlap): the batch in `chunks`
+  // parts, pass 1 on the caller's stream, the x pass and pass 3 on `aux`,
+  // ordered by events ev[0 .. chunks) and joined back by ev[kMaxChunks]
+  static constexpr int kMaxChunks = 4;
+  int chunks = 1;
+  hipStream_t aux = nullptr;
+  hipEvent_t ev[kMaxChunks + 1] = {};
 };
 
 namespace ga_detail {

@@ -75,10 +75,37 @@ ga_status ga_plan_create(ga_plan** plan, int32_t n, int32_t max_batch, uint32_t 
 ga_status ga_plan_destroy(ga_plan* plan) {
   if (!plan) return GA_EINVAL;
   prof_drain(plan);
+  if (plan->aux) {
+    (void)hipStreamSynchronize(plan->aux);
+    for (hipEvent_t e : plan->ev)
+      if (e) (void)hipEventDestroy(e);
+    (void)hipStreamDestroy(plan->aux);
+  }
   if (plan->d_tw) (void)hipFree(plan->d_tw);
   delete plan;
   return GA_OK;
 }
+
+ga_status ga_plan_set_overlap(ga_plan* plan, int32_t chunks) {
+  if (!valid_stream_call(plan) || (chunks != 1 && chunks != 2 && chunks != ga_plan::kMaxChunks)) return GA_EINVAL;
+  if (chunks > 1 && !plan->aux) {
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess || hipSetDevice(plan->device) != hipSuccess) return GA_EDEVICE;
+    bool ok = hipStreamCreateWithFlags(&plan->aux, hipStreamNonBlocking) == hipSuccess;
+    for (hipEvent_t& e : plan->ev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+    (void)hipSetDevice(cur);
+    if (!ok) {
+      for (hipEvent_t& e : plan->ev)
+        if (e) (void)hipEventDestroy(e), e = nullptr;
+      if (plan->aux) (void)hipStreamDestroy(plan->aux), plan->aux = nullptr;
+      return GA_EDEVICE;
+    }
+  }
+  plan->chunks = chunks;
+  return GA_OK;
+}
+
+int32_t ga_plan_get_overlap(const ga_plan* plan) { return plan ? plan->chunks : 0; }
 
 int32_t ga_plan_n(const ga_plan* plan) { return plan ? plan->n : 0; }
 
@@ -327,26 +354,55 @@ ga_status ga_energy_fields(const ga_plan* plan, const float* d_Ahat, const float
   int* off = reinterpret_cast<int*>(bins + (size_t)batch * (size_t)n_pts * sizeof(Placed));
   float* rmax = reinterpret_cast<float*>(reinterpret_cast<char*>(off) +
                                          ((size_t)batch * (n + 1) * sizeof(int) + 15) / 16 * 16);
+  // chunked, two-stream execution (ga_plan_set_overlap); one stream under
+  // graph capture
+  int chunks = std::min(plan->chunks, (int)batch);
+  if (chunks > 1) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (!plan->aux || hipStreamIsCapturing(stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) chunks = 1;
+  }
+  if (chunks > 1) {  // the second stream starts after the caller's earlier work
+    (void)hipEventRecord(plan->ev[0], stream);
+    (void)hipStreamWaitEvent(plan->aux, plan->ev[0], 0);
+  }
   dispatch(n, [&]<int N>() {
-    {
+    const int k = plan->tune_k ? plan->tune_k : Launch<N>::kCorrK;
+    // parts of whole workgroups of the x pass (k members each), whole
+    // pipelines alternating between the caller's stream and the second one
+    const int per = ((batch + chunks - 1) / chunks + k - 1) / k * k;
+    int ci = 0;
+    for (int c0 = 0; c0 < batch; c0 += per, ++ci) {
+      const int nb = std::min(per, batch - c0);
+      hipStream_t sc = (ci & 1) ? plan->aux : stream;
+      SplatParams spc = sp;
+      spc.Rdev = sp.Rdev + (size_t)9 * c0;
+      Placed* rc = rec + (size_t)c0 * (size_t)n_pts;
+      int* oc = off + (size_t)c0 * (N + 1);
+      float* mc = rmax + c0;
+      float2* tc = tmp + (size_t)c0 * spectrum_elems(n);
       {
-        ProfScope pb(plan, GA_K_BIN, stream);
-        Launch<N>::bin_samples(sp, rec, off, rmax, batch, stream);
+        ProfScope pb(plan, GA_K_BIN, sc);
+        Launch<N>::bin_samples(spc, rc, oc, mc, nb, sc);
       }
-      ProfScope ps(plan, GA_K_PLANE_FWD, stream);
-      SplatParams spb = sp;
-      spb.rec = rec;
-      spb.off = off;
-      spb.rmax = rmax;
-      Launch<N>::plane_fwd(spb, nullptr, 1, tmp, batch, plan->d_tw, stream);
+      spc.rec = rc;
+      spc.off = oc;
+      spc.rmax = mc;
+      {
+        ProfScope ps(plan, GA_K_PLANE_FWD, sc);
+        Launch<N>::plane_fwd(spc, nullptr, 1, tc, nb, plan->d_tw, sc);
+      }
+      {
+        ProfScope ps(plan, GA_K_STRIP, sc);
+        Launch<N>::corr_fwd_tuned(groups, k, plan->tune_xcd == 1, reinterpret_cast<const float2*>(d_Ahat), 0, tc, nb,
+                                  plan->d_tw, sc);
+      }
+      ProfScope ps(plan, GA_K_PLANE_INV, sc);
+      Launch<N>::plane_inv(tc, d_E + (size_t)c0 * n * n * n, scale, nb, plan->d_tw, sc);
     }
-    {
-      ProfScope ps(plan, GA_K_STRIP, stream);
-      Launch<N>::corr_fwd_tuned(groups, plan->tune_k ? plan->tune_k : Launch<N>::kCorrK, plan->tune_xcd == 1,
-                                reinterpret_cast<const float2*>(d_Ahat), 0, tmp, batch, plan->d_tw, stream);
+    if (chunks > 1) {
+      (void)hipEventRecord(plan->ev[ga_plan::kMaxChunks], plan->aux);
+      (void)hipStreamWaitEvent(stream, plan->ev[ga_plan::kMaxChunks], 0);
     }
-    ProfScope ps(plan, GA_K_PLANE_INV, stream);
-    Launch<N>::plane_inv(tmp, d_E, scale, batch, plan->d_tw, stream);
   });
   return launch_status();
 }

@@ -35,7 +35,8 @@ EXPORTS = [
     "ga_server_create", "ga_server_destroy", "ga_pair_register", "ga_pair_release", "ga_submit", "ga_poll",
     "ga_server_get_stats", "ga_batch_create", "ga_batch_launch", "ga_batch_destroy",
     "ga_plan_autotune", "ga_plan_set_tuning", "ga_plan_get_tuning", "ga_lowpass",
-    "ga_spectral_rotate", "ga_field_table", "ga_field_table_query", "ga_score",
+    "ga_spectral_rotate", "ga_field_table", "ga_field_table_query", "ga_score", "ga_plan_set_overlap",
+    "ga_plan_get_overlap",
 ]
 GA_K_SPLAT, GA_K_PLANE_FWD, GA_K_STRIP, GA_K_PLANE_INV, GA_K_READOUT, GA_K_BIN = 0, 1, 2, 3, 4, 5
 KERNEL_KINDS = {"splat": 0, "plane_fwd": 1, "strip": 2, "plane_inv": 3, "readout": 4, "bin": 5}
@@ -83,6 +84,8 @@ _SIGS = {
     "ga_splat": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_float, ctypes.c_int32, _vp, _vp]),
     "ga_fft3d": (ctypes.c_int32, [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32, _vp, ctypes.c_size_t, _vp]),
     "ga_correlate": (ctypes.c_int32, [_vp, _vp, ctypes.c_int64, _vp, ctypes.c_int32, _vp, _vp, ctypes.c_size_t, _vp]),
+    "ga_plan_set_overlap": (ctypes.c_int32, [_vp, ctypes.c_int32]),
+    "ga_plan_get_overlap": (ctypes.c_int32, [_vp]),
     "ga_score": (ctypes.c_int32, [_vp, _vp, ctypes.c_int64, _vp, ctypes.c_int32, ctypes.c_uint32, _vp, _vp,
                                   ctypes.c_size_t, _vp]),
     "ga_energy_fields": (ctypes.c_int32, [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_float, ctypes.c_int32,
@@ -244,6 +247,13 @@ class Plan:
         _check("ga_plan_get_tuning", load().ga_plan_get_tuning(self._h, ctypes.byref(g), ctypes.byref(k),
                                                                ctypes.byref(x)))
         return g.value, k.value, x.value
+
+    def set_overlap(self, chunks: int):
+        """ga_energy_fields in `chunks` parts (1, 2, 4) over two streams."""
+        _check("ga_plan_set_overlap", load().ga_plan_set_overlap(self._h, int(chunks)))
+
+    def overlap(self) -> int:
+        return int(load().ga_plan_get_overlap(self._h))
 
     def profile(self, enable: bool = True):
         """Start (and clear) or stop per-kernel event timing."""

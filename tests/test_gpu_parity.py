@@ -389,3 +389,45 @@ def test_every_tuning_candidate_matches_oracle(G, n, npts, nrot):
         plan.set_tuning(4, 3)
     with pytest.raises(G.GaError):
         plan.set_tuning(4, 4, 3)
+
+
+# ---------------------------------------------------------------------------
+# overlapped execution: chunks of the batch over two streams
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,npts,nrot,chunks,k", [(32, 200, 7, 4, 4), (96, 700, 6, 2, 1), (128, 1500, 9, 4, 2)])
+def test_overlapped_energy_fields_match_oracle(G, n, npts, nrot, chunks, k):
+    A = _part(n, 1200 + n, npts, 1.0, 3.0)
+    B = _part(n, 1250 + n, npts, 1.0, 3.0, conf=n / 6)
+    rots = synth.shoemake_rotations(1290 + n, 2 * nrot)
+    cB = B.ref_point()
+    plan = G.Plan(n, max_batch=nrot)
+    plan.set_tuning(4, k)
+    Ahat = G.ga_fft3d(plan, G.GA_R2C, G.ga_splat(plan, _dev(A.xyzr), _dev(A.w)))[0].contiguous()
+    R1 = _dev(rots[:nrot].reshape(nrot, 9).astype(np.float32))
+    R2 = _dev(rots[nrot:].reshape(nrot, 9).astype(np.float32))
+    xb, wb = _dev(B.xyzr), _dev(B.w)
+    seq1 = G.ga_energy_fields(plan, Ahat, xb, wb, R1, cB).cpu().numpy()
+    seq2 = G.ga_energy_fields(plan, Ahat, xb, wb, R2, cB).cpu().numpy()
+    plan.set_overlap(chunks)
+    assert plan.overlap() == chunks
+    # two calls back to back on a side stream, sharing one workspace, read on
+    # that stream right after: the second call's binning must wait for the
+    # first call's second-stream work, and the reads for both
+    s = torch.cuda.Stream()
+    work = plan.workspace(G.ga.GA_OP_ENERGY, nrot, B.n)
+    with torch.cuda.stream(s):
+        E1 = G.ga_energy_fields(plan, Ahat, xb, wb, R1, cB, work=work, stream=s)
+        E2 = G.ga_energy_fields(plan, Ahat, xb, wb, R2, cB, work=work, stream=s)
+        sums = torch.stack([E1.double().sum(), E2.double().sum()])
+    s.synchronize()
+    E1, E2, sums = E1.cpu().numpy(), E2.cpu().numpy(), sums.cpu().numpy()
+    assert O.rel_l2(E1, seq1) < 1e-6 and O.rel_l2(E2, seq2) < 1e-6
+    assert sums[0] == pytest.approx(E1.astype(np.float64).sum(), rel=1e-12)
+    assert sums[1] == pytest.approx(E2.astype(np.float64).sum(), rel=1e-12)
+    for r in (0, nrot - 1):
+        ref = O.pair_fields(A.xyzr, A.w, B.xyzr, B.w, rots[r], cB, n, want_torque=False)["E"]
+        assert O.rel_l2(E1[r], ref) < FIELD_TOL, r
+    plan.set_overlap(1)
+    with pytest.raises(G.GaError):
+        plan.set_overlap(3)
