@@ -357,7 +357,11 @@ int32_t ga_plan_get_overlap(const ga_plan* plan);
  * item's own grid edge, i.e. one ga_energy_fields call; items may use
  * different plans (grid edges). ga_batch_create records all items into one
  * HIP graph, each item on its own parallel branch, and instantiates it;
- * ga_batch_launch replays it on `stream` with a single graph launch.
+ * ga_batch_launch replays it on `stream` with a single graph launch. An item
+ * whose plan is set to 2 or 4 parts (ga_plan_set_overlap, plane path) is
+ * recorded as that many parts of its batch on parallel branches, each in a
+ * 256-byte aligned slice of the item's d_work, when the slices fit in
+ * work_bytes (otherwise as one branch).
  *
  * Every pointer of an item is captured by the graph: a replay reads the
  * current contents of d_Ahat, d_xyzr, d_w and d_R and overwrites d_E and

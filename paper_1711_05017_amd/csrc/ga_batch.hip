@@ -4,6 +4,7 @@
 // parallel branches of the graph; one graph launch replays them all.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -49,17 +50,50 @@ ga_status ga_batch_create(ga_batch** out, const ga_batch_item* items, int32_t n_
         return GA_EINVAL;
     }
   }
+  // An item whose plan asks for overlapped execution (ga_plan_set_overlap)
+  // is recorded as that many parts of its batch on parallel branches, each
+  // with its own slice of the item's workspace (when the slices fit).
+  struct Part {
+    const ga_batch_item* it;
+    int c0, nb;
+    char* work;
+    size_t work_bytes;
+  };
+  std::vector<Part> parts;
+  for (int i = 0; i < n_items; ++i) {
+    const ga_batch_item& it = items[i];
+    const int k = it.plan->tune_k ? it.plan->tune_k : 4;
+    const int chunks = std::min(it.plan->chunks, (int)it.batch);
+    const int per = ((it.batch + chunks - 1) / chunks + k - 1) / k * k;
+    auto slice = [&](int nb) {  // 256-byte aligned slices
+      return (ga_workspace_size(it.plan, GA_OP_ENERGY, nb, it.n_pts) + 255) / 256 * 256;
+    };
+    size_t need = 0;
+    for (int c0 = 0; c0 < it.batch; c0 += per) need += slice(std::min(per, it.batch - c0));
+    if (chunks <= 1 || need > it.work_bytes || axis_mode(it.plan)) {
+      parts.push_back({&it, 0, it.batch, static_cast<char*>(it.d_work), it.work_bytes});
+      continue;
+    }
+    char* w = static_cast<char*>(it.d_work);
+    for (int c0 = 0; c0 < it.batch; c0 += per) {
+      const int nb = std::min(per, it.batch - c0);
+      const size_t wb = slice(nb);
+      parts.push_back({&it, c0, nb, w, wb});
+      w += wb;
+    }
+  }
+  const int n_parts = (int)parts.size();
   ga_batch* b = new (std::nothrow) ga_batch{};
   if (!b) return GA_ENOMEM;
   b->n_items = n_items;
   (void)hipGetDevice(&b->device);
   hipStream_t cap = nullptr;
   hipEvent_t fork = nullptr;
-  std::vector<hipStream_t> br(n_items, nullptr);
-  std::vector<hipEvent_t> joins(n_items, nullptr);
+  std::vector<hipStream_t> br(n_parts, nullptr);
+  std::vector<hipEvent_t> joins(n_parts, nullptr);
   bool ok = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) == hipSuccess &&
             hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess;
-  for (int i = 0; ok && i < n_items; ++i)
+  for (int i = 0; ok && i < n_parts; ++i)
     ok = hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking) == hipSuccess &&
          hipEventCreateWithFlags(&joins[i], hipEventDisableTiming) == hipSuccess;
   ga_status st = GA_OK;
@@ -69,12 +103,14 @@ ga_status ga_batch_create(ga_batch** out, const ga_batch_item* items, int32_t n_
     capturing = ok;
   }
   ok = ok && hipEventRecord(fork, cap) == hipSuccess;
-  for (int i = 0; ok && i < n_items; ++i) {
-    const ga_batch_item& it = items[i];
+  for (int i = 0; ok && i < n_parts; ++i) {
+    const Part& pt = parts[i];
+    const ga_batch_item& it = *pt.it;
+    const size_t n3 = (size_t)it.plan->n * it.plan->n * it.plan->n;
     ok = hipStreamWaitEvent(br[i], fork, 0) == hipSuccess;
     if (!ok) break;
-    st = ga_energy_fields(it.plan, it.d_Ahat, it.d_xyzr, it.d_w, it.n_pts, it.d_R, it.c, it.sigma, it.batch, it.d_E,
-                          it.d_work, it.work_bytes, br[i]);
+    st = ga_energy_fields(it.plan, it.d_Ahat, it.d_xyzr, it.d_w, it.n_pts, it.d_R + (size_t)9 * pt.c0, it.c, it.sigma,
+                          pt.nb, it.d_E + (size_t)pt.c0 * n3, pt.work, pt.work_bytes, br[i]);
     ok = (st == GA_OK) && hipEventRecord(joins[i], br[i]) == hipSuccess &&
          hipStreamWaitEvent(cap, joins[i], 0) == hipSuccess;
   }
@@ -85,7 +121,7 @@ ga_status ga_batch_create(ga_batch** out, const ga_batch_item* items, int32_t n_
     ok = ok && ended && g != nullptr;
   }
   ok = ok && hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess;
-  for (int i = 0; i < n_items; ++i) {
+  for (int i = 0; i < n_parts; ++i) {
     if (joins[i]) (void)hipEventDestroy(joins[i]);
     if (br[i]) (void)hipStreamDestroy(br[i]);
   }

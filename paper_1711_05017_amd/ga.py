@@ -527,6 +527,8 @@ class Batch:
             _need(Ahat, torch.complex64, _spec_elems(n), "Ahat")
             E = torch.empty((batch, n, n, n), dtype=torch.float32, device=xyzr.device)
             work = plan.workspace(GA_OP_ENERGY, batch, m, device=xyzr.device)
+            if plan.overlap() > 1:  # room for the parts' 256-byte aligned workspace slices
+                work = torch.empty(work.numel() + 4 * 512, dtype=torch.uint8, device=xyzr.device)
             self._keep += [plan, xyzr, w, R, Ahat, E, work]
             self.outputs.append(E)
             c = [float(v) for v in torch.as_tensor(it["c"], dtype=torch.float64).reshape(-1).tolist()]

@@ -100,3 +100,28 @@ def test_graph_batch_errors(G):
     two[1] = item(E.data_ptr(), work.data_ptr(), work.numel())  # same output and workspace
     assert lib.ga_batch_create(ctypes.byref(h), two, 2) != 0
     assert lib.ga_batch_launch(None, None) != 0
+
+
+def test_graph_batch_records_overlapped_items_as_parts(G):
+    """Items whose plan asks for 2 or 4 parts are recorded as parallel branches
+    of their batch slices: every replay equals the eager one-stream call."""
+    items = [_item(G, 32, 71, 150, 7), _item(G, 64, 81, 300, 8)]
+    items[0]["plan"].set_overlap(4)
+    items[1]["plan"].set_overlap(2)
+    refs = []
+    for it in items:
+        it["plan"].set_overlap(1)
+        refs.append(_eager(G, it))
+    items[0]["plan"].set_overlap(4)
+    items[1]["plan"].set_overlap(2)
+    b = G.Batch(items)
+    try:
+        for rep in range(3):
+            outs = b.launch()
+            torch.cuda.synchronize()
+            for E, ref in zip(outs, refs):
+                assert O.rel_l2(E.double().cpu().numpy(), ref.double().cpu().numpy()) < 1e-6, rep
+            _ = _eager(G, items[1])  # overlapped eager call between replays
+            torch.cuda.synchronize()
+    finally:
+        b.close()
