@@ -38,9 +38,9 @@ HBM_PEAK_GBPS = 8000.0
 # make a plain 512 MiB device copy read and write 512 MiB). Valid only for the
 # kernel sources they were taken on: reported as null once those change.
 COUNTER_TRAFFIC = {
-    "sources_sha256": "8d4d1f2df9c85437422ca88d94583aa7e352317e35c2458822bcaa64c5ea3759",
-    "bytes": {"bin": (188.6 * 2 + 4036.0) * 1024, "plane_fwd": (18172.0 * 2 + 532480.0) * 1024,
-              "strip": (329516.0 * 2 + 532480.0) * 1024, "plane_inv": (266319.8 * 2 + 525939.6) * 1024},
+    "sources_sha256": "a30065227325efce3b49741790f7a4db340ace6e9ab943511c7b32a4c95283b5",
+    "bytes": {"bin": (188.6 * 2 + 4036.0) * 1024, "plane_fwd": (18231.9 * 2 + 532480.0) * 1024,
+              "strip": (329608.5 * 2 + 532480.0) * 1024, "plane_inv": (266319.7 * 2 + 526010.3) * 1024},
 }
 KERNEL_SOURCES = ("ga_fft.hpp", "ga_kernels.hpp", "ga_launch.hpp")
 
@@ -461,14 +461,18 @@ def main():
                      "timing": f"HIP events on the launch stream, {args.roofline_steps} one-stream steps of the "
                                f"same call after the timed region"},
     }
+    # the serving leg first among the others: the 512^3 leg leaves ~14 GB of
+    # cached device memory behind, measured to lengthen the latency tail
+    if not args.no_serving:
+        torch.cuda.empty_cache()
+        out["serving"] = serving_leg(args.serving_queries, args.serving_rate, mode=args.serving_mode)
     if not args.no_graph:
         out["graph"] = graph_leg(G, synth, np, torch, dev, chunks=best_chunks)
     if not args.no_c4:
         out["c4_512"] = c4_leg(G, synth, np, torch, dev)
+        torch.cuda.empty_cache()
     if not args.no_next:
         out["next_rows"] = next_rows_leg(G, synth, np, torch, dev)
-    if not args.no_serving:
-        out["serving"] = serving_leg(args.serving_queries, args.serving_rate, mode=args.serving_mode)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a)
     print(json.dumps(out), flush=True)

@@ -43,6 +43,11 @@
  *     valid until the work queued on `stream` has finished. The library never
  *     frees or keeps caller pointers. Host pointers are read before the call
  *     returns.
+ *   - Grids, spectra, sample arrays (d_xyzr), tables and workspaces are read
+ *     and written with 16-byte vector accesses and must be 16-byte aligned
+ *     (hipMalloc and torch allocations are); a misaligned one gives
+ *     GA_EINVAL. Weights, rotations, poses and pose outputs need only float
+ *     alignment.
  *   - Calls that need scratch device memory take a caller-owned workspace
  *     (d_work, work_bytes); ga_workspace_size() returns the bytes needed.
  *   - Every compute call only enqueues work on `stream` (a hipStream_t; 0 is

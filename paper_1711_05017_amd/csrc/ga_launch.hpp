@@ -51,6 +51,11 @@ inline constexpr const char* kVersion = "ga 0.1.0 (gfx950)";
 
 inline bool valid_stream_call(const ga_plan* p) { return p != nullptr && p->d_tw != nullptr; }
 
+// Device buffers are read and written with 16-byte vector accesses.
+template <class... P> inline bool all_aligned(P... p) {
+  return ((reinterpret_cast<uintptr_t>(p) % 16 == 0) && ...);
+}
+
 // Brackets one kernel launch with events on its stream when profiling is on.
 struct ProfScope {
   const ga_plan* plan;

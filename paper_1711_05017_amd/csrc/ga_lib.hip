@@ -133,6 +133,7 @@ size_t ga_workspace_size(const ga_plan* plan, int32_t op, int32_t batch, int64_t
 ga_status ga_splat(const ga_plan* plan, const float* d_xyzr, const float* d_w, int64_t n_pts, const float* h_R,
                    const float* h_c, float sigma, int32_t channels, float* d_grid, hipStream_t stream) {
   if (!valid_stream_call(plan) || !d_grid || n_pts < 0 || (n_pts > 0 && (!d_xyzr || !d_w))) return GA_EINVAL;
+  if (!all_aligned(d_xyzr, d_grid)) return GA_EINVAL;
   if ((channels != 1 && channels != 4) || !valid_sigma(sigma)) return GA_EINVAL;
   if ((h_R == nullptr) != (h_c == nullptr)) return GA_EINVAL;
   if (h_R && !rotation_ok(h_R)) return GA_EINVAL;
@@ -146,7 +147,10 @@ ga_status ga_splat(const ga_plan* plan, const float* d_xyzr, const float* d_w, i
     return launch_status();
   }
   if (n_pts == 0) {
-    (void)hipMemsetAsync(d_grid, 0, sizeof(float) * n3 * channels, stream);
+    // a fill kernel rather than a memset node, so the call can be captured
+    const long long n4 = (long long)(n3 * channels / 4);
+    hipLaunchKernelGGL(k_zero4, dim3((unsigned)std::min<long long>((n4 + 255) / 256, 65535)), dim3(256), 0, stream,
+                       reinterpret_cast<float4*>(d_grid), n4);
     return launch_status();
   }
   dispatch(n, [&]<int N>() {
@@ -159,6 +163,7 @@ ga_status ga_splat(const ga_plan* plan, const float* d_xyzr, const float* d_w, i
 ga_status ga_fft3d(const ga_plan* plan, int32_t dir, const void* d_in, void* d_out, int32_t batch, void* d_work,
                    size_t work_bytes, hipStream_t stream) {
   if (!valid_stream_call(plan) || !d_in || !d_out || batch < 1 || batch > plan->max_batch) return GA_EINVAL;
+  if (!all_aligned(d_in, d_out, d_work)) return GA_EINVAL;
   if (dir != GA_R2C && dir != GA_C2R) return GA_EINVAL;
   const int n = plan->n;
   const size_t real_b = (size_t)batch * n * n * n * sizeof(float);
@@ -224,6 +229,7 @@ ga_status ga_correlate(const ga_plan* plan, const float* d_Ahat, int64_t a_strid
   if (!valid_stream_call(plan) || !d_Ahat || !d_Bhat || !d_E || batch < 1 || batch > plan->max_batch ||
       a_stride < 0)
     return GA_EINVAL;
+  if (!all_aligned(d_Ahat, d_Bhat, d_E, d_work)) return GA_EINVAL;
   if (!d_work || work_bytes < ga_workspace_size(plan, GA_OP_CORRELATE, batch, 0)) return GA_ENOMEM;
   const int n = plan->n;
   {
@@ -266,6 +272,7 @@ ga_status ga_score(const ga_plan* plan, const float* d_A2, int64_t a_stride, con
   if (!valid_stream_call(plan) || !d_A2 || !d_B2 || !d_out || batch < 1 || batch > plan->max_batch || a_stride < 0 ||
       parts < 1 || parts > (GA_SCORE_RE | GA_SCORE_IM))
     return GA_EINVAL;
+  if (!all_aligned(d_A2, d_B2, d_out, d_work)) return GA_EINVAL;
   const int nparts = (parts == (GA_SCORE_RE | GA_SCORE_IM)) ? 2 : 1;
   const int first = (parts == GA_SCORE_IM) ? 1 : 0;
   if (!d_work || work_bytes < ga_workspace_size(plan, GA_OP_SCORE, batch, nparts)) return GA_ENOMEM;
@@ -312,6 +319,7 @@ ga_status ga_energy_fields(const ga_plan* plan, const float* d_Ahat, const float
   if (!valid_stream_call(plan) || !d_Ahat || !d_R || !h_c || !d_E || batch < 1 || batch > plan->max_batch ||
       n_pts < 0 || (n_pts > 0 && (!d_xyzr || !d_w)) || !valid_sigma(sigma))
     return GA_EINVAL;
+  if (!all_aligned(d_Ahat, d_xyzr, d_E, d_work)) return GA_EINVAL;
   if (!(std::isfinite(h_c[0]) && std::isfinite(h_c[1]) && std::isfinite(h_c[2]))) return GA_EINVAL;
   if (!d_work || work_bytes < ga_workspace_size(plan, GA_OP_ENERGY, batch, n_pts)) return GA_ENOMEM;
   const int n = plan->n;
@@ -412,6 +420,7 @@ ga_status ga_force_torque(const ga_plan* plan, const float* d_Ahat, const float*
                           hipStream_t stream) {
   if (!valid_stream_call(plan) || !d_Ahat || !d_Bhat4 || n_poses < 0 || (n_poses > 0 && (!d_t || !d_out7)))
     return GA_EINVAL;
+  if (!all_aligned(d_Ahat, d_Bhat4, d_work)) return GA_EINVAL;
   if (mode != GA_FIELDS && mode != GA_SINGLE) return GA_EINVAL;
   if (n_poses == 0) return GA_OK;
   const int n = plan->n;
@@ -461,6 +470,7 @@ ga_status ga_force_torque(const ga_plan* plan, const float* d_Ahat, const float*
 ga_status ga_field_grad(const ga_plan* plan, const float* d_uA, const float* d_Ahat, float* d_FA4, void* d_work,
                         size_t work_bytes, hipStream_t stream) {
   if (!valid_stream_call(plan) || !d_uA || !d_Ahat || !d_FA4) return GA_EINVAL;
+  if (!all_aligned(d_uA, d_Ahat, d_FA4, d_work)) return GA_EINVAL;
   if (!d_work || work_bytes < ga_workspace_size(plan, GA_OP_FIELD_GRAD, 1, 0)) return GA_ENOMEM;
   const int n = plan->n;
   const size_t spec = spectrum_elems(n);
@@ -498,6 +508,7 @@ ga_status ga_pose_local(const ga_plan* plan, const float* d_FA4, const float* d_
   if (!valid_stream_call(plan) || !d_FA4 || n_pts < 0 || (n_pts > 0 && (!d_xyzr || !d_w)) || !h_c ||
       !valid_sigma(sigma) || n_poses < 0 || (n_poses > 0 && (!d_R || !d_t || !d_out7)))
     return GA_EINVAL;
+  if (!all_aligned(d_FA4, d_xyzr, d_work)) return GA_EINVAL;
   if (!(std::isfinite(h_c[0]) && std::isfinite(h_c[1]) && std::isfinite(h_c[2]))) return GA_EINVAL;
   if (n_poses == 0) return GA_OK;
   if (!d_work || work_bytes < ga_workspace_size(plan, GA_OP_POSE_LOCAL, n_poses, n_pts)) return GA_ENOMEM;
@@ -526,6 +537,7 @@ ga_status ga_plan_autotune(ga_plan* plan, const float* d_Ahat, int32_t batch, vo
                            hipStream_t stream, float* h_us, int32_t n_us) {
   if (!valid_stream_call(plan) || !d_Ahat || batch < 1 || batch > plan->max_batch || n_us < 0 || (n_us > 0 && !h_us))
     return GA_EINVAL;
+  if (!all_aligned(d_Ahat, d_work)) return GA_EINVAL;
   const int n = plan->n;
   const size_t spec_b = spectrum_elems(n) * sizeof(float2);
   const size_t tmp_b = (size_t)batch * spec_b;
@@ -605,6 +617,7 @@ ga_status ga_plan_get_tuning(const ga_plan* plan, int32_t* groups, int32_t* k, i
 ga_status ga_field_table(const ga_plan* plan, const float* d_Ahat, const float* d_Bhat4, int32_t n_orient,
                          float* d_tables, void* d_work, size_t work_bytes, hipStream_t stream) {
   if (!valid_stream_call(plan) || !d_Ahat || !d_Bhat4 || !d_tables || n_orient < 1) return GA_EINVAL;
+  if (!all_aligned(d_Ahat, d_Bhat4, d_tables, d_work)) return GA_EINVAL;
   const int n = plan->n;
   const size_t spec = spectrum_elems(n), n3 = (size_t)n * n * n;
   if (!d_work || work_bytes < 7 * spec * sizeof(float2)) return GA_ENOMEM;
@@ -641,6 +654,7 @@ ga_status ga_field_table_query(const ga_plan* plan, const float* d_tables, int32
                                const float* d_t, int32_t n_q, float* d_out7, hipStream_t stream) {
   if (!valid_stream_call(plan) || !d_tables || n_orient < 1 || n_q < 0 || (n_q > 0 && (!d_orient || !d_t || !d_out7)))
     return GA_EINVAL;
+  if (!all_aligned(d_tables)) return GA_EINVAL;
   if (n_q == 0) return GA_OK;
   const int threads = 256, total = n_q * 7;
   ProfScope ps(plan, GA_K_READOUT, stream);
@@ -653,6 +667,7 @@ ga_status ga_spectral_rotate(const ga_plan* plan, const float* d_in, int32_t cha
                              float* d_out, hipStream_t stream) {
   if (!valid_stream_call(plan) || !d_in || !d_R || !d_out || batch < 1 || (channels != 1 && channels != 4))
     return GA_EINVAL;
+  if (!all_aligned(d_in, d_out)) return GA_EINVAL;
   const int n = plan->n;
   const size_t spec_b = spectrum_elems(n) * sizeof(float2);
   if (overlaps(d_in, channels * spec_b, d_out, (size_t)batch * channels * spec_b) ||
@@ -680,6 +695,7 @@ ga_status ga_spectral_rotate(const ga_plan* plan, const float* d_in, int32_t cha
 ga_status ga_lowpass(const ga_plan* plan, int32_t L, uint32_t mode, const float* d_in, float* d_out, int32_t batch,
                      float scale, hipStream_t stream) {
   if (!valid_stream_call(plan) || !d_in || !d_out || batch < 1 || !std::isfinite(scale)) return GA_EINVAL;
+  if (!all_aligned(d_in, d_out)) return GA_EINVAL;
   const int n = plan->n;
   if (L < 4 || (L & 1) || L > n || (mode != GA_LOWPASS_COARSE && mode != GA_LOWPASS_ZEROPAD)) return GA_EINVAL;
   const int m = (mode == GA_LOWPASS_COARSE) ? L : n;

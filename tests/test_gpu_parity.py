@@ -431,3 +431,17 @@ def test_overlapped_energy_fields_match_oracle(G, n, npts, nrot, chunks, k):
     plan.set_overlap(1)
     with pytest.raises(G.GaError):
         plan.set_overlap(3)
+
+
+def test_misaligned_buffers_are_rejected(G):
+    n = 32
+    plan = G.Plan(n)
+    p = _part(n, 77, 20)
+    buf = torch.zeros(n ** 3 + 4, dtype=torch.float32, device="cuda")
+    with pytest.raises(G.GaError):
+        G.ga_splat(plan, _dev(p.xyzr), _dev(p.w), out=buf[1:1 + n ** 3].view(1, n, n, n))
+    xyzr = torch.zeros(4 * p.n + 4, dtype=torch.float32, device="cuda")
+    with pytest.raises(G.GaError):
+        G.ga_splat(plan, xyzr[2:2 + 4 * p.n].view(p.n, 4), _dev(p.w))
+    u = G.ga_splat(plan, _dev(p.xyzr), _dev(p.w), out=buf[4:4 + n ** 3].view(1, n, n, n))  # 16 bytes in: fine
+    assert float(u.abs().sum()) > 0
