@@ -42,6 +42,14 @@ COUNTER_TRAFFIC = {
     "bytes": {"bin": (188.6 * 2 + 4036.0) * 1024, "plane_fwd": (18231.9 * 2 + 532480.0) * 1024,
               "strip": (329608.5 * 2 + 532480.0) * 1024, "plane_inv": (266319.7 * 2 + 526010.3) * 1024},
 }
+# Wavefront VALU instructions per launch at 128^3 x 64 (rocprofv3
+# SQ_INSTS_VALU, same validity rule): against the issue rate of one VALU
+# instruction per CU per cycle they give each kernel's instruction-issue floor.
+COUNTER_VALU = {
+    "sources_sha256": "a30065227325efce3b49741790f7a4db340ace6e9ab943511c7b32a4c95283b5",
+    "insts": {"plane_fwd": 122259001, "plane_inv": 58425344},
+}
+VALU_ISSUE_PER_S = 256 * 2.4e9  # CUs x clock: one wave64 VALU instruction per CU per cycle
 KERNEL_SOURCES = ("ga_fft.hpp", "ga_kernels.hpp", "ga_launch.hpp")
 
 
@@ -57,6 +65,16 @@ def counter_traffic(kernel):
     if COUNTER_TRAFFIC["sources_sha256"] != kernel_sources_sha256():
         return None
     return int(COUNTER_TRAFFIC["bytes"][kernel])
+
+
+def valu_issue(kernel, ms):
+    """The kernel's VALU instruction-issue floor against its measured time, or
+    None when the counters do not describe the current sources."""
+    if COUNTER_VALU["sources_sha256"] != kernel_sources_sha256() or kernel not in COUNTER_VALU["insts"]:
+        return None
+    floor_us = COUNTER_VALU["insts"][kernel] / VALU_ISSUE_PER_S * 1e6
+    return {"instructions": COUNTER_VALU["insts"][kernel], "floor_us": round(floor_us, 1),
+            "frac": round(floor_us / (ms * 1000.0), 4)}
 
 
 def algorithmic_bytes(n, batch, n_pts):
@@ -458,11 +476,15 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": counter_traffic(dom),
                      "algorithmic_bytes_per_launch": abytes[dom],
+                     "valu_issue": valu_issue(dom, kern[dom]),
                      "timing": f"HIP events on the launch stream, {args.roofline_steps} one-stream steps of the "
                                f"same call after the timed region"},
     }
     # the serving leg first among the others: the 512^3 leg leaves ~14 GB of
-    # cached device memory behind, measured to lengthen the latency tail
+    # cached device memory behind, measured to lengthen the latency tail. The
+    # field plan goes first too: its second stream takes one of the process's
+    # hardware queues, which the server's launch-group streams share.
+    plan.close()
     if not args.no_serving:
         torch.cuda.empty_cache()
         out["serving"] = serving_leg(args.serving_queries, args.serving_rate, mode=args.serving_mode)
