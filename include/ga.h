@@ -53,6 +53,10 @@
  *   - Every compute call only enqueues work on `stream` (a hipStream_t; 0 is
  *     the null stream) and returns; argument errors are reported
  *     synchronously, launch errors as GA_EDEVICE.
+ *   - A plan holds no per-call device state except the events of its
+ *     overlapped execution (ga_plan_set_overlap) and its profiling records:
+ *     with either in use, one host thread at a time calls with a given plan.
+ *     Otherwise compute calls on one plan from several threads are safe.
  *
  * Errors: every call returns a ga_status; ga_status_str() gives its text.
  */
