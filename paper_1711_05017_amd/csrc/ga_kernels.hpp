@@ -408,12 +408,19 @@ __device__ void splat_plane(const SplatParams& p, const double* R, int b, int x,
   }
 }
 
-// z R2C of every row pair and y FFT of every column, in the LDS plane W.
-// On entry W holds the pair-packed real plane (rows 2t, 2t+1 as the real and
-// imaginary parts of region t); on exit the plane's 2D spectrum [ky][kz]
-// with row stride H.
-template <int N>
-__device__ void plane_forward_lds(float2* W, const Twiddles<N>& tw) {
+// z R2C of every row pair and y FFT of every column of the LDS plane W, the
+// plane's 2D spectrum [ky][kz] (row stride H) written to global memory: to
+// dst0, and scaled by s1 to dst1 unless dst1 is null. On entry W holds the
+// pair-packed real plane (rows 2t, 2t+1 as the real and imaginary parts of
+// region t). The y transforms' last stage stores each output straight to
+// global memory (a wavefront's store covers 8 rows x 8 consecutive kz); the
+// real columns kz = 0 and kz = N/2, transformed together, are split in LDS
+// and written after. DIRECT = false: the spectrum stays in W (layout
+// yc) and dst0, dst1 are not used; the caller copies it out (edges whose
+// transforms leave no registers for the direct stores).
+template <int N, bool DIRECT>
+__device__ void plane_forward_out(float2* W, const Twiddles<N>& tw, float2* __restrict__ dst0,
+                                  float2* __restrict__ dst1, float s1) {
   using P = Plane<N>;
   constexpr int L = P::L, TPW = P::TPW, H = P::H;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -463,12 +470,19 @@ __device__ void plane_forward_lds(float2* W, const Twiddles<N>& tw) {
         if (t == 0) v.y = W[P::yc(pos, N / 2)].x;
         return v;
       };
-      auto st = [&](int pos, float2 v) { *col(pos) = v; };
+      auto st = [&](int pos, float2 v) {
+        if (!DIRECT || t == 0) {
+          *col(pos) = v;
+          return;
+        }
+        dst0[(size_t)pos * H + t] = v;
+        if (dst1) dst1[(size_t)pos * H + t] = make_float2(v.x * s1, v.y * s1);
+      };
       fft_at<N, -1>(l, tw, col, ld, st);
       if (t == 0) {
         // C = A + i B with A, B the spectra of the real columns kz = 0 and
         // kz = N/2: B(k) = (C(k) - conj C(N-k))/(2i) to column N/2 (not read
-        // here), then A(k) = C(k) - i B(k) in place, position by position.
+        // here), then A(k) = C(k) - i B(k), position by position.
         for (int k = l; k < N; k += L) {
           const float2 a = W[P::yc(k, 0)];
           const float2 z = W[P::yc((N - k) % N, 0)];
@@ -478,7 +492,17 @@ __device__ void plane_forward_lds(float2* W, const Twiddles<N>& tw) {
         for (int k = l; k < N; k += L) {
           const float2 c = W[P::yc(k, 0)];
           const float2 bb = W[P::yc(k, N / 2)];
-          W[P::yc(k, 0)] = make_float2(c.x + bb.y, c.y - bb.x);
+          const float2 a = make_float2(c.x + bb.y, c.y - bb.x);
+          if constexpr (DIRECT) {
+            dst0[(size_t)k * H] = a;
+            dst0[(size_t)k * H + N / 2] = bb;
+            if (dst1) {
+              dst1[(size_t)k * H] = make_float2(a.x * s1, a.y * s1);
+              dst1[(size_t)k * H + N / 2] = make_float2(bb.x * s1, bb.y * s1);
+            }
+          } else {
+            W[P::yc(k, 0)] = a;
+          }
         }
         wave_sync();
       }
@@ -564,8 +588,13 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_fwd
   const int x = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
   float* Wf = reinterpret_cast<float*>(W);
   const size_t plane_sz = (size_t)N * P::H;
+  // the y transforms store the spectrum straight to global memory up to
+  // edge 128; the 192 transforms need their registers (copy-out from LDS)
+  constexpr bool kDirect = N <= 128;
   auto run_pass = [&](int pass) {
     const int chan = (pass == 0) ? 0 : pass + 1;  // 0, 2, 3
+    float2* dst0 = out + (((size_t)b * NCH + chan) * N + x) * plane_sz;
+    float2* dst1 = (NCH == 4 && chan == 0) ? out + (((size_t)b * NCH + 1) * N + x) * plane_sz : nullptr;
     if constexpr (GRID) {
       const float2* src = reinterpret_cast<const float2*>(grid + ((size_t)b * N + x) * N * N);
       // two adjacent z values of one row land in one pair-region entry each
@@ -586,13 +615,12 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_fwd
     {
       Twiddles<N> tw;
       load_twiddles<N>(tw, table, (tid & 63) % P::L);
-      plane_forward_lds<N>(W, tw);
+      plane_forward_out<N, kDirect>(W, tw, dst0, dst1, yhat(x, N));
     }
-    plane_to_global<N>(out + (((size_t)b * NCH + chan) * N + x) * plane_sz, W, 1.0f);
-    if constexpr (NCH == 4) {
-      if (chan == 0) plane_to_global<N>(out + (((size_t)b * NCH + 1) * N + x) * plane_sz, W, yhat(x, N));
+    if constexpr (!kDirect) {
+      plane_to_global<N>(dst0, W, 1.0f);
+      if (dst1) plane_to_global<N>(dst1, W, yhat(x, N));
     }
-    __syncthreads();
   };
   if constexpr (NCH == 1) run_pass(0);
   else run_pass(blockIdx.z);  // one channel pass per workgroup: grid z = 3
