@@ -1732,25 +1732,30 @@ __global__ void k_table_query(const float* __restrict__ tables, int n, int n_ori
 // L/2 - 1 on every axis are kept (times scale), the rest are dropped.
 // coarse = 1: out is [batch][L][L][L/2+1] (the kept modes on an L grid);
 // coarse = 0: out is [batch][n][n][n/2+1] with the dropped modes zero.
-// Grid-stride loop over the output elements.
+// grid = (runs of one output kx plane, output kx, batch members strided by
+// gridDim.z); 32-bit index arithmetic within a plane.
 __global__ void k_lowpass(const float2* __restrict__ in, float2* __restrict__ out, int n, int L, int coarse,
-                          long long batch, float scale) {
+                          int batch, float scale) {
   const int hn = n / 2 + 1, m = coarse ? L : n, hm = m / 2 + 1;
-  const long long per = (long long)m * m * hm, total = batch * per;
   const int lim = L / 2 - 1;
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (long long)gridDim.x * blockDim.x) {
-    const long long b = e / per;
-    const long long r = e - b * per;
-    const int kz = (int)(r % hm), ky = (int)((r / hm) % m), kx = (int)(r / ((long long)hm * m));
-    const int ax = kx < m / 2 ? kx : kx - m, ay = ky < m / 2 ? ky : ky - m;  // signed frequencies
-    float2 v = make_float2(0.f, 0.f);
-    if (ax <= lim && ax >= -lim && ay <= lim && ay >= -lim && kz <= lim) {
-      const int sx = ax < 0 ? ax + n : ax, sy = ay < 0 ? ay + n : ay;
-      const float2 a = in[(size_t)b * n * n * hn + ((size_t)sx * n + sy) * hn + kz];
-      v = make_float2(a.x * scale, a.y * scale);
+  const int kx = blockIdx.y;
+  const int ax = kx < m / 2 ? kx : kx - m;  // signed frequency
+  const bool xin = ax <= lim && ax >= -lim;
+  const int sx = ax < 0 ? ax + n : ax;
+  const int plane = m * hm;
+  for (int b = blockIdx.z; b < batch; b += gridDim.z) {
+    const float2* src = in + (size_t)b * n * n * hn + (size_t)sx * n * hn;
+    float2* dst = out + ((size_t)b * m + kx) * plane;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < plane; r += gridDim.x * blockDim.x) {
+      const int ky = r / hm, kz = r - ky * hm;
+      const int ay = ky < m / 2 ? ky : ky - m;
+      float2 v = make_float2(0.f, 0.f);
+      if (xin && ay <= lim && ay >= -lim && kz <= lim) {
+        const float2 a = src[(size_t)(ay < 0 ? ay + n : ay) * hn + kz];
+        v = make_float2(a.x * scale, a.y * scale);
+      }
+      dst[r] = v;
     }
-    out[e] = v;
   }
 }
 

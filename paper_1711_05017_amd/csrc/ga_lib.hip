@@ -702,11 +702,12 @@ ga_status ga_lowpass(const ga_plan* plan, int32_t L, uint32_t mode, const float*
   const size_t in_b = (size_t)batch * spectrum_elems(n) * sizeof(float2);
   const size_t out_b = (size_t)batch * spectrum_elems(m) * sizeof(float2);
   if (overlaps(d_in, in_b, d_out, out_b)) return GA_EINVAL;
-  const long long total = (long long)batch * (long long)spectrum_elems(m);
-  const unsigned blocks = (unsigned)std::min<long long>((total + 255) / 256, 65535);
+  // grid: (kz-ky runs of one kx plane, kx, batch members)
+  const unsigned bx = (unsigned)((m * (m / 2 + 1) + 255) / 256);
   ProfScope ps(plan, GA_K_READOUT, stream);
-  hipLaunchKernelGGL(k_lowpass, dim3(blocks), dim3(256), 0, stream, reinterpret_cast<const float2*>(d_in),
-                     reinterpret_cast<float2*>(d_out), n, L, mode == GA_LOWPASS_COARSE ? 1 : 0, (long long)batch, scale);
+  hipLaunchKernelGGL(k_lowpass, dim3(bx, (unsigned)m, (unsigned)std::min(batch, 65535)), dim3(256), 0, stream,
+                     reinterpret_cast<const float2*>(d_in), reinterpret_cast<float2*>(d_out), n, L,
+                     mode == GA_LOWPASS_COARSE ? 1 : 0, (int)batch, scale);
   return launch_status();
 }
 
