@@ -1692,6 +1692,25 @@ __global__ void k_zero4(float4* __restrict__ p, long long n4) {
     p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
+// The periodic lattice cell of coordinate t: lower corner i0 and upper corner
+// i1 = i0 + 1 (both mod n, in [0, n)) and the fraction a = t - floor(t). The
+// quotient by n comes from a float division, off by at most one for
+// |t| < 2^24 n and then corrected; any other value (huge or not finite)
+// takes a 64-bit remainder, so the corners are always inside the grid.
+__device__ __forceinline__ void lattice_cell(float t, int n, int& i0, int& i1, float& a) {
+  const float fl = floorf(t);
+  a = t - fl;
+  long long m = (long long)fl - (long long)floorf(fl / (float)n) * n;
+  if (m < 0) m += n;
+  if (m >= n) m -= n;
+  if (m < 0 || m >= n) {
+    m = (long long)fl % n;
+    if (m < 0) m += n;
+  }
+  i0 = (int)m;
+  i1 = (i0 + 1 == n) ? 0 : i0 + 1;
+}
+
 // Queries of precomputed field tables: query q reads the 7 fields of
 // orientation orient[q] (tables + orient * 7 * n^3) trilinearly at t[q]
 // (periodic). An orientation index outside [0, n_orient) gives NaN outputs.
@@ -1708,21 +1727,15 @@ __global__ void k_table_query(const float* __restrict__ tables, int n, int n_ori
   const size_t n3 = (size_t)n * n * n;
   const float* f = tables + ((size_t)ori * 7 + o) * n3;
   float a[3];
-  int i0[3];
+  int i0[3], i1[3];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const float t = poses[q * 3 + d];
-    const float fl = floorf(t);
-    a[d] = t - fl;
-    long long m = (long long)fl % n;
-    i0[d] = (int)(m < 0 ? m + n : m);
-  }
+  for (int d = 0; d < 3; ++d) lattice_cell(poses[q * 3 + d], n, i0[d], i1[d], a[d]);
   float acc = 0.f;
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     const int dx = c >> 2, dy = (c >> 1) & 1, dz = c & 1;
     const float w = (dx ? a[0] : 1.f - a[0]) * (dy ? a[1] : 1.f - a[1]) * (dz ? a[2] : 1.f - a[2]);
-    const int ix = (i0[0] + dx) % n, iy = (i0[1] + dy) % n, iz = (i0[2] + dz) % n;
+    const int ix = dx ? i1[0] : i0[0], iy = dy ? i1[1] : i0[1], iz = dz ? i1[2] : i0[2];
     acc += w * f[((size_t)ix * n + iy) * n + iz];
   }
   out7[q * 7 + o] = acc;
@@ -1786,16 +1799,10 @@ __global__ void k_gather7(const float* __restrict__ fields, int n, const float* 
   const int p = i / 7, o = i % 7;
   const size_t n3 = (size_t)n * n * n;
   const float* f = fields + (size_t)o * n3;
-  float fl[3], a[3];
-  int i0[3];
+  float a[3];
+  int i0[3], i1[3];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const float t = poses[p * 3 + d];
-    fl[d] = floorf(t);
-    a[d] = t - fl[d];
-    long long q = (long long)fl[d] % n;
-    i0[d] = (int)(q < 0 ? q + n : q);
-  }
+  for (int d = 0; d < 3; ++d) lattice_cell(poses[p * 3 + d], n, i0[d], i1[d], a[d]);
   float acc = 0.f;
 #pragma unroll
   for (int dx = 0; dx < 2; ++dx)
@@ -1804,7 +1811,7 @@ __global__ void k_gather7(const float* __restrict__ fields, int n, const float* 
 #pragma unroll
       for (int dz = 0; dz < 2; ++dz) {
         const float wgt = (dx ? a[0] : 1.f - a[0]) * (dy ? a[1] : 1.f - a[1]) * (dz ? a[2] : 1.f - a[2]);
-        const int ix = (i0[0] + dx) % n, iy = (i0[1] + dy) % n, iz = (i0[2] + dz) % n;
+        const int ix = dx ? i1[0] : i0[0], iy = dy ? i1[1] : i0[1], iz = dz ? i1[2] : i0[2];
         acc += wgt * f[((size_t)ix * n + iy) * n + iz];
       }
   out7[p * 7 + o] = acc;
