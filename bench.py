@@ -311,7 +311,7 @@ def next_rows_leg(G, synth, np, torch, dev, reps=20):
         "f3_score_re_im_x16": (lambda: G.ga_score(plan, A2, B2, out=score_out, work=score_work),
                                2 * 8 * H + nb * (2 * 8 * H + 2 * 8 * H) + nb * 2 * (8 * H + 4 * n ** 3)),
         "f4_table_query_100k": (lambda: G.ga_field_table_query(plan, tables, orient, tq, out=q_out),
-                                n_q * (16 + 8 * 7 * 4 + 7 * 4)),
+                                n_q * (16 + 8 * 32 + 7 * 4)),
     }
     out = {"grid": n, "lowpass_L": L, "orientations": n_orient}
     for name, (f, nbytes) in ops.items():

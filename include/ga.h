@@ -263,10 +263,12 @@ ga_status ga_pose_local(const ga_plan* plan, const float* d_FA4, const float* d_
  * with the orientation fixed the correlation is precomputed once and read
  * at every frame). ga_field_table writes, for each orientation o, the 7
  * fields (E, F_x, F_y, F_z, tau_x, tau_y, tau_z over all translations, as
- * ga_force_torque GA_FIELDS) to d_tables + o * 7 * n^3 (float32 [o][7][x][y][z],
- * 28 n^3 bytes per orientation). d_Bhat4: n_orient x 4 half spectra of the
- * moving part at each orientation (ga_splat + ga_fft3d, or
- * ga_spectral_rotate); workspace 7 * n^2 (n/2+1) * 8 bytes.
+ * ga_force_torque GA_FIELDS) to d_tables + o * 8 * n^3 as one 32-byte record
+ * per voxel (float32 [o][x][y][z][8]: the 7 fields, then 0; 32 n^3 bytes per
+ * orientation), so that a query reads one record per trilinear corner.
+ * d_Bhat4: n_orient x 4 half spectra of the moving part at each orientation
+ * (ga_splat + ga_fft3d, or ga_spectral_rotate); workspace
+ * 7 * n^2 (n/2+1) * 8 + 7 * n^3 * 4 bytes.
  * ga_field_table_query reads query q's fields trilinearly at d_t[q]
  * (periodic, voxel units) in the table of orientation d_orient[q] (int32,
  * device): d_out7 = n_q x 7. An orientation index outside [0, n_orient)

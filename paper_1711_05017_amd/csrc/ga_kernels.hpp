@@ -1711,34 +1711,49 @@ __device__ __forceinline__ void lattice_cell(float t, int n, int& i0, int& i1, f
   i1 = (i0 + 1 == n) ? 0 : i0 + 1;
 }
 
-// Queries of precomputed field tables: query q reads the 7 fields of
-// orientation orient[q] (tables + orient * 7 * n^3) trilinearly at t[q]
-// (periodic). An orientation index outside [0, n_orient) gives NaN outputs.
-__global__ void k_table_query(const float* __restrict__ tables, int n, int n_orient, const int* __restrict__ orient,
+// Queries of precomputed field tables: query q reads the 32-byte records of
+// orientation orient[q] (tables + orient * 8 * n^3 floats, [x][y][z][8])
+// trilinearly at t[q] (periodic): two 16-byte loads per corner. An
+// orientation index outside [0, n_orient) gives NaN outputs. One thread per
+// query.
+__global__ void k_table_query(const float4* __restrict__ tables, int n, int n_orient, const int* __restrict__ orient,
                               const float* __restrict__ poses, int n_q, float* __restrict__ out7) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_q * 7) return;
-  const int q = i / 7, o = i % 7;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_q) return;
   const int ori = orient[q];
   if (ori < 0 || ori >= n_orient) {
-    out7[q * 7 + o] = __int_as_float(0x7fc00000);
+    for (int o = 0; o < 7; ++o) out7[q * 7 + o] = __int_as_float(0x7fc00000);
     return;
   }
   const size_t n3 = (size_t)n * n * n;
-  const float* f = tables + ((size_t)ori * 7 + o) * n3;
+  const float4* f = tables + (size_t)ori * 2 * n3;
   float a[3];
   int i0[3], i1[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) lattice_cell(poses[q * 3 + d], n, i0[d], i1[d], a[d]);
-  float acc = 0.f;
+  float4 lo = make_float4(0.f, 0.f, 0.f, 0.f), hi = lo;
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     const int dx = c >> 2, dy = (c >> 1) & 1, dz = c & 1;
     const float w = (dx ? a[0] : 1.f - a[0]) * (dy ? a[1] : 1.f - a[1]) * (dz ? a[2] : 1.f - a[2]);
-    const int ix = dx ? i1[0] : i0[0], iy = dy ? i1[1] : i0[1], iz = dz ? i1[2] : i0[2];
-    acc += w * f[((size_t)ix * n + iy) * n + iz];
+    const size_t v = ((size_t)(dx ? i1[0] : i0[0]) * n + (dy ? i1[1] : i0[1])) * n + (dz ? i1[2] : i0[2]);
+    const float4 r0 = f[2 * v], r1 = f[2 * v + 1];
+    lo.x += w * r0.x;
+    lo.y += w * r0.y;
+    lo.z += w * r0.z;
+    lo.w += w * r0.w;
+    hi.x += w * r1.x;
+    hi.y += w * r1.y;
+    hi.z += w * r1.z;
   }
-  out7[q * 7 + o] = acc;
+  float* o = out7 + (size_t)q * 7;
+  o[0] = lo.x;
+  o[1] = lo.y;
+  o[2] = lo.z;
+  o[3] = lo.w;
+  o[4] = hi.x;
+  o[5] = hi.y;
+  o[6] = hi.z;
 }
 
 // Low-pass filtering of half spectra (Sec. 3.3): modes with |kappa(k_a)| <=
@@ -1822,6 +1837,15 @@ __global__ void k_pack4(const float* __restrict__ u, const float* __restrict__ g
                         long long n3) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n3) FA[i] = make_float4(u[i], g3[i], g3[n3 + i], g3[2 * n3 + i]);
+}
+
+// Interleaves 7 real fields [7][n3] into one 32-byte record per voxel
+// (E, F_x, F_y, F_z, tau_x, tau_y, tau_z, 0): the field-table layout.
+__global__ void k_pack8(const float* __restrict__ f7, float4* __restrict__ out, long long n3) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n3; i += (long long)gridDim.x * blockDim.x) {
+    out[2 * i] = make_float4(f7[i], f7[n3 + i], f7[2 * n3 + i], f7[3 * n3 + i]);
+    out[2 * i + 1] = make_float4(f7[4 * n3 + i], f7[5 * n3 + i], f7[6 * n3 + i], 0.f);
+  }
 }
 
 // Query descriptors for a batch of (rotation, translation) poses of one part:

@@ -620,19 +620,19 @@ ga_status ga_field_table(const ga_plan* plan, const float* d_Ahat, const float* 
   if (!all_aligned(d_Ahat, d_Bhat4, d_tables, d_work)) return GA_EINVAL;
   const int n = plan->n;
   const size_t spec = spectrum_elems(n), n3 = (size_t)n * n * n;
-  if (!d_work || work_bytes < 7 * spec * sizeof(float2)) return GA_ENOMEM;
-  const size_t tab_b = (size_t)n_orient * 7 * n3 * sizeof(float);
+  if (!d_work || work_bytes < 7 * spec * sizeof(float2) + 7 * n3 * sizeof(float)) return GA_ENOMEM;
+  const size_t tab_b = (size_t)n_orient * 8 * n3 * sizeof(float);
   if (overlaps(d_work, work_bytes, d_tables, tab_b) || overlaps(d_work, work_bytes, d_Ahat, spec * 8) ||
       overlaps(d_work, work_bytes, d_Bhat4, (size_t)n_orient * 4 * spec * 8) ||
       overlaps(d_tables, tab_b, d_Ahat, spec * 8) || overlaps(d_tables, tab_b, d_Bhat4, (size_t)n_orient * 4 * spec * 8))
     return GA_EINVAL;
   const float2* A = reinterpret_cast<const float2*>(d_Ahat);
   float2* spec7 = static_cast<float2*>(d_work);
+  float* fields7 = reinterpret_cast<float*>(spec7 + 7 * spec);
   const float scale = (float)(1.0 / ((double)n * n * n));
   const bool ax = axis_mode(plan);
   for (int o = 0; o < n_orient; ++o) {
     const float2* B4 = reinterpret_cast<const float2*>(d_Bhat4) + (size_t)o * 4 * spec;
-    float* fields7 = d_tables + (size_t)o * 7 * n3;
     dispatch_axis(n, [&]<int N>() {
       {
         ProfScope ps(plan, GA_K_READOUT, stream);
@@ -646,6 +646,9 @@ ga_status ga_field_table(const ga_plan* plan, const float* d_Ahat, const float* 
         Axis<N>::yz_inv(spec7, fields7, scale, 7, plan->d_tw, stream);
       }
     });
+    // one 32-byte record per voxel: a query reads 8 records, not 56 scattered floats
+    hipLaunchKernelGGL(k_pack8, dim3((unsigned)std::min<size_t>((n3 + 255) / 256, 65535)), dim3(256), 0, stream,
+                       fields7, reinterpret_cast<float4*>(d_tables) + (size_t)o * 2 * n3, (long long)n3);
   }
   return launch_status();
 }
@@ -656,10 +659,11 @@ ga_status ga_field_table_query(const ga_plan* plan, const float* d_tables, int32
     return GA_EINVAL;
   if (!all_aligned(d_tables)) return GA_EINVAL;
   if (n_q == 0) return GA_OK;
-  const int threads = 256, total = n_q * 7;
+  const int threads = 256;
   ProfScope ps(plan, GA_K_READOUT, stream);
-  hipLaunchKernelGGL(k_table_query, dim3((total + threads - 1) / threads), dim3(threads), 0, stream, d_tables,
-                     plan->n, (int)n_orient, d_orient, d_t, (int)n_q, d_out7);
+  hipLaunchKernelGGL(k_table_query, dim3((n_q + threads - 1) / threads), dim3(threads), 0, stream,
+                     reinterpret_cast<const float4*>(d_tables), plan->n, (int)n_orient, d_orient, d_t, (int)n_q,
+                     d_out7);
   return launch_status();
 }
 

@@ -440,16 +440,17 @@ def ga_pose_local(plan: Plan, FA4: torch.Tensor, xyzr: torch.Tensor, w: torch.Te
 def ga_field_table(plan: Plan, Ahat: torch.Tensor, Bhat4: torch.Tensor, out: Optional[torch.Tensor] = None,
                    work: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
     """The 7 fields per orientation: Bhat4 [n_orient, 4, n, n, n/2+1] (or
-    [4, ...] for one) -> tables [n_orient, 7, n, n, n]."""
+    [4, ...] for one) -> tables [n_orient, n, n, n, 8] (the 7 fields of a
+    voxel in one 32-byte record, the last float 0)."""
     n = plan.n
     n_orient = Bhat4.shape[0] if Bhat4.dim() == 5 else 1
     _need(Ahat, torch.complex64, _spec_elems(n), "Ahat")
     _need(Bhat4, torch.complex64, n_orient * 4 * _spec_elems(n), "Bhat4", exact=True)
     if out is None:
-        out = torch.empty((n_orient, 7, n, n, n), dtype=torch.float32, device=Bhat4.device)
-    _need(out, torch.float32, n_orient * 7 * n ** 3, "out")
+        out = torch.empty((n_orient, n, n, n, 8), dtype=torch.float32, device=Bhat4.device)
+    _need(out, torch.float32, n_orient * 8 * n ** 3, "out")
     if work is None:
-        work = torch.empty(7 * _spec_elems(n) * 8, dtype=torch.uint8, device=Bhat4.device)
+        work = torch.empty(7 * _spec_elems(n) * 8 + 7 * n ** 3 * 4, dtype=torch.uint8, device=Bhat4.device)
     _check("ga_field_table", load().ga_field_table(plan.handle, _ptr(Ahat), _ptr(Bhat4), n_orient, _ptr(out),
                                                    _ptr(work), int(work.numel()), _stream(stream)))
     return out
@@ -459,7 +460,7 @@ def ga_field_table_query(plan: Plan, tables: torch.Tensor, orient: torch.Tensor,
                          out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
     n = plan.n
     n_orient = int(tables.shape[0])
-    _need(tables, torch.float32, n_orient * 7 * n ** 3, "tables", exact=True)
+    _need(tables, torch.float32, n_orient * 8 * n ** 3, "tables", exact=True)
     n_q = int(t.shape[0])
     _need(t, torch.float32, 3 * n_q, "t", exact=True)
     _need(orient, torch.int32, n_q, "orient", exact=True)

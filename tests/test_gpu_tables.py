@@ -40,15 +40,17 @@ def test_field_tables_match_oracle(G):
     B4 = torch.stack([G.ga_fft3d(plan, G.GA_R2C, G.ga_splat(plan, _dev(B.xyzr), _dev(B.w), R=R, c=cB, channels=4))
                       for R in rots]).contiguous()
     tables = G.ga_field_table(plan, Ahat, B4)
-    assert tables.shape == (3, 7, n, n, n)
+    assert tables.shape == (3, n, n, n, 8)
+    assert float(tables[..., 7].abs().max()) == 0.0
     fields = []
     for R in rots:
         d = O.pair_fields(A.xyzr, A.w, B.xyzr, B.w, R, cB, n)
         fields.append(np.concatenate([d["E"][None], d["F"], d["tau"]]))
     for o in range(3):
-        assert O.rel_l2(tables[o, 0].cpu().numpy(), fields[o][0]) < FIELD_TOL
-        assert O.rel_l2(tables[o, 1:4].cpu().numpy(), fields[o][1:4]) < FORCE_TOL
-        assert O.rel_l2(tables[o, 4:7].cpu().numpy(), fields[o][4:7]) < FORCE_TOL
+        t7 = np.moveaxis(tables[o, ..., :7].cpu().numpy(), -1, 0)
+        assert O.rel_l2(t7[0], fields[o][0]) < FIELD_TOL
+        assert O.rel_l2(t7[1:4], fields[o][1:4]) < FORCE_TOL
+        assert O.rel_l2(t7[4:7], fields[o][4:7]) < FORCE_TOL
     rng = np.random.default_rng(5)
     nq = 60
     orient = rng.integers(0, 3, nq).astype(np.int32)
