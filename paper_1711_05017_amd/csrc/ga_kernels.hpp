@@ -168,7 +168,7 @@ __device__ __forceinline__ bool place_sample(const SplatParams& p, const double*
 
 // Places every sample of one part once and counting-sorts the records by
 // bx: records rb[0 .. count), bin offsets ob[0 .. N] (ob[N] = count), largest
-// radius *rm. One workgroup of 256 threads.
+// radius *rm. One workgroup (any size of at least 64 threads).
 template <int N>
 __device__ void bin_block(const SplatParams& p, const double* R, Placed* __restrict__ rb, int* __restrict__ ob,
                           float* __restrict__ rm) {
@@ -176,10 +176,10 @@ __device__ void bin_block(const SplatParams& p, const double* R, Placed* __restr
   __shared__ int cur[N];
   __shared__ int s_rmax;
   const int tid = threadIdx.x;
-  for (int i = tid; i < N; i += 256) cnt[i] = 0;
+  for (int i = tid; i < N; i += (int)blockDim.x) cnt[i] = 0;
   if (tid == 0) s_rmax = __float_as_int(1.0f);
   __syncthreads();
-  for (long long s = tid; s < p.n_pts; s += 256) {
+  for (long long s = tid; s < p.n_pts; s += blockDim.x) {
     Placed q;
     if (place_sample<N>(p, R, s, q)) {
       atomicAdd(&cnt[q.b.x], 1);
@@ -210,16 +210,16 @@ __device__ void bin_block(const SplatParams& p, const double* R, Placed* __restr
     }
   }
   __syncthreads();
-  for (long long s = tid; s < p.n_pts; s += 256) {
+  for (long long s = tid; s < p.n_pts; s += blockDim.x) {
     Placed q;
     if (place_sample<N>(p, R, s, q)) rb[atomicAdd(&cur[q.b.x], 1)] = q;
   }
 }
 
 // Per batch member b: the moving part rotated by R_b, binned into
-// rec[b*n_pts ...], off[b*(N+1) ...], rmax[b]. grid = batch, block = 256.
+// rec[b*n_pts ...], off[b*(N+1) ...], rmax[b]. grid = batch, block = 1024.
 template <int N>
-__global__ void __launch_bounds__(256) k_bin_samples(SplatParams p, Placed* __restrict__ rec, int* __restrict__ off,
+__global__ void __launch_bounds__(1024) k_bin_samples(SplatParams p, Placed* __restrict__ rec, int* __restrict__ off,
                                                      float* __restrict__ rmax) {
   const int b = blockIdx.x;
   double R[9];

@@ -116,7 +116,8 @@ template <int N> struct Launch {
   static int nsingle() { return (T::C + kSingleG - 1) / kSingleG; }
 
   static void bin_samples(const SplatParams& sp, Placed* rec, int* off, float* rmax, int batch, hipStream_t s) {
-    hipLaunchKernelGGL(k_bin_samples<N>, dim3(batch), dim3(256), 0, s, sp, rec, off, rmax);
+    // one workgroup per member: 1024 threads, as a batch has far fewer members than CUs
+    hipLaunchKernelGGL(k_bin_samples<N>, dim3(batch), dim3(1024), 0, s, sp, rec, off, rmax);
   }
   // pass 1 from real grids (nch = 1) or from binned samples (nch = 1 or 4)
   static void plane_fwd(const SplatParams& sp, const float* grid, int nch, float2* out, int batch, const float2* tw,
