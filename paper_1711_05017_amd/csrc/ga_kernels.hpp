@@ -1039,6 +1039,77 @@ __global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_ft_fields(cons
   strip_store<N, G>(S, out7 + (size_t)o * spec, c0);
 }
 
+// The same 7 fields with the spectra read once per strip: grid = (nstrips,
+// 2). Workgroup y = 0 keeps P_E = A conj(B_u) of its strip elements in
+// registers and produces E, F_x, F_y, F_z (P_E and -2 pi i w_a P_E); y = 1
+// keeps Q_b = A conj(M_b) and produces tau = 2 pi i (w x conj M) A, i.e.
+// tau_x = 2 pi i (w_y Q_z - w_z Q_y) and cyclic. Each output is transformed
+// along x in LDS in turn. Reads 6 spectra per strip instead of 35. The
+// products take registers: two wavefronts per SIMD are enough here.
+template <int N, int G>
+__global__ void __launch_bounds__((Strip<N, G>::THREADS)) __attribute__((amdgpu_waves_per_eu(1, 2))) k_strip_ft_fields2(const float2* __restrict__ A,
+                                                                           const float2* __restrict__ B4,
+                                                                           float2* __restrict__ out7,
+                                                                           const float2* __restrict__ table) {
+  using T = Strip<N, G>;
+  constexpr int IT = (N * G + T::THREADS - 1) / T::THREADS;
+  __shared__ float2 S[T::SIZE];
+  Twiddles<N> tw;
+  load_twiddles<N>(tw, table, (threadIdx.x & 63) % T::L);
+  const size_t spec = (size_t)N * T::C;
+  const bool torque = blockIdx.y == 1;
+  const int c0 = blockIdx.x * G;
+  float2 q0[IT], q1[IT], q2[IT];
+#pragma unroll
+  for (int u = 0; u < IT; ++u) {
+    const int i = threadIdx.x + u * T::THREADS;
+    const int x = i / G, c = c0 + i % G;
+    q0[u] = q1[u] = q2[u] = make_float2(0.f, 0.f);
+    if (i < N * G && c < T::C) {
+      const size_t e = (size_t)x * T::C + c;
+      const float2 a = A[e];
+      if (!torque) {
+        q0[u] = cmulc(a, B4[e]);
+      } else {
+        q0[u] = cmulc(a, B4[spec + e]);
+        q1[u] = cmulc(a, B4[2 * spec + e]);
+        q2[u] = cmulc(a, B4[3 * spec + e]);
+      }
+    }
+  }
+  const int nout = torque ? 3 : 4;
+#pragma unroll 1
+  for (int k = 0; k < nout; ++k) {
+#pragma unroll
+    for (int u = 0; u < IT; ++u) {
+      const int i = threadIdx.x + u * T::THREADS;
+      if (i < N * G) {
+        const int x = i / G, c = c0 + i % G;
+        const float wx = omega_of<N>(x), wy = omega_of<N>(c / T::H), wz = omega_of<N>(c % T::H);
+        float2 v;
+        if (!torque) {
+          const float2 p = q0[u];
+          const float w = (k == 1) ? wx : (k == 2) ? wy : wz;
+          // -2 pi i w P = 2 pi w (P.y, -P.x)
+          v = (k == 0) ? p : make_float2(kTwoPi * w * p.y, -kTwoPi * w * p.x);
+        } else {
+          float2 ax;
+          if (k == 0) ax = make_float2(wy * q2[u].x - wz * q1[u].x, wy * q2[u].y - wz * q1[u].y);
+          else if (k == 1) ax = make_float2(wz * q0[u].x - wx * q2[u].x, wz * q0[u].y - wx * q2[u].y);
+          else ax = make_float2(wx * q1[u].x - wy * q0[u].x, wx * q1[u].y - wy * q0[u].y);
+          v = make_float2(-kTwoPi * ax.y, kTwoPi * ax.x);  // 2 pi i ax
+        }
+        S[T::idx(x, i % G)] = v;
+      }
+    }
+    __syncthreads();
+    strip_fft<N, G, +1>(S, tw);
+    __syncthreads();
+    strip_store<N, G>(S, out7 + (size_t)((torque ? 4 : 0) + k) * spec, c0);
+    __syncthreads();
+  }
+}
+
 // Single-pose partial sums (eq. 7b at one translation): for pose p and strip
 // c0, sum over the strip's elements of w(kz) Re[P_o(k) exp(+2 pi i k.t/N)] in
 // float64, written to part[(p * nblk + blk) * 7 + o]. Full spectra in.

@@ -205,8 +205,15 @@ template <int N> struct Launch {
       hipLaunchKernelGGL((k_strip_score<N, G, false>), dim3(nstrips(), batch, nparts), dim3(T::THREADS), 0, s, A2,
                          a_stride, B2, out, first, tw);
   }
+  // the 7 force/torque products with the inverse x FFT: spectra read once per
+  // strip where the products fit in registers (at most 16 strip elements per
+  // thread), else one output per workgroup
   static void ft_fields(const float2* A, const float2* B4, float2* out7, const float2* tw, hipStream_t s) {
-    hipLaunchKernelGGL((k_strip_ft_fields<N, G>), dim3(nstrips(), 7), dim3(T::THREADS), 0, s, A, B4, out7, tw);
+    constexpr int IT = (N * G + T::THREADS - 1) / T::THREADS;
+    if constexpr (IT <= 16)
+      hipLaunchKernelGGL((k_strip_ft_fields2<N, G>), dim3(nstrips(), 2), dim3(T::THREADS), 0, s, A, B4, out7, tw);
+    else
+      hipLaunchKernelGGL((k_strip_ft_fields<N, G>), dim3(nstrips(), 7), dim3(T::THREADS), 0, s, A, B4, out7, tw);
   }
   static void single(const float2* A, const float2* B4, const float* poses, int n_poses, double* part,
                      const float2* tw, hipStream_t s) {
