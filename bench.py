@@ -38,16 +38,16 @@ HBM_PEAK_GBPS = 8000.0
 # make a plain 512 MiB device copy read and write 512 MiB). Valid only for the
 # kernel sources they were taken on: reported as null once those change.
 COUNTER_TRAFFIC = {
-    "sources_sha256": "0d9f5d1d89bc5f1944a17619298e313f035c705ce3163ecc12fe6ab9e9a1bb6a",
-    "bytes": {"bin": (182.1 * 2 + 4036.0) * 1024, "plane_fwd": (18579.9 * 2 + 537253.9) * 1024,
-              "strip": (395686.8 * 2 + 532480.0) * 1024, "plane_inv": (266319.8 * 2 + 525952.8) * 1024},
+    "sources_sha256": "148f02756871f781dd7e32fa34979225e1ffbf7debad30a9cddfc5d3cea9690b",
+    "bytes": {"bin": (182.1 * 2 + 4036.0) * 1024, "plane_fwd": (18570.1 * 2 + 537249.9) * 1024,
+              "strip": (395663.2 * 2 + 532480.0) * 1024, "plane_inv": (266319.8 * 2 + 525960.0) * 1024},
 }
 # Wavefront VALU instructions per launch at 128^3 x 64 (rocprofv3
 # SQ_INSTS_VALU, same validity rule): against the issue rate of one VALU
 # instruction per CU per cycle they give each kernel's instruction-issue floor.
 COUNTER_VALU = {
-    "sources_sha256": "0d9f5d1d89bc5f1944a17619298e313f035c705ce3163ecc12fe6ab9e9a1bb6a",
-    "insts": {"plane_fwd": 110347559, "plane_inv": 58425344},
+    "sources_sha256": "148f02756871f781dd7e32fa34979225e1ffbf7debad30a9cddfc5d3cea9690b",
+    "insts": {"plane_fwd": 110347150, "plane_inv": 58425344},
 }
 VALU_ISSUE_PER_S = 256 * 2.4e9  # CUs x clock: one wave64 VALU instruction per CU per cycle
 KERNEL_SOURCES = ("ga_fft.hpp", "ga_kernels.hpp", "ga_launch.hpp")
