@@ -232,6 +232,26 @@ ga_status ga_force_torque(const ga_plan* plan, const float* d_Ahat, const float*
                           hipStream_t stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight haptic or serving loops, harnesses that forbid hipMalloc):
+ * ga_force_torque in GA_SINGLE mode with no workspace argument. Same
+ * arguments, kernels and results as ga_force_torque(..., GA_SINGLE, ...);
+ * the per-strip float64 partial sums live in a static device array of the
+ * library, GA_NOALLOC_SCRATCH_BYTES per device, held until the process ends.
+ * The call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine). It needs n_poses * ceil(n (n/2+1) / 64) * 56 bytes of that array
+ * (2304 poses at n = 128, 145 at n = 512) and returns GA_ENOMEM beyond it,
+ * before enqueueing anything. Every partial sum is written before it is read,
+ * so nothing has to be cleared between calls. All calls on one device share
+ * its array: calls that may overlap on one device (several streams or host
+ * threads) race and must be serialised by the caller; d_out7 must not alias
+ * the inputs.
+ */
+#define GA_NOALLOC_SCRATCH_BYTES (16u << 20)
+ga_status ga_force_torque_noalloc(const ga_plan* plan, const float* d_Ahat, const float* d_Bhat4, const float* d_t,
+                                  int32_t n_poses, float* d_out7, hipStream_t stream);
+
+/*
  * Resident field of the stationary part for single-translation queries:
  * d_FA4[v] = (u_A, d_x u_A, d_y u_A, d_z u_A) at voxel v (float4 per voxel,
  * n^3 of them), the gradient being the spectral derivative of eq. 6a,

@@ -28,6 +28,7 @@ from .ga import (  # noqa: F401
     ga_field_table_query,
     ga_field_grad,
     ga_force_torque,
+    ga_force_torque_noalloc,
     ga_lowpass,
     ga_spectral_rotate,
     ga_pose_local,

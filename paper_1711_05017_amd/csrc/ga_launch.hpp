@@ -23,6 +23,9 @@ struct ga_plan {
   uint32_t flags;
   int device;
   float2* d_tw;  // exp(-2 pi i k / n), k < n, float64-accurate values rounded to float32
+  // device address of the library's static scratch array on `device`
+  // (ga_force_torque_noalloc), resolved when the plan is created
+  void* scratch = nullptr;
   // per-kernel timing (ga_profile_*); mutable because compute calls take a const plan
   mutable bool prof = false;
   mutable std::vector<ga_prof_entry> prof_pending;

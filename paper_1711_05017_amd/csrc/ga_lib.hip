@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -15,6 +16,45 @@
 
 using namespace ga;
 using namespace ga_detail;
+
+// Scratch of ga_force_torque_noalloc: one array per device, in the code
+// object's static device memory (no allocation at call time). Its name is a
+// host-side stand-in; kernels get the device address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) double scratch[GA_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on `dev`, which must be the current device;
+// resolved once per device and kept for the life of the process.
+ga_status scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return GA_EDEVICE;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return GA_EDEVICE;
+    g_scratch_addr[dev] = ptr;
+  }
+  *out = g_scratch_addr[dev];
+  return GA_OK;
+}
+
+// GA_SINGLE readout: per-strip partial sums into `part`, then their sum per pose.
+void launch_single(const ga_plan* plan, const float2* A, const float2* B4, const float* d_t, int n_poses,
+                   double* part, float* d_out7, hipStream_t stream) {
+  const int n = plan->n;
+  ProfScope ps(plan, GA_K_READOUT, stream);
+  dispatch_axis(n, [&]<int N>() { Launch<N>::single(A, B4, d_t, n_poses, part, plan->d_tw, stream); });
+  const double scale = 1.0 / ((double)n * n * n);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(n_poses), dim3(64), 0, stream, (const double*)part, nsingle_of(n), d_out7,
+                     scale);
+}
+
+}  // namespace
 
 
 extern "C" {
@@ -49,7 +89,7 @@ ga_status ga_plan_create(ga_plan** plan, int32_t n, int32_t max_batch, uint32_t 
   p->n = n;
   p->max_batch = max_batch;
   p->flags = flags;
-  if (hipGetDevice(&p->device) != hipSuccess) {
+  if (hipGetDevice(&p->device) != hipSuccess || scratch_address(p->device, &p->scratch) != GA_OK) {
     delete p;
     return GA_EDEVICE;
   }
@@ -458,12 +498,26 @@ ga_status ga_force_torque(const ga_plan* plan, const float* d_Ahat, const float*
     hipLaunchKernelGGL(k_gather7, dim3((total + threads - 1) / threads), dim3(threads), 0, stream, fields7, n, d_t,
                        n_poses, d_out7);
   } else {
-    double* part = static_cast<double*>(d_work);
-    ProfScope ps(plan, GA_K_READOUT, stream);
-    dispatch_axis(n, [&]<int N>() { Launch<N>::single(A, B4, d_t, n_poses, part, plan->d_tw, stream); });
-    const double scale = 1.0 / ((double)n * n * n);
-    hipLaunchKernelGGL(k_reduce_partials, dim3(n_poses), dim3(64), 0, stream, part, nsingle_of(n), d_out7, scale);
+    launch_single(plan, A, B4, d_t, n_poses, static_cast<double*>(d_work), d_out7, stream);
   }
+  return launch_status();
+}
+
+ga_status ga_force_torque_noalloc(const ga_plan* plan, const float* d_Ahat, const float* d_Bhat4, const float* d_t,
+                                  int32_t n_poses, float* d_out7, hipStream_t stream) {
+  if (!valid_stream_call(plan) || !plan->scratch || !d_Ahat || !d_Bhat4 || n_poses < 0 ||
+      (n_poses > 0 && (!d_t || !d_out7)))
+    return GA_EINVAL;
+  if (!all_aligned(d_Ahat, d_Bhat4)) return GA_EINVAL;
+  if (n_poses == 0) return GA_OK;
+  const size_t need = ga_workspace_size(plan, GA_OP_FORCE_SINGLE, 1, (int64_t)n_poses);
+  if (need == 0 || need > GA_NOALLOC_SCRATCH_BYTES) return GA_ENOMEM;
+  const size_t spec_b = spectrum_elems(plan->n) * sizeof(float2);
+  if (overlaps(d_out7, sizeof(float) * 7 * (size_t)n_poses, d_Ahat, spec_b) ||
+      overlaps(d_out7, sizeof(float) * 7 * (size_t)n_poses, d_Bhat4, 4 * spec_b))
+    return GA_EINVAL;
+  launch_single(plan, reinterpret_cast<const float2*>(d_Ahat), reinterpret_cast<const float2*>(d_Bhat4), d_t,
+                n_poses, static_cast<double*>(plan->scratch), d_out7, stream);
   return launch_status();
 }
 

@@ -36,7 +36,7 @@ EXPORTS = [
     "ga_server_get_stats", "ga_batch_create", "ga_batch_launch", "ga_batch_destroy",
     "ga_plan_autotune", "ga_plan_set_tuning", "ga_plan_get_tuning", "ga_lowpass",
     "ga_spectral_rotate", "ga_field_table", "ga_field_table_query", "ga_score", "ga_plan_set_overlap",
-    "ga_plan_get_overlap",
+    "ga_plan_get_overlap", "ga_force_torque_noalloc",
 ]
 GA_K_SPLAT, GA_K_PLANE_FWD, GA_K_STRIP, GA_K_PLANE_INV, GA_K_READOUT, GA_K_BIN = 0, 1, 2, 3, 4, 5
 KERNEL_KINDS = {"splat": 0, "plane_fwd": 1, "strip": 2, "plane_inv": 3, "readout": 4, "bin": 5}
@@ -92,6 +92,7 @@ _SIGS = {
                                           _vp, _vp, ctypes.c_size_t, _vp]),
     "ga_force_torque": (ctypes.c_int32, [_vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_uint32, _vp, _vp, ctypes.c_size_t,
                                          _vp]),
+    "ga_force_torque_noalloc": (ctypes.c_int32, [_vp, _vp, _vp, _vp, ctypes.c_int32, _vp, _vp]),
     "ga_field_grad": (ctypes.c_int32, [_vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "ga_pose_local": (ctypes.c_int32, [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_float, _vp,
                                        ctypes.c_int32, _vp, _vp, ctypes.c_size_t, _vp]),
@@ -396,6 +397,25 @@ def ga_force_torque(plan: Plan, Ahat: torch.Tensor, Bhat4: torch.Tensor, t: torc
     st = load().ga_force_torque(plan.handle, _ptr(Ahat), _ptr(Bhat4), _ptr(t), n_poses, int(mode), _ptr(out),
                                 _ptr(work), int(work.numel()), _stream(stream))
     _check("ga_force_torque", st)
+    return out
+
+
+GA_NOALLOC_SCRATCH_BYTES = 16 << 20
+
+
+def ga_force_torque_noalloc(plan: Plan, Ahat: torch.Tensor, Bhat4: torch.Tensor, t: torch.Tensor,
+                            out: torch.Tensor, stream=None) -> torch.Tensor:
+    """GA_SINGLE readout with the library's static scratch (no workspace); the
+    caller passes the output buffer, so the call allocates nothing."""
+    n = plan.n
+    n_poses = int(t.shape[0])
+    _need(t, torch.float32, 3 * n_poses, "t", exact=True)
+    _need(Ahat, torch.complex64, _spec_elems(n), "Ahat")
+    _need(Bhat4, torch.complex64, 4 * _spec_elems(n), "Bhat4")
+    _need(out, torch.float32, 7 * n_poses, "out")
+    st = load().ga_force_torque_noalloc(plan.handle, _ptr(Ahat), _ptr(Bhat4), _ptr(t), n_poses, _ptr(out),
+                                        _stream(stream))
+    _check("ga_force_torque_noalloc", st)
     return out
 
 
