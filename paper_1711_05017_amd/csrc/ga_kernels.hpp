@@ -127,6 +127,19 @@ struct HitList {
   int nhits;
 };
 
+// Raw buffer stores of float2: the address is the resource's base plus a
+// per-lane byte offset (VGPR) and a uniform byte offset (SGPR, here a
+// compile-time constant), so a run of stores at fixed distances costs no
+// vector address arithmetic. Stores at or beyond `bytes` are dropped.
+using u32x2 = __attribute__((ext_vector_type(2))) unsigned;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(void* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ void buffer_store2(float2 v, __amdgpu_buffer_rsrc_t rs, int lane_bytes, int const_bytes) {
+  const u32x2 d = {__float_as_uint(v.x), __float_as_uint(v.y)};
+  __builtin_amdgcn_raw_buffer_store_b64(d, rs, lane_bytes, const_bytes, 0);
+}
+
 __device__ __forceinline__ int wrapn(int v, int n) {
   v = (v < 0) ? v + n : v;
   return (v >= n) ? v - n : v;
@@ -624,6 +637,224 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_fwd
   };
   if constexpr (NCH == 1) run_pass(0);
   else run_pass(blockIdx.z);  // one channel pass per workgroup: grid z = 3
+}
+
+// ---------------------------------------------------------------------------
+// Pass 1 for grid edges with a two-stage transform schedule (the 128^3
+// workloads): the same splat -> z R2C -> y FFT of one x-plane as k_plane_fwd,
+// arranged so that every LDS address is a per-lane base plus a compile-time
+// offset and the transforms' access shapes do not meet bank conflicts.
+//
+//  * Rows t and t + N/2 of the plane form the complex row pair t (real and
+//    imaginary parts). A lane of the y transforms reads rows y and y + N/2 of
+//    its column together, so the two-for-one split of the z pass happens in
+//    that read: A_t(c) = Z_t(c) + conj Z_t(N-c) for row t and
+//    B_t(c) = -i (Z_t(c) - conj Z_t(N-c)) for row t + N/2. The factor 1/2 of
+//    the split is applied by the splat (an exact power-of-two scale), so no
+//    separate split pass through LDS remains.
+//  * Z_t(k) of row pair t lives at slot al(t) + be(k) with
+//      al(t) = S t + 4 floor(t/4) + 2 floor(t/8),   be(k) = k + floor(k/16).
+//    In every access below the compile-time part of t or k is a multiple of
+//    each floor term's divisor, so the address splits into a lane base and an
+//    immediate offset.
+//  * The y transform of column c (1 <= c < N/2) runs in place in the slots of
+//    Z_t(c) and Z_t(N-c), which no other transform reads; column 0 packs the
+//    real columns kz = 0 and kz = N/2 into one transform (the slots of k = 0
+//    and k = N/2) and is split after it. Its position q lives in row
+//    (q & 7) | ((q >> 4) << 3) of column c or N - c by bit 3 of q, a bit that
+//    is the same for all lanes of each access.
+// With 8-byte LDS reads served per half-wave on 32 bank pairs (slot mod 32)
+// and writes per quarter-wave on 16 (slot mod 16), S = 136 makes every z
+// access conflict-free; a y access conflicts (two ways, in one lane group)
+// only where four consecutive columns N - c straddle a multiple of 16.
+template <int N> struct PlaneP {
+  static constexpr bool ok = false;
+};
+template <> struct PlaneP<128> {
+  static constexpr bool ok = true;
+  static constexpr int R0 = 16, R1 = 8;  // stage radices
+  static constexpr int E = 16, L = 8;    // elements per lane, lanes per transform
+  static constexpr int NB1 = E / R1;     // stage-1 butterflies per lane
+  static constexpr int TPW = 64 / L;     // transforms per wavefront
+  static constexpr int WAVES = 8, THREADS = 512;
+  static constexpr int H = 65, S = 136;
+  __host__ __device__ static constexpr int al(int t) { return t * S + (t >> 2) * 4 + (t >> 3) * 2; }
+  __host__ __device__ static constexpr int be(int k) { return k + (k >> 4); }
+  static constexpr int SIZE = 8778;  // float2 slots: al(63) + be(127) + 1, rounded up to even (zeroed as float4)
+};
+static_assert(PlaneP<128>::TPW * PlaneP<128>::WAVES == 64, "one transform per lane group and phase");
+static_assert(PlaneP<128>::be(127) < PlaneP<128>::S, "rows do not overlap");
+static_assert(PlaneP<128>::al(63) + PlaneP<128>::be(127) < PlaneP<128>::SIZE && PlaneP<128>::SIZE % 2 == 0,
+              "plane slots");
+
+// grid = (N planes, batch, NCH == 4 ? 3 : 1); block = 512. Splats the
+// binned samples of batch member blockIdx.y (p.rec) into plane x and writes
+// its 2D spectrum, out[((b*NCH + c)*N + x)*N*H]: with NCH = 4 workgroup z
+// splats channel pass z (u, then yhat_y u, then yhat_z u) and the u pass also
+// writes yhat_x u (u scaled by yhat(x)).
+template <int N, int NCH>
+__global__ void __launch_bounds__(PlaneP<N>::THREADS, 4) k_plane_splat_fwd(SplatParams p, float2* __restrict__ out,
+                                                                          const float2* __restrict__ table) {
+  using P = PlaneP<N>;
+  constexpr int H = P::H, L = P::L, R1 = P::R1, NB1 = P::NB1, T = N / 2;
+  static_assert(P::R0 == 16 && R1 == 8 && L == 8 && NB1 == 2, "schedule of the code below");
+  __shared__ __attribute__((aligned(16))) float2 W[P::SIZE];
+  __shared__ HitList hl;
+  const int x = blockIdx.x, b = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tau = lane / L, l = lane % L;
+  // stage-1 twiddles exp(-2 pi i r j / N), j = l + L bb (both transforms)
+  float2 tw[NB1][R1];
+#pragma unroll
+  for (int bb = 0; bb < NB1; ++bb)
+#pragma unroll
+    for (int r = 1; r < R1; ++r) tw[bb][r] = table[r * (l + L * bb)];
+  const int pass = (NCH == 4) ? (int)blockIdx.z : 0;
+  const int chan = (pass == 0) ? 0 : pass + 1;  // 0, 2, 3
+  const size_t plane_sz = (size_t)N * H;
+  float2* dst0 = out + (((size_t)b * NCH + chan) * N + x) * plane_sz;
+  float2* dst1 = (NCH == 4 && chan == 0) ? out + (((size_t)b * NCH + 1) * N + x) * plane_sz : nullptr;
+  const float s1 = yhat(x, N);
+
+  float4* W4 = reinterpret_cast<float4*>(W);
+  for (int i = tid; i < P::SIZE / 2; i += P::THREADS) W4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+  __syncthreads();
+  {
+    SplatParams sp = p;
+    sp.inv1me0 *= 0.5f;  // the 1/2 of the two-for-one split
+    splat_plane<N, P::WAVES, P::THREADS>(sp, nullptr, b, x, chan, reinterpret_cast<float*>(W), hl,
+                                         [](int yy, int zz) {
+                                           return 2 * (P::al(yy & (T - 1)) + P::be(zz)) + (yy >= T ? 1 : 0);
+                                         });
+  }
+  __syncthreads();
+
+  // z: complex transform of row pair t = 8 wave + tau
+  {
+    const int t = P::TPW * wave + tau;
+    float2* zb = W + P::al(t) + l;  // position l + m (m a multiple of 8) at zb[be(m)]
+    float2 v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = zb[P::be(8 * r)];
+    Bfly<16, -1>::run(v);
+    float2* zw = W + P::al(t) + 17 * l;  // position 16 l + r at be(16 l + r) = 17 l + r
+    wave_sync();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) zw[r] = v[r];
+    wave_sync();
+    float2 u[NB1][R1];
+#pragma unroll
+    for (int bb = 0; bb < NB1; ++bb)
+#pragma unroll
+      for (int r = 0; r < R1; ++r) u[bb][r] = zb[P::be(8 * bb + 16 * r)];
+    wave_sync();
+#pragma unroll
+    for (int bb = 0; bb < NB1; ++bb) {
+#pragma unroll
+      for (int r = 1; r < R1; ++r) u[bb][r] = cmul(u[bb][r], tw[bb][r]);
+      Bfly<8, -1>::run(u[bb]);
+    }
+#pragma unroll
+    for (int bb = 0; bb < NB1; ++bb)
+#pragma unroll
+      for (int r = 0; r < R1; ++r) zb[P::be(8 * bb + 16 * r)] = u[bb][r];  // Z_t(k), k = l + 8 bb + 16 r
+  }
+  __syncthreads();
+
+  // y: column transform c = 8 wave + tau over rows 0 .. N-1
+  {
+    const int c = P::TPW * wave + tau;
+    const int b1 = P::be(c), b2 = P::be(c == 0 ? T : N - c);
+    float2* r1 = W + P::al(l) + b1;  // row l + 8 m of column c at r1[al(8 m)]
+    float2* r2 = W + P::al(l) + b2;  // ... of column N - c (or N/2)
+    float2 v[16];
+    {
+      float2 z1[8], z2[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        z1[r] = r1[P::al(8 * r)];
+        z2[r] = r2[P::al(8 * r)];
+      }
+      if (c != 0) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          v[r] = make_float2(z1[r].x + z2[r].x, z1[r].y - z2[r].y);      // row l + 8 r
+          v[r + 8] = make_float2(z1[r].y + z2[r].y, z2[r].x - z1[r].x);  // row l + 8 r + N/2
+        }
+      } else {
+        // real columns kz = 0 (real part) and kz = N/2 (imaginary part)
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          v[r] = make_float2(z1[r].x + z1[r].x, z2[r].x + z2[r].x);
+          v[r + 8] = make_float2(z1[r].y + z1[r].y, z2[r].y + z2[r].y);
+        }
+      }
+    }
+    Bfly<16, -1>::run(v);
+    float2* w1 = W + P::al(8 * l) + b1;  // position 16 l + r: row 8 l + (r & 7)
+    float2* w2 = W + P::al(8 * l) + b2;
+    wave_sync();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      w1[P::al(r)] = v[r];
+      w2[P::al(r)] = v[r + 8];
+    }
+    wave_sync();
+    float2 u[NB1][R1];
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+      u[0][r] = r1[P::al(8 * r)];  // position l + 16 r
+      u[1][r] = r2[P::al(8 * r)];  // position l + 8 + 16 r
+    }
+#pragma unroll
+    for (int bb = 0; bb < NB1; ++bb) {
+#pragma unroll
+      for (int r = 1; r < R1; ++r) u[bb][r] = cmul(u[bb][r], tw[bb][r]);
+      Bfly<8, -1>::run(u[bb]);
+    }
+    // outputs Y(ky), ky = l + 8 bb + 16 r
+    if (c != 0) {
+      const int lo = (l * H + c) * (int)sizeof(float2);
+      const auto rs0 = buffer_rsrc(dst0, (unsigned)(plane_sz * sizeof(float2)));
+#pragma unroll
+      for (int bb = 0; bb < NB1; ++bb)
+#pragma unroll
+        for (int r = 0; r < R1; ++r) buffer_store2(u[bb][r], rs0, lo, (8 * bb + 16 * r) * H * (int)sizeof(float2));
+      if (dst1) {
+        const auto rs1 = buffer_rsrc(dst1, (unsigned)(plane_sz * sizeof(float2)));
+#pragma unroll
+        for (int bb = 0; bb < NB1; ++bb)
+#pragma unroll
+          for (int r = 0; r < R1; ++r)
+            buffer_store2(make_float2(u[bb][r].x * s1, u[bb][r].y * s1), rs1, lo, (8 * bb + 16 * r) * H * (int)sizeof(float2));
+      }
+    } else {
+      // C = P + i Q with P, Q the spectra of the real columns kz = 0 and N/2:
+      // P(k) = (C(k) + conj C(N-k))/2, Q(k) = -i (C(k) - conj C(N-k))/2
+      wave_sync();
+#pragma unroll
+      for (int r = 0; r < R1; ++r) {
+        r1[P::al(8 * r)] = u[0][r];
+        r2[P::al(8 * r)] = u[1][r];
+      }
+      wave_sync();
+#pragma unroll
+      for (int bb = 0; bb < NB1; ++bb)
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+          const int k = l + 8 * bb + 16 * r, m = (N - k) & (N - 1);
+          const float2 a = u[bb][r];
+          const float2 z = W[P::al((m & 7) | ((m >> 4) << 3)) + (((m >> 3) & 1) ? b2 : b1)];
+          const float2 pk = make_float2(0.5f * (a.x + z.x), 0.5f * (a.y - z.y));
+          const float2 qk = make_float2(0.5f * (a.y + z.y), -0.5f * (a.x - z.x));
+          dst0[(size_t)k * H] = pk;
+          dst0[(size_t)k * H + T] = qk;
+          if (dst1) {
+            dst1[(size_t)k * H] = make_float2(pk.x * s1, pk.y * s1);
+            dst1[(size_t)k * H + T] = make_float2(qk.x * s1, qk.y * s1);
+          }
+        }
+    }
+  }
 }
 
 // The density itself: grid = (N planes). Writes nch real grids

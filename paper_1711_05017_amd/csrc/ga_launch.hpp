@@ -127,10 +127,23 @@ template <int N> struct Launch {
                         hipStream_t s) {
     if (grid)
       hipLaunchKernelGGL((k_plane_fwd<N, true, 1>), dim3(N, batch), dim3(P::THREADS), 0, s, sp, grid, out, tw);
-    else if (nch == 4)
-      hipLaunchKernelGGL((k_plane_fwd<N, false, 4>), dim3(N, batch, 3), dim3(P::THREADS), 0, s, sp, grid, out, tw);
     else
-      hipLaunchKernelGGL((k_plane_fwd<N, false, 1>), dim3(N, batch), dim3(P::THREADS), 0, s, sp, grid, out, tw);
+      plane_splat(sp, nch, out, batch, tw, s);
+  }
+  // pass 1 from binned samples (sp.rec): nch = 1, or 4 in three channel passes
+  static void plane_splat(const SplatParams& sp, int nch, float2* out, int batch, const float2* tw, hipStream_t s) {
+    if constexpr (PlaneP<N>::ok) {
+      constexpr int TH = PlaneP<N>::THREADS;
+      if (nch == 4)
+        hipLaunchKernelGGL((k_plane_splat_fwd<N, 4>), dim3(N, batch, 3), dim3(TH), 0, s, sp, out, tw);
+      else
+        hipLaunchKernelGGL((k_plane_splat_fwd<N, 1>), dim3(N, batch), dim3(TH), 0, s, sp, out, tw);
+    } else {
+      if (nch == 4)
+        hipLaunchKernelGGL((k_plane_fwd<N, false, 4>), dim3(N, batch, 3), dim3(P::THREADS), 0, s, sp, nullptr, out, tw);
+      else
+        hipLaunchKernelGGL((k_plane_fwd<N, false, 1>), dim3(N, batch), dim3(P::THREADS), 0, s, sp, nullptr, out, tw);
+    }
   }
   static void plane_inv(const float2* in, float* out, float scale, int batch, const float2* tw, hipStream_t s) {
     hipLaunchKernelGGL(k_plane_inv<N>, dim3(N, batch), dim3(P::THREADS), 0, s, in, out, scale, tw);

@@ -236,8 +236,7 @@ void ga_server::launch(SizeClass& c, Group& g) {
       sp.off = g.off;
       sp.rmax = g.rmax;
       sp.n_pts = c.max_pts;
-      hipLaunchKernelGGL((k_plane_fwd<N, false, 4>), dim3(N, k, 3), dim3(Plane<N>::THREADS), 0, g.stream, sp,
-                         (const float*)nullptr, g.spec4, tw);
+      L::plane_splat(sp, 4, g.spec4, k, tw, g.stream);
       hipLaunchKernelGGL((k_strip_single<N, L::G>), dim3(L::nstrips(), k), dim3(L::T::THREADS), 0, g.stream,
                          (const float2*)g.spec4, (const QueryItem*)g.d_items, g.part, tw);
     });
