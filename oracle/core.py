@@ -349,19 +349,20 @@ def single_pose_sum(Ahat, Bhat, Mhat, t):
     return np.array(out) / float(n) ** 3
 
 
-def local_pose_sum(uA, uB, t):
+def local_pose_sum(uA, uB, t, grad=None):
     """(E, F, tau) at one integer translation t by sums over the lattice in
     physical space, with the gradient on the stationary part:
     E = sum_q u_A(q + t) u_B(q), F = -sum_q grad u_A(q + t) u_B(q),
     tau = sum_q (grad u_A(q + t) x yhat(q)) u_B(q).
     Equal to single_pose_sum: the correlation of eq. 3 with q = p - t, and the
     spectral derivative of eq. 6a/6b moved from B to A by summation by parts
-    (its multiplier 2 pi i omega is odd, the Nyquist mode being zero)."""
+    (its multiplier 2 pi i omega is odd, the Nyquist mode being zero).
+    grad: grad_spectral(uA) when the caller already has it (several poses)."""
     n = uA.shape[0]
     t = np.asarray(np.rint(t), dtype=np.int64).reshape(3)
     shift = tuple(int(-v) for v in t)
     a = np.roll(uA, shift, axis=(0, 1, 2))  # a[q] = u_A(q + t)
-    g = np.roll(grad_spectral(uA), shift, axis=(1, 2, 3))
+    g = np.roll(grad_spectral(uA) if grad is None else grad, shift, axis=(1, 2, 3))
     yh = min_image_coord(n)
     Y = (yh[:, None, None], yh[None, :, None], yh[None, None, :])
     cross = [g[1] * Y[2] - g[2] * Y[1], g[2] * Y[0] - g[0] * Y[2], g[0] * Y[1] - g[1] * Y[0]]

@@ -109,6 +109,10 @@ struct SplatParams {
   const Placed* rec;
   const int* off;
   const float* rmax;
+  // per batch member and plane x: cand[b*N + x] = (lo1, n1, lo2, n2), the
+  // records whose x bin lies within reach of plane x (two runs when the range
+  // wraps around the torus); null where the kernels do not use it
+  const int4* cand;
 };
 
 // A sample that reaches the current plane, with the bounding square of its
@@ -184,10 +188,11 @@ __device__ __forceinline__ bool place_sample(const SplatParams& p, const double*
 // radius *rm. One workgroup (any size of at least 64 threads).
 template <int N>
 __device__ void bin_block(const SplatParams& p, const double* R, Placed* __restrict__ rb, int* __restrict__ ob,
-                          float* __restrict__ rm) {
+                          float* __restrict__ rm, int4* __restrict__ cand) {
   __shared__ int cnt[N];
   __shared__ int cur[N];
   __shared__ int s_rmax;
+  __shared__ int s_total;
   const int tid = threadIdx.x;
   for (int i = tid; i < N; i += (int)blockDim.x) cnt[i] = 0;
   if (tid == 0) s_rmax = __float_as_int(1.0f);
@@ -219,10 +224,28 @@ __device__ void bin_block(const SplatParams& p, const double* R, Placed* __restr
     }
     if (tid == 0) {
       ob[N] = carry;
+      s_total = carry;
       *rm = __int_as_float(s_rmax);
     }
   }
   __syncthreads();
+  if (cand) {
+    // candidate runs per plane: bins x - reach .. x + reach (mod N), read
+    // from the exclusive scan in cur[] before the scatter below advances it
+    const int reach = (int)ceilf(__int_as_float(s_rmax)) + 1;
+    const int total = s_total;
+    for (int x = tid; x < N; x += (int)blockDim.x) {
+      int4 r = make_int4(0, total, 0, 0);
+      if (2 * reach + 1 < N) {
+        const int blo = x - reach, bhi = x + reach;  // inclusive, mod N
+        if (blo < 0) r = make_int4(cur[blo + N], total - cur[blo + N], 0, cur[bhi + 1]);
+        else if (bhi >= N) r = make_int4(cur[blo], total - cur[blo], 0, (bhi + 1 - N < N) ? cur[bhi + 1 - N] : total);
+        else r = make_int4(cur[blo], ((bhi + 1 < N) ? cur[bhi + 1] : total) - cur[blo], 0, 0);
+      }
+      cand[x] = r;
+    }
+    __syncthreads();
+  }
   for (long long s = tid; s < p.n_pts; s += blockDim.x) {
     Placed q;
     if (place_sample<N>(p, R, s, q)) rb[atomicAdd(&cur[q.b.x], 1)] = q;
@@ -233,11 +256,12 @@ __device__ void bin_block(const SplatParams& p, const double* R, Placed* __restr
 // rec[b*n_pts ...], off[b*(N+1) ...], rmax[b]. grid = batch, block = 1024.
 template <int N>
 __global__ void __launch_bounds__(1024) k_bin_samples(SplatParams p, Placed* __restrict__ rec, int* __restrict__ off,
-                                                     float* __restrict__ rmax) {
+                                                     float* __restrict__ rmax, int4* __restrict__ cand) {
   const int b = blockIdx.x;
   double R[9];
   load_rotation(p, b, R);
-  bin_block<N>(p, R, rec + (size_t)b * p.n_pts, off + (size_t)b * (N + 1), rmax + b);
+  bin_block<N>(p, R, rec + (size_t)b * p.n_pts, off + (size_t)b * (N + 1), rmax + b,
+               cand ? cand + (size_t)b * N : nullptr);
 }
 
 // One query of the serving loop: a registered pair (its moving part's
@@ -260,7 +284,7 @@ struct QueryItem {
 template <int N>
 __global__ void __launch_bounds__(256) k_bin_items(const QueryItem* __restrict__ items, SplatParams base,
                                                    long long stride, Placed* __restrict__ rec, int* __restrict__ off,
-                                                   float* __restrict__ rmax) {
+                                                   float* __restrict__ rmax, int4* __restrict__ cand) {
   const int b = blockIdx.x;
   const QueryItem& it = items[b];
   SplatParams p = base;
@@ -273,7 +297,8 @@ __global__ void __launch_bounds__(256) k_bin_items(const QueryItem* __restrict__
   double R[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) R[i] = (double)it.R[i];
-  bin_block<N>(p, R, rec + (size_t)b * stride, off + (size_t)b * (N + 1), rmax + b);
+  bin_block<N>(p, R, rec + (size_t)b * stride, off + (size_t)b * (N + 1), rmax + b,
+               cand ? cand + (size_t)b * N : nullptr);
 }
 
 // Candidate hit test of one placed sample against plane x; appends it and
@@ -687,8 +712,90 @@ static_assert(PlaneP<128>::be(127) < PlaneP<128>::S, "rows do not overlap");
 static_assert(PlaneP<128>::al(63) + PlaneP<128>::be(127) < PlaneP<128>::SIZE && PlaneP<128>::SIZE % 2 == 0,
               "plane slots");
 
+// One hit of the per-wave splat below: the bounding square of the sample's
+// disk in the plane, rows ybase .. ybase + sy - 1 and columns zbase ..
+// zbase + sz - 1 (voxel indices, not yet reduced mod N), the offsets of its
+// first row and column from the disk centre, dx^2 and 1/(2 s^2).
+struct WaveHit {
+  int ybase, zbase, syz;  // syz = sy | sz << 16
+  float offy, offz, dx2, c2s, w;
+};
+
+// Hit test of candidate c (of the plane's candidate runs rg) against plane
+// x; false for c beyond the runs or a sample that misses the plane.
+template <int N>
+__device__ __forceinline__ bool wave_hit(const SplatParams& p, const Placed* rb, int4 rg, int c, int x, WaveHit& h) {
+  if (c >= rg.y + rg.w) return false;
+  const Placed q = rb[c < rg.y ? rg.x + c : rg.z + (c - rg.y)];
+  int m = x - q.b.x;
+  m = (m >= N / 2) ? m - N : m;
+  m = (m < -N / 2) ? m + N : m;
+  float dx = (float)m - q.a.x;
+  dx = (dx < -0.5f * N) ? dx + (float)N : dx;
+  h.w = __int_as_float(q.b.w);
+  const float rho = q.a.w;
+  if (!(fabsf(dx) < rho) || h.w == 0.0f) return false;
+  const float rd = sqrtf(fmaxf(rho * rho - dx * dx, 0.0f));
+  const int ylo = (int)ceilf(q.a.y - rd), yhi = (int)floorf(q.a.y + rd);
+  const int zlo = (int)ceilf(q.a.z - rd), zhi = (int)floorf(q.a.z + rd);
+  const int sy = yhi - ylo + 1, sz = zhi - zlo + 1;
+  if (sy <= 0 || sz <= 0) return false;
+  h.ybase = q.b.y + ylo;
+  h.zbase = q.b.z + zlo;
+  h.syz = sy | (sz << 16);
+  h.offy = (float)ylo - q.a.y;
+  h.offz = (float)zlo - q.a.z;
+  h.dx2 = dx * dx;
+  h.c2s = p.sig_c / (rho * rho);
+  return true;
+}
+
+// Splat of the hits one wavefront found (flag `hit`, parameters `h` in each
+// lane): the wave takes them one at a time, broadcast from their lanes, and
+// its 64 lanes cover 8 x 8 blocks of the hit's bounding square (lane = row
+// offset lane / 8, column offset lane % 8), adding w K(d) (times yhat_y or
+// yhat_z for channel 2 or 3) with LDS float atomics at Wf[idx(y, z)]. The
+// lanes of one atomic instruction never share an address, and no search or
+// workgroup barrier is involved. N must be a power of two.
+template <int N, class Idx>
+__device__ __forceinline__ void wave_splat(const SplatParams& p, bool hit, const WaveHit& h, int chan, float* Wf,
+                                           Idx idx) {
+  static_assert((N & (N - 1)) == 0, "wrap by mask");
+  const int lane = threadIdx.x & 63, ly = lane >> 3, lz = lane & 7;
+  const float fly = (float)ly, flz = (float)lz;
+  unsigned long long mask = __ballot(hit);
+  while (mask) {
+    const int i = __ffsll(mask) - 1;
+    mask &= mask - 1;
+    const int yb = __builtin_amdgcn_readlane(h.ybase, i), zb = __builtin_amdgcn_readlane(h.zbase, i);
+    const int syz = __builtin_amdgcn_readlane(h.syz, i);
+    const int sy = syz & 0xffff, sz = syz >> 16;
+    const float oy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h.offy), i));
+    const float oz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h.offz), i));
+    const float d2x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h.dx2), i));
+    const float cs = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h.c2s), i));
+    const float wk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h.w), i)) * p.inv1me0;
+    for (int by0 = 0; by0 < sy; by0 += 8) {
+      const float dy = fly + (oy + (float)by0);
+      const float dyy = fmaf(dy, dy, d2x);
+      const bool rowok = ly + by0 < sy;
+      for (int bz0 = 0; bz0 < sz; bz0 += 8) {
+        const float dz = flz + (oz + (float)bz0);
+        const float e = fmaf(dz, dz, dyy) * cs;  // d^2 / (2 s^2)
+        if (rowok && lz + bz0 < sz && e < p.sig_c) {  // inside the square and d < rho
+          const int yy = (yb + by0 + ly) & (N - 1), zz = (zb + bz0 + lz) & (N - 1);
+          float val = wk * (__expf(-e) - p.e0);
+          if (chan == 2) val *= yhat(yy, N);
+          if (chan == 3) val *= yhat(zz, N);
+          atomicAdd(&Wf[idx(yy, zz)], val);
+        }
+      }
+    }
+  }
+}
+
 // grid = (N planes, batch, NCH == 4 ? 3 : 1); block = 512. Splats the
-// binned samples of batch member blockIdx.y (p.rec) into plane x and writes
+// binned samples of batch member blockIdx.y (p.rec, p.cand) into plane x and writes
 // its 2D spectrum, out[((b*NCH + c)*N + x)*N*H]: with NCH = 4 workgroup z
 // splats channel pass z (u, then yhat_y u, then yhat_z u) and the u pass also
 // writes yhat_x u (u scaled by yhat(x)).
@@ -699,7 +806,6 @@ __global__ void __launch_bounds__(PlaneP<N>::THREADS, 4) k_plane_splat_fwd(Splat
   constexpr int H = P::H, L = P::L, R1 = P::R1, NB1 = P::NB1, T = N / 2;
   static_assert(P::R0 == 16 && R1 == 8 && L == 8 && NB1 == 2, "schedule of the code below");
   __shared__ __attribute__((aligned(16))) float2 W[P::SIZE];
-  __shared__ HitList hl;
   const int x = blockIdx.x, b = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tau = lane / L, l = lane % L;
   // stage-1 twiddles exp(-2 pi i r j / N), j = l + L bb (both transforms)
@@ -715,16 +821,25 @@ __global__ void __launch_bounds__(PlaneP<N>::THREADS, 4) k_plane_splat_fwd(Splat
   float2* dst1 = (NCH == 4 && chan == 0) ? out + (((size_t)b * NCH + 1) * N + x) * plane_sz : nullptr;
   const float s1 = yhat(x, N);
 
+  // splat: candidate c of the plane's runs is tested by lane c / WAVES of
+  // wave c % WAVES (the first round's loads overlap the zero fill), then each
+  // wave splats its own hits
+  SplatParams sp = p;
+  sp.inv1me0 *= 0.5f;  // the 1/2 of the two-for-one split
+  const int4 rg = p.cand[(size_t)b * N + x];
+  const Placed* rb = p.rec + (size_t)b * p.n_pts;
+  auto pidx = [](int yy, int zz) { return 2 * (P::al(yy & (T - 1)) + P::be(zz)) + (yy >= T ? 1 : 0); };
+  WaveHit h;
+  bool hit = wave_hit<N>(sp, rb, rg, lane * P::WAVES + wave, x, h);
   float4* W4 = reinterpret_cast<float4*>(W);
   for (int i = tid; i < P::SIZE / 2; i += P::THREADS) W4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
   __syncthreads();
-  {
-    SplatParams sp = p;
-    sp.inv1me0 *= 0.5f;  // the 1/2 of the two-for-one split
-    splat_plane<N, P::WAVES, P::THREADS>(sp, nullptr, b, x, chan, reinterpret_cast<float*>(W), hl,
-                                         [](int yy, int zz) {
-                                           return 2 * (P::al(yy & (T - 1)) + P::be(zz)) + (yy >= T ? 1 : 0);
-                                         });
+  float* Wf = reinterpret_cast<float*>(W);
+  for (int c0 = 0;;) {
+    wave_splat<N>(sp, hit, h, chan, Wf, pidx);
+    c0 += 64 * P::WAVES;
+    if (c0 >= rg.y + rg.w) break;  // uniform
+    hit = wave_hit<N>(sp, rb, rg, c0 + lane * P::WAVES + wave, x, h);
   }
   __syncthreads();
 

@@ -118,9 +118,10 @@ template <int N> struct Launch {
   static int nstrips() { return (T::C + G - 1) / G; }
   static int nsingle() { return (T::C + kSingleG - 1) / kSingleG; }
 
-  static void bin_samples(const SplatParams& sp, Placed* rec, int* off, float* rmax, int batch, hipStream_t s) {
+  static void bin_samples(const SplatParams& sp, Placed* rec, int* off, float* rmax, int4* cand, int batch,
+                          hipStream_t s) {
     // one workgroup per member: 1024 threads, as a batch has far fewer members than CUs
-    hipLaunchKernelGGL(k_bin_samples<N>, dim3(batch), dim3(1024), 0, s, sp, rec, off, rmax);
+    hipLaunchKernelGGL(k_bin_samples<N>, dim3(batch), dim3(1024), 0, s, sp, rec, off, rmax, cand);
   }
   // pass 1 from real grids (nch = 1) or from binned samples (nch = 1 or 4)
   static void plane_fwd(const SplatParams& sp, const float* grid, int nch, float2* out, int batch, const float2* tw,
@@ -354,13 +355,21 @@ inline int nlocal_of(int64_t n_pts) { return (int)((n_pts + kLocalSPB - 1) / kLo
 inline bool valid_sigma(float s) { return std::isfinite(s) && s > 0.0f; }
 
 // Workspace of the fused field path: batch spectra, then the binned samples
-// (records, bin offsets, largest radius per batch member).
+// (records, bin offsets, largest radius and per-plane candidate runs per
+// batch member), each part 16-byte aligned.
 inline size_t bin_offset(int n, int batch) { return (size_t)batch * spectrum_elems(n) * sizeof(float2); }
-inline size_t bin_bytes(int n, int batch, int64_t n_pts) {
-  const size_t rec = (size_t)batch * (size_t)n_pts * sizeof(Placed);
-  const size_t off = ((size_t)batch * (n + 1) * sizeof(int) + 15) / 16 * 16;
-  return rec + off + (size_t)batch * sizeof(float);
-}
+struct BinLayout {
+  size_t rec, off, rmax, cand, total;  // byte offsets from the start of the binned part
+  BinLayout(int n, int batch, int64_t n_pts) {
+    auto up = [](size_t v) { return (v + 15) / 16 * 16; };
+    rec = 0;
+    off = up((size_t)batch * (size_t)n_pts * sizeof(Placed));
+    rmax = off + up((size_t)batch * (n + 1) * sizeof(int));
+    cand = rmax + up((size_t)batch * sizeof(float));
+    total = cand + (size_t)batch * n * sizeof(int4);
+  }
+};
+inline size_t bin_bytes(int n, int batch, int64_t n_pts) { return BinLayout(n, batch, n_pts).total; }
 
 inline SplatParams make_splat(const float* xyzr, const float* w, int64_t n_pts, const float* Rdev, const float* hR,
                        const float* hc, float sigma) {
@@ -368,6 +377,7 @@ inline SplatParams make_splat(const float* xyzr, const float* w, int64_t n_pts, 
   p.rec = nullptr;
   p.off = nullptr;
   p.rmax = nullptr;
+  p.cand = nullptr;
   p.xyzr = reinterpret_cast<const float4*>(xyzr);
   p.w = w;
   p.n_pts = n_pts;

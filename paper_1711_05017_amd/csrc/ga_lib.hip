@@ -398,10 +398,11 @@ ga_status ga_energy_fields(const ga_plan* plan, const float* d_Ahat, const float
     return launch_status();
   }
   char* bins = static_cast<char*>(d_work) + bin_offset(n, batch);
-  Placed* rec = reinterpret_cast<Placed*>(bins);
-  int* off = reinterpret_cast<int*>(bins + (size_t)batch * (size_t)n_pts * sizeof(Placed));
-  float* rmax = reinterpret_cast<float*>(reinterpret_cast<char*>(off) +
-                                         ((size_t)batch * (n + 1) * sizeof(int) + 15) / 16 * 16);
+  const BinLayout bl(n, batch, n_pts);
+  Placed* rec = reinterpret_cast<Placed*>(bins + bl.rec);
+  int* off = reinterpret_cast<int*>(bins + bl.off);
+  float* rmax = reinterpret_cast<float*>(bins + bl.rmax);
+  int4* cand = reinterpret_cast<int4*>(bins + bl.cand);
   // chunked, two-stream execution (ga_plan_set_overlap); one stream under
   // graph capture
   int chunks = std::min(plan->chunks, (int)batch);
@@ -427,14 +428,16 @@ ga_status ga_energy_fields(const ga_plan* plan, const float* d_Ahat, const float
       Placed* rc = rec + (size_t)c0 * (size_t)n_pts;
       int* oc = off + (size_t)c0 * (N + 1);
       float* mc = rmax + c0;
+      int4* cc = cand + (size_t)c0 * N;
       float2* tc = tmp + (size_t)c0 * spectrum_elems(n);
       {
         ProfScope pb(plan, GA_K_BIN, sc);
-        Launch<N>::bin_samples(spc, rc, oc, mc, nb, sc);
+        Launch<N>::bin_samples(spc, rc, oc, mc, cc, nb, sc);
       }
       spc.rec = rc;
       spc.off = oc;
       spc.rmax = mc;
+      spc.cand = cc;
       {
         ProfScope ps(plan, GA_K_PLANE_FWD, sc);
         Launch<N>::plane_fwd(spc, nullptr, 1, tc, nb, plan->d_tw, sc);

@@ -18,6 +18,7 @@
 #include <cmath>
 #include <condition_variable>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <memory>
@@ -74,6 +75,7 @@ struct Group {
   Placed* rec = nullptr;
   int* off = nullptr;
   float* rmax = nullptr;
+  int4* cand = nullptr;
   float2* spec4 = nullptr;  // slots x 4 spectra (x not yet transformed)
   double* part = nullptr;
   std::vector<Pending> batch;
@@ -105,15 +107,15 @@ size_t group_bytes(uint32_t mode, int n, int slots, int64_t max_pts) {
   const size_t spec = spectrum_elems(n) * sizeof(float2);
   const size_t nblk = (size_t)nstrips_of(n);
   return common + (size_t)slots * (4 * spec + (size_t)max_pts * sizeof(Placed) + (size_t)(n + 1) * sizeof(int) +
-                                   sizeof(float) + nblk * 7 * sizeof(double));
+                                   sizeof(float) + (size_t)n * sizeof(int4) + nblk * 7 * sizeof(double));
 }
 
 void free_group(Group& g) {
   if (g.stream) (void)hipStreamSynchronize(g.stream);
   if (g.h_items) (void)hipHostFree(g.h_items);
   if (g.h_out) (void)hipHostFree(g.h_out);
-  for (void* p : {(void*)g.d_items, (void*)g.d_out, (void*)g.rec, (void*)g.off, (void*)g.rmax, (void*)g.spec4,
-                  (void*)g.part})
+  for (void* p : {(void*)g.d_items, (void*)g.d_out, (void*)g.rec, (void*)g.off, (void*)g.rmax, (void*)g.cand,
+                  (void*)g.spec4, (void*)g.part})
     if (p) (void)hipFree(p);
   if (g.done) (void)hipEventDestroy(g.done);
   if (g.stream) (void)hipStreamDestroy(g.stream);
@@ -135,6 +137,7 @@ bool alloc_group(Group& g, uint32_t mode, int n, int slots, int64_t max_pts) {
     ok = hipMalloc(&g.rec, sizeof(Placed) * (size_t)max_pts * slots) == hipSuccess &&
          hipMalloc(&g.off, sizeof(int) * (size_t)(n + 1) * slots) == hipSuccess &&
          hipMalloc(&g.rmax, sizeof(float) * slots) == hipSuccess &&
+         hipMalloc(&g.cand, sizeof(int4) * (size_t)n * slots) == hipSuccess &&
          hipMalloc(&g.spec4, sizeof(float2) * spec * 4 * slots) == hipSuccess &&
          hipMalloc(&g.part, sizeof(double) * nblk * 7 * slots) == hipSuccess;
   }
@@ -187,6 +190,23 @@ struct ga_server {
       if (q) (void)hipFree(q);
     bytes -= p.bytes;
   }
+  // After a sticky error nothing is launched any more: every queued query
+  // is dropped (its ticket then polls as the sticky error), so that the
+  // scheduler can drain and ga_server_destroy return (caller holds mu).
+  void fail_queued_locked() {
+    for (auto& cp : classes) {
+      for (const Pending& q : cp->queue) {
+        auto pit = pairs.find(q.pair);
+        if (pit != pairs.end() && --pit->second.inflight == 0 && pit->second.released) {
+          free_pair_locked(pit->second);
+          pairs.erase(pit);
+        }
+      }
+      queued -= (int)cp->queue.size();
+      cp->queue.clear();
+    }
+    stats.pairs = (int32_t)pairs.size();
+  }
   void run();
   void launch(SizeClass& c, Group& g);
 };
@@ -230,11 +250,12 @@ void ga_server::launch(SizeClass& c, Group& g) {
     dispatch(n, [&]<int N>() {
       using L = Launch<N>;
       hipLaunchKernelGGL(k_bin_items<N>, dim3(k), dim3(256), 0, g.stream, g.d_items, base, (long long)c.max_pts, g.rec,
-                         g.off, g.rmax);
+                         g.off, g.rmax, g.cand);
       SplatParams sp = base;
       sp.rec = g.rec;
       sp.off = g.off;
       sp.rmax = g.rmax;
+      sp.cand = g.cand;
       sp.n_pts = c.max_pts;
       L::plane_splat(sp, 4, g.spec4, k, tw, g.stream);
       hipLaunchKernelGGL((k_strip_single<N, L::G>), dim3(L::nstrips(), k), dim3(L::T::THREADS), 0, g.stream,
@@ -253,6 +274,7 @@ void ga_server::run() {
     std::vector<std::pair<SizeClass*, Group*>> busy;
     {
       std::unique_lock<std::mutex> lk(mu);
+      if (sticky != GA_OK && queued > 0) fail_queued_locked();
       if (queued == 0 && busy_groups == 0) {
         if (stop) break;
         cv.wait_for(lk, std::chrono::milliseconds(20));
@@ -418,7 +440,10 @@ ga_status ga_pair_register(ga_server* s, const ga_part* A, const ga_part* B, con
         std::this_thread::sleep_for(std::chrono::microseconds(100));
         lk.lock();
       }
-      bool ok = true;
+      // GA_TEST_FAIL_REGROW=1 makes this reallocation report failure
+      // without allocating (a host-side test of the sticky-error path)
+      const char* fail = std::getenv("GA_TEST_FAIL_REGROW");
+      bool ok = !(fail && fail[0] == '1');
       for (int gi = 0; gi < c->ngroups; ++gi) {
         free_group(c->groups[gi]);
         ok = ok && alloc_group(c->groups[gi], s->mode, n, c->slots, B->n_pts);
