@@ -169,3 +169,105 @@ def test_local_and_spectral_modes_agree(G):
     assert O.rel_l2(out["local"][:, 0], out["spectral"][:, 0]) < FIELD_TOL
     assert O.rel_l2(out["local"][:, 1:4], out["spectral"][:, 1:4]) < FORCE_TOL
     assert O.rel_l2(out["local"][:, 4:7], out["spectral"][:, 4:7]) < FORCE_TOL
+
+
+def _oracle_queries(A, B, n, rots, ts, sigma=0.5):
+    """(E, F, tau) of each query (rotation of B about its reference point,
+    translation rounded half away from zero) by the oracle's single-pose sums
+    with the spectral gradient of u_A computed once."""
+    uA = O.splat(A.xyzr[:, :3].astype(np.float64), A.xyzr[:, 3], A.w, n, sigma)
+    g = O.grad_spectral(uA)
+    out = []
+    for R, t in zip(rots, ts):
+        uB = O.splat(O.place(B.xyzr[:, :3], R, B.ref_point()), B.xyzr[:, 3], B.w, n, sigma)
+        t_lat = [np.floor(abs(v) + 0.5) * np.sign(v) for v in t]
+        out.append(O.local_pose_sum(uA, uB, t_lat, grad=g))
+    return np.array(out)
+
+
+@pytest.mark.timeout(900)
+@MODES
+def test_served_grid_sizes_match_oracle_alone_and_in_the_mix(G, mode):
+    """The serving workload's grid sizes 96, 128 and 192 (64 is covered
+    above), parts of 500-5000 samples with radii U[1,4]: two queries per size
+    alone against the oracle, then the same queries again among 150 queries
+    of the three sizes in flight together."""
+    srv = G.Server(max_slots=8, queue_depth=1024, mode=_mode(G, mode))
+    try:
+        pairs = {}
+        for i, (n, npts) in enumerate(((96, 600), (128, 2500), (192, 5000))):
+            A = synth.random_part(300 + i, n, npts, 1.0, 4.0, conf_radius=n / 4)
+            B = synth.random_part(350 + i, n, max(500, npts // 2), 1.0, 4.0, conf_radius=n / 6)
+            rots = synth.shoemake_rotations(400 + i, 2)
+            ts = [[n / 2 + 1.4, n / 2 - 2.0, n / 2 + 0.6], [n / 2 - 3.0, n / 2 + 2.5, n / 2]]
+            pid = srv.register_pair(A.xyzr, A.w, B.xyzr, B.w, B.ref_point(), n)
+            pairs[n] = (pid, rots, ts, _oracle_queries(A, B, n, rots, ts))
+        alone = {}
+        for n, (pid, rots, ts, ref) in pairs.items():
+            got = np.array([srv.wait(srv.submit(pid, rots[q], ts[q])).values() for q in range(2)], np.float64)
+            assert np.abs(ref[:, 0]).max() > 0 and np.abs(ref[:, 1:]).max() > 0
+            assert O.rel_l2(got[:, 0], ref[:, 0]) < FIELD_TOL, n
+            assert O.rel_l2(got[:, 1:4], ref[:, 1:4]) < FORCE_TOL, n
+            assert O.rel_l2(got[:, 4:7], ref[:, 4:7]) < FORCE_TOL, n
+            alone[n] = got
+        rng = np.random.default_rng(9)
+        others = synth.shoemake_rotations(450, 150)
+        sizes = list(pairs)
+        probes, tickets = {}, []
+        for q in range(150):
+            if q in (40, 41, 80, 81, 120, 121):
+                n = sizes[(q - 40) // 40]
+                pid, rots, ts, _ = pairs[n]
+                probes[(n, q % 2)] = srv.submit(pid, rots[q % 2], ts[q % 2])
+            n = sizes[rng.integers(3)]
+            tickets.append(srv.submit(pairs[n][0], others[q], n / 2 + rng.integers(-3, 4, 3)))
+        for (n, q), tk in probes.items():
+            mixed = np.array(srv.wait(tk).values(), np.float64)
+            assert O.rel_l2(mixed[0:1], alone[n][q, 0:1]) < FIELD_TOL, (n, q)
+            assert O.rel_l2(mixed[1:4], alone[n][q, 1:4]) < FORCE_TOL, (n, q)
+            assert O.rel_l2(mixed[4:7], alone[n][q, 4:7]) < FORCE_TOL, (n, q)
+        for tk in tickets:
+            srv.wait(tk)
+    finally:
+        srv.close()
+
+
+def test_sticky_error_drops_queued_queries_and_close_returns(G):
+    """A failed scratch reallocation (forced from the host with
+    GA_TEST_FAIL_REGROW=1, nothing is launched) makes the server's error
+    sticky: queries still queued are dropped and poll with that error, later
+    calls return it, and close() returns."""
+    import os
+    import time
+
+    srv = G.Server(max_slots=4, queue_depth=8192, mode=G.GA_SERVE_LOCAL)
+    closed = False
+    try:
+        A, B = _pair(32, 61, 50)
+        pid = srv.register_pair(A.xyzr, A.w, B.xyzr, B.w, B.ref_point(), 32)
+        I = np.eye(3)
+        tks = [srv.submit(pid, I, [16, 16, 16]) for _ in range(3000)]
+        A2, B2 = _pair(32, 63, 120)  # more samples than the size class holds: regrow
+        os.environ["GA_TEST_FAIL_REGROW"] = "1"
+        try:
+            with pytest.raises(G.GaError):
+                srv.register_pair(A2.xyzr, A2.w, B2.xyzr, B2.w, B2.ref_point(), 32)
+        finally:
+            del os.environ["GA_TEST_FAIL_REGROW"]
+        with pytest.raises(G.GaError):
+            srv.submit(pid, I, [16, 16, 16])
+        done = failed = 0
+        for tk in tks:
+            try:
+                res = srv.poll(tk)
+                done += res is not None
+            except G.GaError:
+                failed += 1
+        assert done + failed > 0
+        t0 = time.time()
+        srv.close()
+        closed = True
+        assert time.time() - t0 < 30
+    finally:
+        if not closed:
+            srv.close()
