@@ -50,6 +50,7 @@ COUNTER_VALU = {
     "insts": {"plane_fwd": 110347150, "plane_inv": 58425344},
 }
 VALU_ISSUE_PER_S = 256 * 2.4e9  # CUs x clock: one wave64 VALU instruction per CU per cycle
+COPY_GBPS = 5390.0  # plain 512 MiB device copy, read + write (rocprofv3 calibration on the MI355X)
 KERNEL_SOURCES = ("ga_fft.hpp", "ga_kernels.hpp", "ga_launch.hpp")
 
 
@@ -78,19 +79,35 @@ def valu_issue(kernel, ms):
 
 
 def algorithmic_bytes(n, batch, n_pts):
-    """Bytes each kernel of the field path must move per launch:
+    """Bytes each kernel of the field path must move per launch, per field
+    as the method is stated (40H + 4 n^3 per field for the three passes):
     the binning pre-pass reads the samples (20 B each) and writes one placed
-    record (32 B) per sample and field, pass 1 writes the plane spectra (8H),
-    pass 2 reads them and the resident spectrum and writes the product after
-    the inverse x transform (24H), pass 3 reads it and writes the field
-    (8H + 4 n^3). H = n^2 (n/2 + 1) complex elements."""
+    record (32 B) per sample and field and the candidate runs of every plane
+    (16 B), pass 1 writes the plane spectra (8H), pass 2 reads them and the
+    resident spectrum and writes the product after the inverse x transform
+    (24H), pass 3 reads it and writes the field (8H + 4 n^3).
+    H = n^2 (n/2 + 1) complex elements. Pass 2 reads the shared resident
+    spectrum once per group of members (counted traffic about 18H per
+    field)."""
     H = n * n * (n // 2 + 1)
     return {
-        "bin": batch * n_pts * (20 + 32),
+        "bin": batch * (n_pts * (20 + 32) + 16 * n),
         "plane_fwd": batch * 8 * H,
         "strip": batch * 24 * H,
         "plane_inv": batch * (8 * H + 4 * n ** 3),
     }
+
+
+def roofline_bound(kernel, ms, traffic):
+    """What bounds a kernel by the committed counters: 'alu' when its VALU
+    issue floor is a larger share of its time than its counted HBM traffic at
+    the measured plain-copy rate, else 'hbm' (also when no counters describe
+    the current sources)."""
+    v = valu_issue(kernel, ms)
+    if v is None or traffic is None:
+        return "hbm"
+    hbm_share = traffic / (COPY_GBPS * 1e9) / (ms * 1e-3)
+    return "alu" if v["frac"] > hbm_share else "hbm"
 
 
 def cpu_baseline(a, budget_s=12.0):
@@ -115,6 +132,55 @@ def cpu_baseline(a, budget_s=12.0):
     return {"value": done / dt, "unit": "fields/s", "cores": 1, "kind": "oracle",
             "sample": f"{done} of the 64 rotations at {n}^3 (float64 splat, own radix-2/3 FFT, product, inverse FFT; "
                       f"single-threaded numpy), {dt:.1f} s"}
+
+
+def host_cpu():
+    """Core count and model of the host the benchmark runs on."""
+    model = None
+    try:
+        import subprocess
+
+        for line in subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except Exception:  # lscpu missing: the count alone
+        pass
+    return {"cpu_count": os.cpu_count(), "model": model,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def cpu_fast_baseline(a, fields=4):
+    """A fast CPU pipeline beside the oracle: the oracle's float64 splat of
+    the rotated moving part, then scipy.fft (pocketfft) rfftn, the conjugate
+    product with the resident spectrum and irfftn with workers = all host
+    workers, in float32 and in float64. Fields per second over `fields`
+    rotations, and the share of the transforms. The worker count is the
+    process's CPU share (OMP_NUM_THREADS where set, else all cores)."""
+    import numpy as np
+    import scipy
+    import scipy.fft as sf
+
+    import oracle as O
+
+    n = a.n
+    workers = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count())
+    uA = O.splat(a.A.xyzr[:, :3].astype(np.float64), a.A.xyzr[:, 3], a.A.w, n, a.sigma)
+    out = {"library": f"scipy {scipy.__version__} (pocketfft)", "workers": workers, "fields": fields}
+    for name, dt in (("f32", np.float32), ("f64", np.float64)):
+        Ah = sf.rfftn(uA.astype(dt), workers=workers)
+        t_splat = t_fft = 0.0
+        for r in range(fields):
+            t0 = time.perf_counter()
+            uB = O.splat(O.place(a.B.xyzr[:, :3], a.rotations[r], a.cB), a.B.xyzr[:, 3], a.B.w, n, a.sigma)
+            t1 = time.perf_counter()
+            E = sf.irfftn(Ah * np.conj(sf.rfftn(uB.astype(dt), workers=workers)), s=(n, n, n), workers=workers)
+            t2 = time.perf_counter()
+            assert E.shape == (n, n, n)
+            t_splat += t1 - t0
+            t_fft += t2 - t1
+        out[name] = {"fields_per_s": round(fields / (t_splat + t_fft), 2),
+                     "transform_fields_per_s": round(fields / t_fft, 2), "splat_s_per_field": round(t_splat / fields, 3)}
+    return out
 
 
 def serving_leg(n_queries, rate_hz, max_slots=8, mode="local"):
@@ -225,6 +291,29 @@ def graph_leg(G, synth, np, torch, dev, chunks=1, reps=20):
     out = {"c3_one_graph": dict(run([c3]), parts=chunks)}
     mixed = [item(64, 710, 16, 1000), item(96, 720, 16, 1500), item(128, 730, 16, 2000), item(192, 740, 16, 3000)]
     out["mixed_64_96_128_192"] = run(mixed)
+
+    def eager(items):  # the same items as separate calls on one stream
+        outs = [torch.empty((int(it["R"].shape[0]),) + (it["plan"].n,) * 3, dtype=torch.float32, device=dev)
+                for it in items]
+        works = [it["plan"].workspace(G.ga.GA_OP_ENERGY, int(it["R"].shape[0]), int(it["xyzr"].shape[0]))
+                 for it in items]
+
+        def once():
+            for it, o, w in zip(items, outs, works):
+                G.ga_energy_fields(it["plan"], it["Ahat"], it["xyzr"], it["w"], it["R"], it["c"], it["sigma"], out=o,
+                                   work=w)
+        for _ in range(3):
+            once()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            once()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        nf = sum(int(it["R"].shape[0]) for it in items)
+        return {"fields_per_s": round(nf * reps / dt, 1), "ms_per_call_set": round(dt * 1000 / reps, 4), "fields": nf}
+
+    out["mixed_64_96_128_192_eager_calls"] = eager(mixed)
     return out
 
 
@@ -264,9 +353,45 @@ def c4_leg(G, synth, np, torch, dev, reps=3):
             e1.synchronize()
             t.append(e0.elapsed_time(e1))
         ms[name] = round(sorted(t)[len(t) // 2], 3)
+    # algorithmic bytes of the whole readout on the separate-axis path (splats,
+    # the R2C of A and of the 4 channels of B, 7 products with their C2R
+    # transforms and the gather): about 360H + 44 n^3
+    H = n * n * (n // 2 + 1)
+    nbytes = 360 * H + 44 * n ** 3
+    total = sum(ms.values())
+    gbps = nbytes / (total * 1e-3) / 1e9
     return {"grid": n, "samples_per_part": int(a.A.n), "poses": int(len(a.poses)), "stage_ms": ms,
-            "total_ms": round(sum(ms.values()), 3),
+            "total_ms": round(total, 3), "algorithmic_bytes": int(nbytes), "GBps": round(gbps, 1),
+            "hbm_frac": round(gbps / HBM_PEAK_GBPS, 4),
             "peak_device_GB": round(torch.cuda.max_memory_allocated() / 1e9, 2)}
+
+
+def batch_leg(G, synth, np, torch, dev, batch, chunks, steps=10):
+    """The 128^3 workload with `batch` rotations per call (a working set well
+    above the 256 MB Infinity Cache at 256): fields/s over `steps` calls."""
+    a = synth.config_c3(batch)
+    n = a.n
+    plan = G.Plan(n, max_batch=batch)
+    plan.set_overlap(chunks)
+    xb, wb = torch.from_numpy(a.B.xyzr).to(dev), torch.from_numpy(a.B.w).to(dev)
+    R = torch.from_numpy(np.ascontiguousarray(a.rotations.reshape(batch, 9))).to(dev)
+    Ahat = G.ga_fft3d(plan, G.GA_R2C, G.ga_splat(plan, torch.from_numpy(a.A.xyzr).to(dev),
+                                                 torch.from_numpy(a.A.w).to(dev), sigma=a.sigma))[0].contiguous()
+    E = torch.empty((batch, n, n, n), dtype=torch.float32, device=dev)
+    work = plan.workspace(G.ga.GA_OP_ENERGY, batch, a.B.n, device=dev)
+    for _ in range(2):
+        G.ga_energy_fields(plan, Ahat, xb, wb, R, a.cB, a.sigma, out=E, work=work)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        G.ga_energy_fields(plan, Ahat, xb, wb, R, a.cB, a.sigma, out=E, work=work)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    H = n * n * (n // 2 + 1)
+    fps = batch * steps / dt
+    plan.close()
+    return {"batch": batch, "parts": chunks, "fields_per_s": round(fps, 1), "ms_per_call": round(dt * 1000 / steps, 4),
+            "path_GBps_algorithmic": round(fps * (40 * H + 4 * n ** 3) / 1e9, 1)}
 
 
 def next_rows_leg(G, synth, np, torch, dev, reps=20):
@@ -347,9 +472,12 @@ def main():
     ap.add_argument("--no-next", action="store_true", help="skip the low-pass / rotation / score / table leg")
     ap.add_argument("--serving-queries", type=int, default=100000)
     ap.add_argument("--serving-rate", type=float, default=16000.0)
-    ap.add_argument("--serving-mode", choices=["local", "spectral"], default="local",
-                    help="how the server evaluates a query: local sums over the moving part's balls, or its "
-                         "splat + R2C + single-translation spectral sum")
+    ap.add_argument("--serving-mode", choices=["local", "spectral", "both"], default="both",
+                    help="how the server evaluates a query: local sums over the moving part's balls, its "
+                         "splat + R2C + single-translation spectral sum (the re-correlation per query), or both "
+                         "legs in turn")
+    ap.add_argument("--spectral-queries", type=int, default=40000, help="queries of the spectral serving leg")
+    ap.add_argument("--no-batch256", action="store_true")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB, three times (the known-size "
                          "kernel that scales the HBM byte counters)")
@@ -473,9 +601,12 @@ def main():
                      "xcd_aware_grid": tuned[2] == 1,
                      "candidates_us": {f"{'xcd' if x == 1 else 'plain'}/{g}x{k}": v
                                        for (g, k, x), v in tune_us.items()}},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+        "roofline": {"bound": roofline_bound(dom, kern[dom], counter_traffic(dom)), "kernel": dom,
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": counter_traffic(dom),
                      "algorithmic_bytes_per_launch": abytes[dom],
+                     "counted_GBps": (round(counter_traffic(dom) / (kern[dom] * 1e-3) / 1e9, 1)
+                                      if counter_traffic(dom) is not None else None),
                      "valu_issue": valu_issue(dom, kern[dom]),
                      "timing": f"HIP events on the launch stream, {args.roofline_steps} one-stream steps of the "
                                f"same call after the timed region"},
@@ -487,7 +618,15 @@ def main():
     plan.close()
     if not args.no_serving:
         torch.cuda.empty_cache()
-        out["serving"] = serving_leg(args.serving_queries, args.serving_rate, mode=args.serving_mode)
+        if args.serving_mode in ("local", "both"):
+            out["serving"] = serving_leg(args.serving_queries, args.serving_rate, mode="local")
+        if args.serving_mode in ("spectral", "both"):
+            key = "serving_spectral" if args.serving_mode == "both" else "serving"
+            nq = args.spectral_queries if args.serving_mode == "both" else args.serving_queries
+            out[key] = serving_leg(nq, args.serving_rate, mode="spectral")
+    if not args.no_batch256:
+        out["batch_256"] = batch_leg(G, synth, np, torch, dev, 256, best_chunks)
+        torch.cuda.empty_cache()
     if not args.no_graph:
         out["graph"] = graph_leg(G, synth, np, torch, dev, chunks=best_chunks)
     if not args.no_c4:
@@ -497,6 +636,8 @@ def main():
         out["next_rows"] = next_rows_leg(G, synth, np, torch, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a)
+        out["cpu_baseline"]["host"] = host_cpu()
+        out["cpu_fast_baseline"] = cpu_fast_baseline(a)
     print(json.dumps(out), flush=True)
 
 

@@ -279,9 +279,10 @@ ga_status ga_pose_local(const ga_plan* plan, const float* d_FA4, const float* d_
                         float* d_out7, void* d_work, size_t work_bytes, hipStream_t stream);
 
 /*
- * Field tables for motion restricted to a set of orientations (Sec. 4.3:
- * with the orientation fixed the correlation is precomputed once and read
- * at every frame). ga_field_table writes, for each orientation o, the 7
+ * Field tables for motion restricted to a set of orientations (Sec. 4.2,
+ * "Restricted Motion DOF": with the orientation fixed the correlation is
+ * precomputed once and read at every frame; the experiment of Sec. 4.3 runs
+ * translation-only). ga_field_table writes, for each orientation o, the 7
  * fields (E, F_x, F_y, F_z, tau_x, tau_y, tau_z over all translations, as
  * ga_force_torque GA_FIELDS) to d_tables + o * 8 * n^3 as one 32-byte record
  * per voxel (float32 [o][x][y][z][8]: the 7 fields, then 0; 32 n^3 bytes per

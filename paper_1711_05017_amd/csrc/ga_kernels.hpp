@@ -609,9 +609,100 @@ __device__ __forceinline__ void plane_from_global(float2* W, const float2* __res
   });
 }
 
+// One hit of the per-wave splat below: the bounding square of the sample's
+// disk in the plane, rows ybase .. ybase + sy - 1 and columns zbase ..
+// zbase + sz - 1 (voxel indices, not yet reduced mod N), the offsets of its
+// first row and column from the disk centre, dx^2 and 1/(2 s^2).
+struct WaveHit {
+  int ybase, zbase, syz;  // syz = sy | sz << 16
+  float offy, offz, dx2, c2s, w;
+};
+
+// Candidate c of the plane's candidate runs rg (false beyond them).
+__device__ __forceinline__ bool wave_cand(const Placed* rb, int4 rg, int c, Placed& q) {
+  if (c >= rg.y + rg.w) return false;
+  q = rb[c < rg.y ? rg.x + c : rg.z + (c - rg.y)];
+  return true;
+}
+
+// Hit test of a candidate against plane x: false for a sample that misses
+// the plane.
+template <int N>
+__device__ __forceinline__ bool wave_hit(const SplatParams& p, const Placed& q, int x, WaveHit& h) {
+  int m = x - q.b.x;
+  m = (m >= N / 2) ? m - N : m;
+  m = (m < -N / 2) ? m + N : m;
+  float dx = (float)m - q.a.x;
+  dx = (dx < -0.5f * N) ? dx + (float)N : dx;
+  h.w = __int_as_float(q.b.w);
+  const float rho = q.a.w;
+  if (!(fabsf(dx) < rho) || h.w == 0.0f) return false;
+  const float rd = sqrtf(fmaxf(rho * rho - dx * dx, 0.0f));
+  const int ylo = (int)ceilf(q.a.y - rd), yhi = (int)floorf(q.a.y + rd);
+  const int zlo = (int)ceilf(q.a.z - rd), zhi = (int)floorf(q.a.z + rd);
+  const int sy = yhi - ylo + 1, sz = zhi - zlo + 1;
+  if (sy <= 0 || sz <= 0) return false;
+  h.ybase = q.b.y + ylo;
+  h.zbase = q.b.z + zlo;
+  h.syz = sy | (sz << 16);
+  h.offy = (float)ylo - q.a.y;
+  h.offz = (float)zlo - q.a.z;
+  h.dx2 = dx * dx;
+  h.c2s = p.sig_c / (rho * rho);
+  return true;
+}
+
+// Splat of the hits one wavefront found (flag `hit`, parameters `h` in each
+// lane): the wave takes them one at a time, broadcast from their lanes, and
+// its 64 lanes cover 8 x 8 blocks of the hit's bounding square (lane = row
+// offset lane / 8, column offset lane % 8), adding w K(d) (times yhat_y or
+// yhat_z for channel 2 or 3) with LDS float atomics at Wf[idx(y, z)]. The
+// lanes of one atomic instruction never share an address, and no search or
+// workgroup barrier is involved.
+template <int N>
+__device__ __forceinline__ int wrap_axis(int v) {  // v in [-N, 2N)
+  if constexpr ((N & (N - 1)) == 0) return v & (N - 1);
+  else return wrapn(v, N);
+}
+template <int N, class Idx>
+__device__ __forceinline__ void wave_splat(const SplatParams& p, bool hit, const WaveHit& h, int chan, float* Wf,
+                                           Idx idx) {
+  const int lane = threadIdx.x & 63, ly = lane >> 3, lz = lane & 7;
+  const float fly = (float)ly, flz = (float)lz;
+  unsigned long long mask = __ballot(hit);
+  while (mask) {
+    const int i = __ffsll(mask) - 1;
+    mask &= mask - 1;
+    const int yb = __builtin_amdgcn_readlane(h.ybase, i), zb = __builtin_amdgcn_readlane(h.zbase, i);
+    const int syz = __builtin_amdgcn_readlane(h.syz, i);
+    const int sy = syz & 0xffff, sz = syz >> 16;
+    const float oy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h.offy), i));
+    const float oz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h.offz), i));
+    const float d2x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h.dx2), i));
+    const float cs = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h.c2s), i));
+    const float wk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h.w), i)) * p.inv1me0;
+    for (int by0 = 0; by0 < sy; by0 += 8) {
+      const float dy = fly + (oy + (float)by0);
+      const float dyy = fmaf(dy, dy, d2x);
+      const bool rowok = ly + by0 < sy;
+      for (int bz0 = 0; bz0 < sz; bz0 += 8) {
+        const float dz = flz + (oz + (float)bz0);
+        const float e = fmaf(dz, dz, dyy) * cs;  // d^2 / (2 s^2)
+        if (rowok && lz + bz0 < sz && e < p.sig_c) {  // inside the square and d < rho
+          const int yy = wrap_axis<N>(yb + by0 + ly), zz = wrap_axis<N>(zb + bz0 + lz);
+          float val = wk * (__expf(-e) - p.e0);
+          if (chan == 2) val *= yhat(yy, N);
+          if (chan == 3) val *= yhat(zz, N);
+          atomicAdd(&Wf[idx(yy, zz)], val);
+        }
+      }
+    }
+  }
+}
+
 // Pass 1. grid = (N planes, batch, NCH == 4 ? 3 : 1). GRID: real grids
 // `grid` [batch][N^3] (NCH = 1). Otherwise splat from the binned samples
-// (p.rec) of each batch member; with NCH = 4 workgroup z splats channel
+// (p.rec, p.cand) of each batch member; with NCH = 4 workgroup z splats channel
 // pass z (u, then yhat_y u, then yhat_z u; yhat_x u is u scaled per plane). Writes NCH spectra planes per batch member,
 // out[((b*NCH + c)*N + x)*N*H]: u, and with NCH = 4 the moment densities
 // yhat_x u, yhat_y u, yhat_z u.
@@ -622,7 +713,6 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_fwd
                                                                                const float2* __restrict__ table) {
   using P = Plane<N>;
   __shared__ __attribute__((aligned(16))) float2 W[P::SIZE];
-  __shared__ std::conditional_t<GRID, int, HitList> hl;  // hit list only when splatting
   const int x = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
   float* Wf = reinterpret_cast<float*>(W);
   const size_t plane_sz = (size_t)N * P::H;
@@ -642,12 +732,36 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_fwd
         Wf[P::zs(y >> 1, z + 1) * 2 + (y & 1)] = v.y;
       });
     } else {
+      // binned samples (p.rec, p.cand): each wavefront tests its candidates
+      // and splats its hits (wave_splat); a plane no sample reaches has a
+      // zero spectrum, written directly
+      const int4 rg = p.cand[(size_t)b * N + x];
+      const int ncand = rg.y + rg.w;
+      const Placed* rb = p.rec + (size_t)b * p.n_pts;
+      const int lane = tid & 63, wave = tid >> 6;
+      auto pidx = [](int yy, int zz) { return P::zs(yy >> 1, zz) * 2 + (yy & 1); };
+      Placed q;
+      const bool is_cand = wave_cand(rb, rg, lane * P::WAVES + wave, q);
       float4* W4 = reinterpret_cast<float4*>(W);
       for (int i = tid; i < P::SIZE / 2; i += P::THREADS) W4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-      __syncthreads();
-      splat_plane<N, P::WAVES, P::THREADS>(p, nullptr, b, x, chan, Wf, hl, [](int yy, int zz) {
-        return P::zs(yy >> 1, zz) * 2 + (yy & 1);
-      });
+      WaveHit h;
+      bool hit = is_cand && wave_hit<N>(p, q, x, h);
+      if (!__syncthreads_or(hit) && ncand <= 64 * P::WAVES) {
+        float4* d0 = reinterpret_cast<float4*>(dst0);
+        float4* d1 = reinterpret_cast<float4*>(dst1);
+        for (int i = tid; i < (int)(plane_sz / 2); i += P::THREADS) {
+          d0[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (dst1) d1[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        return;
+      }
+      for (int c0 = 0;;) {
+        wave_splat<N>(p, hit, h, chan, Wf, pidx);
+        c0 += 64 * P::WAVES;
+        if (c0 >= ncand) break;  // uniform
+        const bool more = wave_cand(rb, rg, c0 + lane * P::WAVES + wave, q);
+        hit = more && wave_hit<N>(p, q, x, h);
+      }
     }
     __syncthreads();
     {
@@ -712,99 +826,18 @@ static_assert(PlaneP<128>::be(127) < PlaneP<128>::S, "rows do not overlap");
 static_assert(PlaneP<128>::al(63) + PlaneP<128>::be(127) < PlaneP<128>::SIZE && PlaneP<128>::SIZE % 2 == 0,
               "plane slots");
 
-// One hit of the per-wave splat below: the bounding square of the sample's
-// disk in the plane, rows ybase .. ybase + sy - 1 and columns zbase ..
-// zbase + sz - 1 (voxel indices, not yet reduced mod N), the offsets of its
-// first row and column from the disk centre, dx^2 and 1/(2 s^2).
-struct WaveHit {
-  int ybase, zbase, syz;  // syz = sy | sz << 16
-  float offy, offz, dx2, c2s, w;
-};
-
-// Hit test of candidate c (of the plane's candidate runs rg) against plane
-// x; false for c beyond the runs or a sample that misses the plane.
-template <int N>
-__device__ __forceinline__ bool wave_hit(const SplatParams& p, const Placed* rb, int4 rg, int c, int x, WaveHit& h) {
-  if (c >= rg.y + rg.w) return false;
-  const Placed q = rb[c < rg.y ? rg.x + c : rg.z + (c - rg.y)];
-  int m = x - q.b.x;
-  m = (m >= N / 2) ? m - N : m;
-  m = (m < -N / 2) ? m + N : m;
-  float dx = (float)m - q.a.x;
-  dx = (dx < -0.5f * N) ? dx + (float)N : dx;
-  h.w = __int_as_float(q.b.w);
-  const float rho = q.a.w;
-  if (!(fabsf(dx) < rho) || h.w == 0.0f) return false;
-  const float rd = sqrtf(fmaxf(rho * rho - dx * dx, 0.0f));
-  const int ylo = (int)ceilf(q.a.y - rd), yhi = (int)floorf(q.a.y + rd);
-  const int zlo = (int)ceilf(q.a.z - rd), zhi = (int)floorf(q.a.z + rd);
-  const int sy = yhi - ylo + 1, sz = zhi - zlo + 1;
-  if (sy <= 0 || sz <= 0) return false;
-  h.ybase = q.b.y + ylo;
-  h.zbase = q.b.z + zlo;
-  h.syz = sy | (sz << 16);
-  h.offy = (float)ylo - q.a.y;
-  h.offz = (float)zlo - q.a.z;
-  h.dx2 = dx * dx;
-  h.c2s = p.sig_c / (rho * rho);
-  return true;
-}
-
-// Splat of the hits one wavefront found (flag `hit`, parameters `h` in each
-// lane): the wave takes them one at a time, broadcast from their lanes, and
-// its 64 lanes cover 8 x 8 blocks of the hit's bounding square (lane = row
-// offset lane / 8, column offset lane % 8), adding w K(d) (times yhat_y or
-// yhat_z for channel 2 or 3) with LDS float atomics at Wf[idx(y, z)]. The
-// lanes of one atomic instruction never share an address, and no search or
-// workgroup barrier is involved. N must be a power of two.
-template <int N, class Idx>
-__device__ __forceinline__ void wave_splat(const SplatParams& p, bool hit, const WaveHit& h, int chan, float* Wf,
-                                           Idx idx) {
-  static_assert((N & (N - 1)) == 0, "wrap by mask");
-  const int lane = threadIdx.x & 63, ly = lane >> 3, lz = lane & 7;
-  const float fly = (float)ly, flz = (float)lz;
-  unsigned long long mask = __ballot(hit);
-  while (mask) {
-    const int i = __ffsll(mask) - 1;
-    mask &= mask - 1;
-    const int yb = __builtin_amdgcn_readlane(h.ybase, i), zb = __builtin_amdgcn_readlane(h.zbase, i);
-    const int syz = __builtin_amdgcn_readlane(h.syz, i);
-    const int sy = syz & 0xffff, sz = syz >> 16;
-    const float oy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h.offy), i));
-    const float oz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h.offz), i));
-    const float d2x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h.dx2), i));
-    const float cs = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h.c2s), i));
-    const float wk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h.w), i)) * p.inv1me0;
-    for (int by0 = 0; by0 < sy; by0 += 8) {
-      const float dy = fly + (oy + (float)by0);
-      const float dyy = fmaf(dy, dy, d2x);
-      const bool rowok = ly + by0 < sy;
-      for (int bz0 = 0; bz0 < sz; bz0 += 8) {
-        const float dz = flz + (oz + (float)bz0);
-        const float e = fmaf(dz, dz, dyy) * cs;  // d^2 / (2 s^2)
-        if (rowok && lz + bz0 < sz && e < p.sig_c) {  // inside the square and d < rho
-          const int yy = (yb + by0 + ly) & (N - 1), zz = (zb + bz0 + lz) & (N - 1);
-          float val = wk * (__expf(-e) - p.e0);
-          if (chan == 2) val *= yhat(yy, N);
-          if (chan == 3) val *= yhat(zz, N);
-          atomicAdd(&Wf[idx(yy, zz)], val);
-        }
-      }
-    }
-  }
-}
-
-// grid = (N planes, batch, NCH == 4 ? 3 : 1); block = 512. Splats the
-// binned samples of batch member blockIdx.y (p.rec, p.cand) into plane x and writes
-// its 2D spectrum, out[((b*NCH + c)*N + x)*N*H]: with NCH = 4 workgroup z
-// splats channel pass z (u, then yhat_y u, then yhat_z u) and the u pass also
-// writes yhat_x u (u scaled by yhat(x)).
+// grid = (N planes, batch); block = 512. Splats the binned samples of batch
+// member blockIdx.y (p.rec, p.cand) into plane x once and writes NCH plane
+// spectra, out[((b*NCH + c)*N + x)*N*H]: u, and with NCH = 4 the moment
+// densities yhat_x u (u's spectrum times yhat(x)), yhat_y u and yhat_z u,
+// whose transforms start from the lane's saved inputs scaled per element.
 template <int N, int NCH>
-__global__ void __launch_bounds__(PlaneP<N>::THREADS, 4) k_plane_splat_fwd(SplatParams p, float2* __restrict__ out,
+__global__ void __launch_bounds__(PlaneP<N>::THREADS, NCH == 4 ? 2 : 4) k_plane_splat_fwd(SplatParams p, float2* __restrict__ out,
                                                                           const float2* __restrict__ table) {
   using P = PlaneP<N>;
   constexpr int H = P::H, L = P::L, R1 = P::R1, NB1 = P::NB1, T = N / 2;
   static_assert(P::R0 == 16 && R1 == 8 && L == 8 && NB1 == 2, "schedule of the code below");
+  static_assert(NCH == 1 || NCH == 4, "channels");
   __shared__ __attribute__((aligned(16))) float2 W[P::SIZE];
   const int x = blockIdx.x, b = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tau = lane / L, l = lane % L;
@@ -814,160 +847,189 @@ __global__ void __launch_bounds__(PlaneP<N>::THREADS, 4) k_plane_splat_fwd(Splat
   for (int bb = 0; bb < NB1; ++bb)
 #pragma unroll
     for (int r = 1; r < R1; ++r) tw[bb][r] = table[r * (l + L * bb)];
-  const int pass = (NCH == 4) ? (int)blockIdx.z : 0;
-  const int chan = (pass == 0) ? 0 : pass + 1;  // 0, 2, 3
   const size_t plane_sz = (size_t)N * H;
-  float2* dst0 = out + (((size_t)b * NCH + chan) * N + x) * plane_sz;
-  float2* dst1 = (NCH == 4 && chan == 0) ? out + (((size_t)b * NCH + 1) * N + x) * plane_sz : nullptr;
+  auto dst = [&](int c) { return out + (((size_t)b * NCH + c) * N + x) * plane_sz; };
   const float s1 = yhat(x, N);
 
   // splat: candidate c of the plane's runs is tested by lane c / WAVES of
-  // wave c % WAVES (the first round's loads overlap the zero fill), then each
-  // wave splats its own hits
+  // wave c % WAVES (the first round's loads are in flight during the zero
+  // fill), then each wave splats its own hits
   SplatParams sp = p;
   sp.inv1me0 *= 0.5f;  // the 1/2 of the two-for-one split
   const int4 rg = p.cand[(size_t)b * N + x];
+  const int ncand = rg.y + rg.w;
   const Placed* rb = p.rec + (size_t)b * p.n_pts;
   auto pidx = [](int yy, int zz) { return 2 * (P::al(yy & (T - 1)) + P::be(zz)) + (yy >= T ? 1 : 0); };
-  WaveHit h;
-  bool hit = wave_hit<N>(sp, rb, rg, lane * P::WAVES + wave, x, h);
+  Placed q;
+  const bool is_cand = wave_cand(rb, rg, lane * P::WAVES + wave, q);
   float4* W4 = reinterpret_cast<float4*>(W);
   for (int i = tid; i < P::SIZE / 2; i += P::THREADS) W4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-  __syncthreads();
+  WaveHit h;
+  bool hit = is_cand && wave_hit<N>(sp, q, x, h);
+  // A plane that no sample reaches is zero, and so are its spectra: they are
+  // written directly, without the transforms.
+  if (!__syncthreads_or(hit) && ncand <= 64 * P::WAVES) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      float4* d = reinterpret_cast<float4*>(dst(c));
+      for (int i = tid; i < (int)(plane_sz / 2); i += P::THREADS) d[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    return;
+  }
   float* Wf = reinterpret_cast<float*>(W);
   for (int c0 = 0;;) {
-    wave_splat<N>(sp, hit, h, chan, Wf, pidx);
+    wave_splat<N>(sp, hit, h, 0, Wf, pidx);
     c0 += 64 * P::WAVES;
-    if (c0 >= rg.y + rg.w) break;  // uniform
-    hit = wave_hit<N>(sp, rb, rg, c0 + lane * P::WAVES + wave, x, h);
+    if (c0 >= ncand) break;  // uniform
+    const bool more = wave_cand(rb, rg, c0 + lane * P::WAVES + wave, q);
+    hit = more && wave_hit<N>(sp, q, x, h);
   }
   __syncthreads();
 
-  // z: complex transform of row pair t = 8 wave + tau
-  {
-    const int t = P::TPW * wave + tau;
-    float2* zb = W + P::al(t) + l;  // position l + m (m a multiple of 8) at zb[be(m)]
-    float2 v[16];
+  // the z-transform inputs of this lane: row pair t = 8 wave + tau at
+  // positions l + 8 r (every plane value is read by exactly one lane)
+  const int t = P::TPW * wave + tau;
+  float2* zb = W + P::al(t) + l;  // position l + m (m a multiple of 8) at zb[be(m)]
+  float2 vs[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = zb[P::be(8 * r)];
-    Bfly<16, -1>::run(v);
-    float2* zw = W + P::al(t) + 17 * l;  // position 16 l + r at be(16 l + r) = 17 l + r
-    wave_sync();
-#pragma unroll
-    for (int r = 0; r < 16; ++r) zw[r] = v[r];
-    wave_sync();
-    float2 u[NB1][R1];
-#pragma unroll
-    for (int bb = 0; bb < NB1; ++bb)
-#pragma unroll
-      for (int r = 0; r < R1; ++r) u[bb][r] = zb[P::be(8 * bb + 16 * r)];
-    wave_sync();
-#pragma unroll
-    for (int bb = 0; bb < NB1; ++bb) {
-#pragma unroll
-      for (int r = 1; r < R1; ++r) u[bb][r] = cmul(u[bb][r], tw[bb][r]);
-      Bfly<8, -1>::run(u[bb]);
-    }
-#pragma unroll
-    for (int bb = 0; bb < NB1; ++bb)
-#pragma unroll
-      for (int r = 0; r < R1; ++r) zb[P::be(8 * bb + 16 * r)] = u[bb][r];  // Z_t(k), k = l + 8 bb + 16 r
-  }
-  __syncthreads();
+  for (int r = 0; r < 16; ++r) vs[r] = zb[P::be(8 * r)];
+  const float hy0 = yhat(t, N), hy1 = yhat(t + T, N);
 
-  // y: column transform c = 8 wave + tau over rows 0 .. N-1
-  {
-    const int c = P::TPW * wave + tau;
-    const int b1 = P::be(c), b2 = P::be(c == 0 ? T : N - c);
-    float2* r1 = W + P::al(l) + b1;  // row l + 8 m of column c at r1[al(8 m)]
-    float2* r2 = W + P::al(l) + b2;  // ... of column N - c (or N/2)
-    float2 v[16];
+#pragma unroll 1
+  for (int pass = 0; pass < (NCH == 4 ? 3 : 1); ++pass) {
+    // pass 0: u; pass 1: yhat_y u; pass 2: yhat_z u
+    if (pass > 0) __syncthreads();  // the previous pass's y transforms are done with LDS
+    // z: complex transform of row pair t
     {
-      float2 z1[8], z2[8];
+      float2 v[16];
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        z1[r] = r1[P::al(8 * r)];
-        z2[r] = r2[P::al(8 * r)];
+      for (int r = 0; r < 16; ++r) {
+        v[r] = vs[r];
+        if (pass == 1) v[r] = make_float2(v[r].x * hy0, v[r].y * hy1);
+        if (pass == 2) v[r] = make_float2(v[r].x * yhat(l + 8 * r, N), v[r].y * yhat(l + 8 * r, N));
       }
-      if (c != 0) {
+      Bfly<16, -1>::run(v);
+      float2* zw = W + P::al(t) + 17 * l;  // position 16 l + r at be(16 l + r) = 17 l + r
+      wave_sync();
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          v[r] = make_float2(z1[r].x + z2[r].x, z1[r].y - z2[r].y);      // row l + 8 r
-          v[r + 8] = make_float2(z1[r].y + z2[r].y, z2[r].x - z1[r].x);  // row l + 8 r + N/2
-        }
-      } else {
-        // real columns kz = 0 (real part) and kz = N/2 (imaginary part)
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          v[r] = make_float2(z1[r].x + z1[r].x, z2[r].x + z2[r].x);
-          v[r + 8] = make_float2(z1[r].y + z1[r].y, z2[r].y + z2[r].y);
-        }
-      }
-    }
-    Bfly<16, -1>::run(v);
-    float2* w1 = W + P::al(8 * l) + b1;  // position 16 l + r: row 8 l + (r & 7)
-    float2* w2 = W + P::al(8 * l) + b2;
-    wave_sync();
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      w1[P::al(r)] = v[r];
-      w2[P::al(r)] = v[r + 8];
-    }
-    wave_sync();
-    float2 u[NB1][R1];
-#pragma unroll
-    for (int r = 0; r < R1; ++r) {
-      u[0][r] = r1[P::al(8 * r)];  // position l + 16 r
-      u[1][r] = r2[P::al(8 * r)];  // position l + 8 + 16 r
-    }
-#pragma unroll
-    for (int bb = 0; bb < NB1; ++bb) {
-#pragma unroll
-      for (int r = 1; r < R1; ++r) u[bb][r] = cmul(u[bb][r], tw[bb][r]);
-      Bfly<8, -1>::run(u[bb]);
-    }
-    // outputs Y(ky), ky = l + 8 bb + 16 r
-    if (c != 0) {
-      const int lo = (l * H + c) * (int)sizeof(float2);
-      const auto rs0 = buffer_rsrc(dst0, (unsigned)(plane_sz * sizeof(float2)));
+      for (int r = 0; r < 16; ++r) zw[r] = v[r];
+      wave_sync();
+      float2 u[NB1][R1];
 #pragma unroll
       for (int bb = 0; bb < NB1; ++bb)
 #pragma unroll
-        for (int r = 0; r < R1; ++r) buffer_store2(u[bb][r], rs0, lo, (8 * bb + 16 * r) * H * (int)sizeof(float2));
-      if (dst1) {
-        const auto rs1 = buffer_rsrc(dst1, (unsigned)(plane_sz * sizeof(float2)));
+        for (int r = 0; r < R1; ++r) u[bb][r] = zb[P::be(8 * bb + 16 * r)];
+      wave_sync();
+#pragma unroll
+      for (int bb = 0; bb < NB1; ++bb) {
+#pragma unroll
+        for (int r = 1; r < R1; ++r) u[bb][r] = cmul(u[bb][r], tw[bb][r]);
+        Bfly<8, -1>::run(u[bb]);
+      }
+#pragma unroll
+      for (int bb = 0; bb < NB1; ++bb)
+#pragma unroll
+        for (int r = 0; r < R1; ++r) zb[P::be(8 * bb + 16 * r)] = u[bb][r];  // Z_t(k), k = l + 8 bb + 16 r
+    }
+    __syncthreads();
+
+    // y: column transform c = 8 wave + tau over rows 0 .. N-1
+    float2* dst0 = dst(pass == 0 ? 0 : pass + 1);
+    float2* dst1 = (NCH == 4 && pass == 0) ? dst(1) : nullptr;
+    {
+      const int c = P::TPW * wave + tau;
+      const int b1 = P::be(c), b2 = P::be(c == 0 ? T : N - c);
+      float2* r1 = W + P::al(l) + b1;  // row l + 8 m of column c at r1[al(8 m)]
+      float2* r2 = W + P::al(l) + b2;  // ... of column N - c (or N/2)
+      float2 v[16];
+      {
+        float2 z1[8], z2[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          z1[r] = r1[P::al(8 * r)];
+          z2[r] = r2[P::al(8 * r)];
+        }
+        if (c != 0) {
+#pragma unroll
+          for (int r = 0; r < 8; ++r) {
+            v[r] = make_float2(z1[r].x + z2[r].x, z1[r].y - z2[r].y);      // row l + 8 r
+            v[r + 8] = make_float2(z1[r].y + z2[r].y, z2[r].x - z1[r].x);  // row l + 8 r + N/2
+          }
+        } else {
+          // real columns kz = 0 (real part) and kz = N/2 (imaginary part)
+#pragma unroll
+          for (int r = 0; r < 8; ++r) {
+            v[r] = make_float2(z1[r].x + z1[r].x, z2[r].x + z2[r].x);
+            v[r + 8] = make_float2(z1[r].y + z1[r].y, z2[r].y + z2[r].y);
+          }
+        }
+      }
+      Bfly<16, -1>::run(v);
+      float2* w1 = W + P::al(8 * l) + b1;  // position 16 l + r: row 8 l + (r & 7)
+      float2* w2 = W + P::al(8 * l) + b2;
+      wave_sync();
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        w1[P::al(r)] = v[r];
+        w2[P::al(r)] = v[r + 8];
+      }
+      wave_sync();
+      float2 u[NB1][R1];
+#pragma unroll
+      for (int r = 0; r < R1; ++r) {
+        u[0][r] = r1[P::al(8 * r)];  // position l + 16 r
+        u[1][r] = r2[P::al(8 * r)];  // position l + 8 + 16 r
+      }
+#pragma unroll
+      for (int bb = 0; bb < NB1; ++bb) {
+#pragma unroll
+        for (int r = 1; r < R1; ++r) u[bb][r] = cmul(u[bb][r], tw[bb][r]);
+        Bfly<8, -1>::run(u[bb]);
+      }
+      // outputs Y(ky), ky = l + 8 bb + 16 r
+      if (c != 0) {
+        const int lo = (l * H + c) * (int)sizeof(float2);
+        const auto rs0 = buffer_rsrc(dst0, (unsigned)(plane_sz * sizeof(float2)));
 #pragma unroll
         for (int bb = 0; bb < NB1; ++bb)
 #pragma unroll
-          for (int r = 0; r < R1; ++r)
-            buffer_store2(make_float2(u[bb][r].x * s1, u[bb][r].y * s1), rs1, lo, (8 * bb + 16 * r) * H * (int)sizeof(float2));
-      }
-    } else {
-      // C = P + i Q with P, Q the spectra of the real columns kz = 0 and N/2:
-      // P(k) = (C(k) + conj C(N-k))/2, Q(k) = -i (C(k) - conj C(N-k))/2
-      wave_sync();
+          for (int r = 0; r < R1; ++r) buffer_store2(u[bb][r], rs0, lo, (8 * bb + 16 * r) * H * (int)sizeof(float2));
+        if (dst1) {
+          const auto rs1 = buffer_rsrc(dst1, (unsigned)(plane_sz * sizeof(float2)));
 #pragma unroll
-      for (int r = 0; r < R1; ++r) {
-        r1[P::al(8 * r)] = u[0][r];
-        r2[P::al(8 * r)] = u[1][r];
-      }
-      wave_sync();
+          for (int bb = 0; bb < NB1; ++bb)
 #pragma unroll
-      for (int bb = 0; bb < NB1; ++bb)
+            for (int r = 0; r < R1; ++r)
+              buffer_store2(make_float2(u[bb][r].x * s1, u[bb][r].y * s1), rs1, lo,
+                            (8 * bb + 16 * r) * H * (int)sizeof(float2));
+        }
+      } else {
+        // C = P + i Q with P, Q the spectra of the real columns kz = 0 and N/2:
+        // P(k) = (C(k) + conj C(N-k))/2, Q(k) = -i (C(k) - conj C(N-k))/2
+        wave_sync();
 #pragma unroll
         for (int r = 0; r < R1; ++r) {
-          const int k = l + 8 * bb + 16 * r, m = (N - k) & (N - 1);
-          const float2 a = u[bb][r];
-          const float2 z = W[P::al((m & 7) | ((m >> 4) << 3)) + (((m >> 3) & 1) ? b2 : b1)];
-          const float2 pk = make_float2(0.5f * (a.x + z.x), 0.5f * (a.y - z.y));
-          const float2 qk = make_float2(0.5f * (a.y + z.y), -0.5f * (a.x - z.x));
-          dst0[(size_t)k * H] = pk;
-          dst0[(size_t)k * H + T] = qk;
-          if (dst1) {
-            dst1[(size_t)k * H] = make_float2(pk.x * s1, pk.y * s1);
-            dst1[(size_t)k * H + T] = make_float2(qk.x * s1, qk.y * s1);
-          }
+          r1[P::al(8 * r)] = u[0][r];
+          r2[P::al(8 * r)] = u[1][r];
         }
+        wave_sync();
+#pragma unroll
+        for (int bb = 0; bb < NB1; ++bb)
+#pragma unroll
+          for (int r = 0; r < R1; ++r) {
+            const int k = l + 8 * bb + 16 * r, m = (N - k) & (N - 1);
+            const float2 a = u[bb][r];
+            const float2 z = W[P::al((m & 7) | ((m >> 4) << 3)) + (((m >> 3) & 1) ? b2 : b1)];
+            const float2 pk = make_float2(0.5f * (a.x + z.x), 0.5f * (a.y - z.y));
+            const float2 qk = make_float2(0.5f * (a.y + z.y), -0.5f * (a.x - z.x));
+            dst0[(size_t)k * H] = pk;
+            dst0[(size_t)k * H + T] = qk;
+            if (dst1) {
+              dst1[(size_t)k * H] = make_float2(pk.x * s1, pk.y * s1);
+              dst1[(size_t)k * H + T] = make_float2(qk.x * s1, qk.y * s1);
+            }
+          }
+      }
     }
   }
 }

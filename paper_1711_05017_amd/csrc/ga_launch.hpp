@@ -131,12 +131,12 @@ template <int N> struct Launch {
     else
       plane_splat(sp, nch, out, batch, tw, s);
   }
-  // pass 1 from binned samples (sp.rec): nch = 1, or 4 in three channel passes
+  // pass 1 from binned samples (sp.rec, sp.cand): nch = 1 or 4
   static void plane_splat(const SplatParams& sp, int nch, float2* out, int batch, const float2* tw, hipStream_t s) {
     if constexpr (PlaneP<N>::ok) {
       constexpr int TH = PlaneP<N>::THREADS;
       if (nch == 4)
-        hipLaunchKernelGGL((k_plane_splat_fwd<N, 4>), dim3(N, batch, 3), dim3(TH), 0, s, sp, out, tw);
+        hipLaunchKernelGGL((k_plane_splat_fwd<N, 4>), dim3(N, batch), dim3(TH), 0, s, sp, out, tw);
       else
         hipLaunchKernelGGL((k_plane_splat_fwd<N, 1>), dim3(N, batch), dim3(TH), 0, s, sp, out, tw);
     } else {

@@ -1,4 +1,4 @@
-"""GPU parity of field tables for restricted orientations (Sec. 4.3): the 7
+"""GPU parity of field tables for restricted orientations (Sec. 4.2): the 7
 fields per orientation against the oracle's, read at lattice and fractional
 translations by queries that mix orientations."""
 
