@@ -100,6 +100,7 @@ typedef int32_t ga_status;
 #define GA_OP_FIELD_GRAD 6
 #define GA_OP_POSE_LOCAL 7
 #define GA_OP_SCORE 8
+#define GA_OP_POSE_SPECTRAL 9
 
 /* Plan flags. */
 #define GA_PLAN_AXIS_PASSES 1u /* separate-axis path at every grid edge */
@@ -277,6 +278,36 @@ ga_status ga_field_grad(const ga_plan* plan, const float* d_uA, const float* d_A
 ga_status ga_pose_local(const ga_plan* plan, const float* d_FA4, const float* d_xyzr, const float* d_w, int64_t n_pts,
                         const float* d_R, const float* h_c, float sigma, const float* d_t, int32_t n_poses,
                         float* d_out7, void* d_work, size_t work_bytes, hipStream_t stream);
+
+/*
+ * Resident data of the stationary part for re-correlated single-translation
+ * queries (ga_pose_spectral): d_AX2 = 2 half-spectrum-sized arrays,
+ * AX(x, k_y, k_z) = sum_kx Ahat(k) exp(+2 pi i kx x / n) and DX, the same
+ * transform of 2 pi i omega(kx) Ahat (the x-derivative multiplier of eq. 6a),
+ * both unnormalised, [2][x][k_y][k_z] in the half-spectrum layout. d_Ahat:
+ * the stationary part's spectrum (ga_fft3d). Needs the plane path (n <= 192,
+ * else GA_EUNSUPPORTED). d_Ahat and d_AX2 must not overlap.
+ */
+ga_status ga_pose_prepare(const ga_plan* plan, const float* d_Ahat, float* d_AX2, hipStream_t stream);
+
+/*
+ * Energy, force and torque at n_poses single poses by re-correlation (Sec.
+ * 3.2 real-time sequence for a new rotation; Sec. 3.3 single translation):
+ * pose b rotates the moving part by d_R[b] about h_c and splats its 4
+ * channels (u and the moment densities of eq. 6b), transforms each x-plane
+ * along z and y, and adds that plane's share of the partial sum of eq. 7b at
+ * translation round(d_t[b]) (nearest lattice point, as GA_SINGLE) for all 7
+ * products of eq. 5, 6a, 6b: with the x transform folded into d_AX2
+ * (ga_pose_prepare), sum_kx Ahat conj(Bhat) e^{2 pi i kx tx/n} =
+ * sum_x conj(B(x)) AX(x + tx). Same values as ga_force_torque GA_SINGLE on
+ * the re-splatted part's spectra (and as ga_pose_local), without writing any
+ * spectrum of the moving part. Partial sums in float64. d_out7: n_poses x 7
+ * floats; n_poses <= 65535. Workspace GA_OP_POSE_SPECTRAL with batch =
+ * n_poses and n_items = n_pts. Needs the plane path (n <= 192).
+ */
+ga_status ga_pose_spectral(const ga_plan* plan, const float* d_AX2, const float* d_xyzr, const float* d_w,
+                           int64_t n_pts, const float* d_R, const float* h_c, float sigma, const float* d_t,
+                           int32_t n_poses, float* d_out7, void* d_work, size_t work_bytes, hipStream_t stream);
 
 /*
  * Field tables for motion restricted to a set of orientations (Sec. 4.2,

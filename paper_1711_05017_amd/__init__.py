@@ -32,6 +32,8 @@ from .ga import (  # noqa: F401
     ga_lowpass,
     ga_spectral_rotate,
     ga_pose_local,
+    ga_pose_prepare,
+    ga_pose_spectral,
     ga_score,
     ga_splat,
     ga_supported_n,

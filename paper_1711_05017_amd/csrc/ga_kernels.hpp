@@ -150,6 +150,12 @@ __device__ __forceinline__ int wrapn(int v, int n) {
 }
 __device__ __forceinline__ float yhat(int q, int n) { return (float)((q < n / 2) ? q : q - n); }
 
+// kappa(k)/N for a half-spectrum index: k for k < N/2, k - N above, 0 at N/2.
+template <int N>
+__device__ __forceinline__ float omega_of(int k) {
+  return (k == N / 2) ? 0.f : (float)((k < N / 2) ? k : k - N) / (float)N;
+}
+
 __device__ __forceinline__ void load_rotation(const SplatParams& p, int b, double* R) {
   if (p.Rdev) {
 #pragma unroll
@@ -271,12 +277,12 @@ struct QueryItem {
   const float4* xyzr;
   const float* w;
   long long n_pts;
-  const float2* Ahat;  // spectral queries: stationary spectrum
-  const float4* FA;    // local queries: (u_A, grad u_A) per voxel
+  const float2* AX;  // spectral queries: the stationary spectrum and its x derivative, x inverse-transformed (2 x 8H)
+  const float4* FA;  // local queries: (u_A, grad u_A) per voxel
   float R[9];
   float c[3];
   int t[3];
-  int pad;
+  int pad;  // 1: the translation was not finite or too large (outputs NaN)
 };
 
 // Binning of heterogeneous queries: item b's samples, placed with its own
@@ -826,19 +832,99 @@ static_assert(PlaneP<128>::be(127) < PlaneP<128>::S, "rows do not overlap");
 static_assert(PlaneP<128>::al(63) + PlaneP<128>::be(127) < PlaneP<128>::SIZE && PlaneP<128>::SIZE % 2 == 0,
               "plane slots");
 
-// grid = (N planes, batch); block = 512. Splats the binned samples of batch
-// member blockIdx.y (p.rec, p.cand) into plane x once and writes NCH plane
-// spectra, out[((b*NCH + c)*N + x)*N*H]: u, and with NCH = 4 the moment
-// densities yhat_x u (u's spectrum times yhat(x)), yhat_y u and yhat_z u,
-// whose transforms start from the lane's saved inputs scaled per element.
-template <int N, int NCH>
-__global__ void __launch_bounds__(PlaneP<N>::THREADS, NCH == 4 ? 2 : 4) k_plane_splat_fwd(SplatParams p, float2* __restrict__ out,
-                                                                          const float2* __restrict__ table) {
+// Single-translation sums of one x-plane (the serving path's re-correlation):
+// the partial sum of eq. 7b over the modes (k_y, k_z) of plane x after the z
+// and y transforms, with the x transform folded into resident data. For the
+// moving part's plane spectrum C(x, k_y, k_z) (x not transformed),
+//   sum_kx Ahat(k) conj(Chat(k)) e^{2 pi i kx tx / N}
+//     = sum_x conj(C(x, k_y, k_z)) AX(x + tx, k_y, k_z),
+// AX(x') = sum_kx Ahat(kx, k_y, k_z) e^{+2 pi i kx x'/N} (Ahat inverse-
+// transformed along x, unnormalised), and the x-derivative multiplier
+// 2 pi i omega(kx) of eq. 6a goes into a second array DX the same way. Each
+// plane therefore adds its own share of all 7 sums: with
+// s = conj(C) AX e^{i phi}, d = conj(C) DX e^{i phi},
+// phi = 2 pi (k_y t_y + k_z t_z)/N, Hermitian weight w (1 at k_z = 0, N/2,
+// else 2), omega_y = omega(k_y), omega_z = omega(k_z), yx = yhat(x):
+//   u channel:        E += w Re s,  F_x -= w Re d,  F_y += 2 pi w omega_y Im s,
+//                     F_z += 2 pi w omega_z Im s,
+//                     tau_y -= 2 pi w omega_z yx Im s,  tau_z += 2 pi w omega_y yx Im s
+//                     (the moment yhat_x u is u times yx on the plane);
+//   yhat_y u channel: tau_x += 2 pi w omega_z Im s,  tau_z += w Re d;
+//   yhat_z u channel: tau_x -= 2 pi w omega_y Im s,  tau_y -= w Re d;
+// all times N^-3 in the final reduction (eq. 6a, 6b, 7b; Sec. 3.3).
+struct SingleAcc {
+  double v[7] = {0, 0, 0, 0, 0, 0, 0};
+  // per-lane float sums of one channel pass, folded into v by fold()
+  float re = 0.f, dre = 0.f, wyim = 0.f, im = 0.f;
+  __device__ __forceinline__ void add(float2 y, float2 a, float2 d, float wy) {
+    const float sre = y.x * a.x + y.y * a.y, sim = y.x * a.y - y.y * a.x;  // conj(y) a
+    re += sre;
+    im += sim;
+    wyim += wy * sim;
+    dre += y.x * d.x + y.y * d.y;  // Re conj(y) d
+  }
+  // pass 0: u; 1: yhat_y u; 2: yhat_z u; w, wz: the lane's weight and omega_z
+  __device__ __forceinline__ void fold(int pass, float w, float wz, float yx) {
+    constexpr double tp = 6.283185307179586476925286766559;
+    const double W = w;
+    if (pass == 0) {
+      v[0] += W * re;
+      v[1] -= W * dre;
+      v[2] += tp * W * wyim;
+      v[3] += tp * W * wz * im;
+      v[5] -= tp * W * wz * yx * im;
+      v[6] += tp * W * yx * wyim;
+    } else if (pass == 1) {
+      v[4] += tp * W * wz * im;
+      v[6] += W * dre;
+    } else {
+      v[4] -= tp * W * wyim;
+      v[5] -= W * dre;
+    }
+    re = dre = wyim = im = 0.f;
+  }
+};
+
+// Sum of the 7 accumulators over a workgroup of NT threads (fixed order),
+// written by threads 0..6 to dst[0..7).
+template <int NT>
+__device__ __forceinline__ void block_sum7(const SingleAcc& acc, double* red /* LDS, 7 x NT/64 */, double* dst) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int o = 0; o < 7; ++o) {
+    double v = acc.v[o];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[o * (NT / 64) + wave] = v;
+  }
+  __syncthreads();
+  if (tid < 7) {
+    double sum = 0;
+    for (int wv = 0; wv < NT / 64; ++wv) sum += red[tid * (NT / 64) + wv];
+    dst[tid] = sum;
+  }
+}
+
+// Body of the pass-1 kernels of the two-stage layout: splat the binned
+// samples of batch member blockIdx.y (p.rec, p.cand) into plane x = blockIdx.x
+// once, then transform NCH = 1 or 4 channels: u, and the moment densities
+// yhat_x u (u's spectrum times yhat(x)), yhat_y u and yhat_z u, whose
+// transforms start from the lane's saved inputs scaled per element.
+// SINGLE = false: the plane spectra go to out[((b*NCH + c)*N + x)*N*H].
+// SINGLE = true (NCH = 4): each plane adds its share of the 7
+// single-translation sums of query items[b] (SingleAcc) and writes them to
+// part[(b*N + x)*7 ..]; nothing else is written.
+template <int N, int NCH, bool SINGLE>
+__device__ __forceinline__ void plane_splat_body(const SplatParams& p, float2* __restrict__ out,
+                                                 const QueryItem* __restrict__ items, double* __restrict__ part,
+                                                 const float2* __restrict__ table) {
   using P = PlaneP<N>;
   constexpr int H = P::H, L = P::L, R1 = P::R1, NB1 = P::NB1, T = N / 2;
   static_assert(P::R0 == 16 && R1 == 8 && L == 8 && NB1 == 2, "schedule of the code below");
   static_assert(NCH == 1 || NCH == 4, "channels");
+  static_assert(!SINGLE || NCH == 4, "single-translation sums need the 4 channels");
   __shared__ __attribute__((aligned(16))) float2 W[P::SIZE];
+  __shared__ float2 tabc[SINGLE ? N : 1];  // exp(+2 pi i m / N)
+  __shared__ double red[SINGLE ? 7 * P::WAVES : 1];
   const int x = blockIdx.x, b = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tau = lane / L, l = lane % L;
   // stage-1 twiddles exp(-2 pi i r j / N), j = l + L bb (both transforms)
@@ -850,6 +936,19 @@ __global__ void __launch_bounds__(PlaneP<N>::THREADS, NCH == 4 ? 2 : 4) k_plane_
   const size_t plane_sz = (size_t)N * H;
   auto dst = [&](int c) { return out + (((size_t)b * NCH + c) * N + x) * plane_sz; };
   const float s1 = yhat(x, N);
+  // single-translation sums: the query's translation and plane x + t_x of
+  // the resident AX and DX
+  int ty = 0, tz = 0;
+  const float2* AXp = nullptr;
+  SingleAcc acc;
+  if constexpr (SINGLE) {
+    const QueryItem& it = items[b];
+    ty = it.t[1];
+    tz = it.t[2];
+    const int xs = (x + it.t[0]) % N;
+    AXp = it.AX + (size_t)xs * plane_sz;
+    for (int i = tid; i < N; i += P::THREADS) tabc[i] = make_float2(table[i].x, -table[i].y);
+  }
 
   // splat: candidate c of the plane's runs is tested by lane c / WAVES of
   // wave c % WAVES (the first round's loads are in flight during the zero
@@ -869,10 +968,14 @@ __global__ void __launch_bounds__(PlaneP<N>::THREADS, NCH == 4 ? 2 : 4) k_plane_
   // A plane that no sample reaches is zero, and so are its spectra: they are
   // written directly, without the transforms.
   if (!__syncthreads_or(hit) && ncand <= 64 * P::WAVES) {
+    if constexpr (SINGLE) {
+      if (tid < 7) part[((size_t)b * N + x) * 7 + tid] = 0.0;
+    } else {
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-      float4* d = reinterpret_cast<float4*>(dst(c));
-      for (int i = tid; i < (int)(plane_sz / 2); i += P::THREADS) d[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int c = 0; c < NCH; ++c) {
+        float4* d = reinterpret_cast<float4*>(dst(c));
+        for (int i = tid; i < (int)(plane_sz / 2); i += P::THREADS) d[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
     }
     return;
   }
@@ -934,8 +1037,8 @@ __global__ void __launch_bounds__(PlaneP<N>::THREADS, NCH == 4 ? 2 : 4) k_plane_
     __syncthreads();
 
     // y: column transform c = 8 wave + tau over rows 0 .. N-1
-    float2* dst0 = dst(pass == 0 ? 0 : pass + 1);
-    float2* dst1 = (NCH == 4 && pass == 0) ? dst(1) : nullptr;
+    float2* dst0 = SINGLE ? nullptr : dst(pass == 0 ? 0 : pass + 1);
+    float2* dst1 = (!SINGLE && NCH == 4 && pass == 0) ? dst(1) : nullptr;
     {
       const int c = P::TPW * wave + tau;
       const int b1 = P::be(c), b2 = P::be(c == 0 ? T : N - c);
@@ -987,7 +1090,22 @@ __global__ void __launch_bounds__(PlaneP<N>::THREADS, NCH == 4 ? 2 : 4) k_plane_
         Bfly<8, -1>::run(u[bb]);
       }
       // outputs Y(ky), ky = l + 8 bb + 16 r
-      if (c != 0) {
+      if (SINGLE && c != 0) {
+        // Y(ky) at ky = l + 8 bb + 16 r, column kz = c (weight 2)
+        const int m0 = l * ty + c * tz;
+        const float2* ap = AXp + l * H + c;
+#pragma unroll
+        for (int bb = 0; bb < NB1; ++bb)
+#pragma unroll
+          for (int r = 0; r < R1; ++r) {
+            const int ky = l + 8 * bb + 16 * r;
+            const float2 ph = tabc[(m0 + (8 * bb + 16 * r) * ty) & (N - 1)];
+            const float2 a = cmul(ap[(8 * bb + 16 * r) * H], ph);
+            const float2 d = cmul(ap[plane_sz * N + (8 * bb + 16 * r) * H], ph);
+            acc.add(u[bb][r], a, d, omega_of<N>(ky));
+          }
+        acc.fold(pass, 2.f, omega_of<N>(c), s1);
+      } else if (c != 0) {
         const int lo = (l * H + c) * (int)sizeof(float2);
         const auto rs0 = buffer_rsrc(dst0, (unsigned)(plane_sz * sizeof(float2)));
 #pragma unroll
@@ -1022,16 +1140,129 @@ __global__ void __launch_bounds__(PlaneP<N>::THREADS, NCH == 4 ? 2 : 4) k_plane_
             const float2 z = W[P::al((m & 7) | ((m >> 4) << 3)) + (((m >> 3) & 1) ? b2 : b1)];
             const float2 pk = make_float2(0.5f * (a.x + z.x), 0.5f * (a.y - z.y));
             const float2 qk = make_float2(0.5f * (a.y + z.y), -0.5f * (a.x - z.x));
-            dst0[(size_t)k * H] = pk;
-            dst0[(size_t)k * H + T] = qk;
-            if (dst1) {
-              dst1[(size_t)k * H] = make_float2(pk.x * s1, pk.y * s1);
-              dst1[(size_t)k * H + T] = make_float2(qk.x * s1, qk.y * s1);
+            if constexpr (SINGLE) {
+              // (k, kz = 0) and (k, kz = N/2), weight 1, omega_z = 0
+              const float2* ap = AXp + (size_t)k * H;
+              const float2 ph0 = tabc[(k * ty) & (N - 1)], ph1 = tabc[(k * ty + T * tz) & (N - 1)];
+              acc.add(pk, cmul(ap[0], ph0), cmul(ap[plane_sz * N], ph0), omega_of<N>(k));
+              acc.add(qk, cmul(ap[T], ph1), cmul(ap[plane_sz * N + T], ph1), omega_of<N>(k));
+            } else {
+              dst0[(size_t)k * H] = pk;
+              dst0[(size_t)k * H + T] = qk;
+              if (dst1) {
+                dst1[(size_t)k * H] = make_float2(pk.x * s1, pk.y * s1);
+                dst1[(size_t)k * H + T] = make_float2(qk.x * s1, qk.y * s1);
+              }
             }
           }
+        if constexpr (SINGLE) acc.fold(pass, 1.f, 0.f, s1);
       }
     }
   }
+  if constexpr (SINGLE) block_sum7<P::THREADS>(acc, red, part + ((size_t)b * N + x) * 7);
+}
+
+// grid = (N planes, batch); block = 512. Pass 1 from binned samples: the
+// plane spectra of NCH = 1 or 4 channels (plane_splat_body).
+template <int N, int NCH>
+__global__ void __launch_bounds__(PlaneP<N>::THREADS, NCH == 4 ? 2 : 4) k_plane_splat_fwd(SplatParams p, float2* __restrict__ out,
+                                                                          const float2* __restrict__ table) {
+  plane_splat_body<N, NCH, false>(p, out, nullptr, nullptr, table);
+}
+
+// grid = (N planes, queries); block = 512. Re-correlated single-translation
+// sums of query b over plane x: part[(b*N + x)*7 + o] (plane_splat_body).
+template <int N>
+__global__ void __launch_bounds__(PlaneP<N>::THREADS, 2) k_plane_single(SplatParams p, const QueryItem* __restrict__ items,
+                                                                     double* __restrict__ part,
+                                                                     const float2* __restrict__ table) {
+  plane_splat_body<N, 4, true>(p, nullptr, items, part, table);
+}
+
+// Single-translation sums of one x-plane for grid edges without the
+// two-stage layout (SingleAcc gives the sums): grid = (N planes, queries, 3
+// channel passes), block = Plane<N>::THREADS. Workgroup (x, b, z) splats
+// channel pass z of query b (u, then yhat_y u, then yhat_z u; yhat_x u is u
+// times yhat(x)) into plane x, transforms it along z and y, and adds the
+// plane's share of the 7 sums with the resident AX, DX of the query's pair
+// (x + t_x plane), to part[((b*3 + z)*N + x)*7 ..]. Thread t takes column
+// k_z = t mod H and rows k_y = t / H + j (THREADS / H), so its Hermitian
+// weight and omega_z are fixed.
+template <int N>
+__global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_single_gen(SplatParams p,
+                                                                                     const QueryItem* __restrict__ items,
+                                                                                     double* __restrict__ part,
+                                                                                     const float2* __restrict__ table) {
+  using P = Plane<N>;
+  constexpr int H = P::H, GR = P::THREADS / H;  // row groups
+  static_assert(GR >= 1, "one column per thread at least");
+  __shared__ __attribute__((aligned(16))) float2 W[P::SIZE];
+  __shared__ float2 tabc[N];  // exp(+2 pi i m / N)
+  __shared__ double red[7 * P::WAVES];
+  const int x = blockIdx.x, b = blockIdx.y, pass = blockIdx.z, tid = threadIdx.x;
+  const int chan = (pass == 0) ? 0 : pass + 1;  // 0, 2, 3
+  double* dstp = part + (((size_t)b * 3 + pass) * N + x) * 7;
+  const QueryItem& it = items[b];
+  const size_t plane_sz = (size_t)N * H;
+  const float2* AXp = it.AX + (size_t)((x + it.t[0]) % N) * plane_sz;
+  const int ty = it.t[1], tz = it.t[2];
+  for (int i = tid; i < N; i += P::THREADS) tabc[i] = make_float2(table[i].x, -table[i].y);
+  // splat: as the binned branch of k_plane_fwd
+  const int4 rg = p.cand[(size_t)b * N + x];
+  const int ncand = rg.y + rg.w;
+  const Placed* rb = p.rec + (size_t)b * p.n_pts;
+  const int lane = tid & 63, wave = tid >> 6;
+  auto pidx = [](int yy, int zz) { return P::zs(yy >> 1, zz) * 2 + (yy & 1); };
+  float* Wf = reinterpret_cast<float*>(W);
+  Placed q;
+  const bool is_cand = wave_cand(rb, rg, lane * P::WAVES + wave, q);
+  float4* W4 = reinterpret_cast<float4*>(W);
+  for (int i = tid; i < P::SIZE / 2; i += P::THREADS) W4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+  WaveHit h;
+  bool hit = is_cand && wave_hit<N>(p, q, x, h);
+  if (!__syncthreads_or(hit) && ncand <= 64 * P::WAVES) {
+    if (tid < 7) dstp[tid] = 0.0;
+    return;
+  }
+  for (int c0 = 0;;) {
+    wave_splat<N>(p, hit, h, chan, Wf, pidx);
+    c0 += 64 * P::WAVES;
+    if (c0 >= ncand) break;  // uniform
+    const bool more = wave_cand(rb, rg, c0 + lane * P::WAVES + wave, q);
+    hit = more && wave_hit<N>(p, q, x, h);
+  }
+  __syncthreads();
+  {
+    Twiddles<N> tw;
+    load_twiddles<N>(tw, table, (tid & 63) % P::L);
+    plane_forward_out<N, false>(W, tw, nullptr, nullptr, 0.f);  // spectrum stays in W
+  }
+  SingleAcc acc;
+  if (tid < GR * H) {
+    const int kz = tid % H;
+    for (int ky = tid / H; ky < N; ky += GR) {
+      const int e = ky * H + kz;
+      const float2 ph = tabc[(ky * ty + kz * tz) % N];
+      acc.add(W[P::yc(ky, kz)], cmul(AXp[e], ph), cmul(AXp[plane_sz * N + e], ph), omega_of<N>(ky));
+    }
+    acc.fold(pass, (kz == 0 || kz == N / 2) ? 1.f : 2.f, omega_of<N>(kz), yhat(x, N));
+  }
+  block_sum7<P::THREADS>(acc, red, dstp);
+}
+
+// The x-inverse-transformed resident data of the single-translation sums:
+// out[e] = Ahat[e] and out[spec + e] = 2 pi i omega(kx) Ahat[e] (the x
+// derivative multiplier of eq. 6a); the x transforms follow (k_strip_fft).
+template <int N>
+__global__ void k_ax_inputs(const float2* __restrict__ A, float2* __restrict__ out) {
+  constexpr int H = N / 2 + 1;
+  const size_t spec = (size_t)N * N * H;
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= spec) return;
+  const float w = omega_of<N>((int)(e / ((size_t)N * H)));
+  const float2 a = A[e];
+  out[e] = a;
+  out[spec + e] = make_float2(-kTwoPi * w * a.y, kTwoPi * w * a.x);
 }
 
 // The density itself: grid = (N planes). Writes nch real grids
@@ -1387,11 +1618,6 @@ __global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_score(const fl
   }
 }
 
-// kappa(k)/N for a half-spectrum index: k for k < N/2, k - N above, 0 at N/2.
-template <int N>
-__device__ __forceinline__ float omega_of(int k) {
-  return (k == N / 2) ? 0.f : (float)((k < N / 2) ? k : k - N) / (float)N;
-}
 
 // The 7 spectral products of eq. 5, 6a, 6b at one element (unscaled):
 // P_E = A conj(B); P_F = -2 pi i w P_E; P_tau = 2 pi i (w x conj M) A.
@@ -1534,10 +1760,14 @@ __global__ void __launch_bounds__(256) k_single_partials(const float2* __restric
   __syncthreads();
   const size_t spec = (size_t)N * T::C;
   int t3[3];
+  bool bad_pose = false;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const float tf = poses[p * 3 + a];
-    long long ti = (long long)roundf(tf) % N;  // nearest lattice point, ties away from zero
+    // nearest lattice point, ties away from zero; a translation that is not
+    // finite or beyond 2^30 makes the pose's outputs NaN (bad_pose)
+    bad_pose |= !(fabsf(tf) < 1073741824.0f);
+    const long long ti = bad_pose ? 0 : (long long)roundf(tf) % N;
     t3[a] = (int)(ti < 0 ? ti + N : ti);
   }
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -1568,88 +1798,7 @@ __global__ void __launch_bounds__(256) k_single_partials(const float2* __restric
   if (tid < 7) {
     double s = 0;
     for (int wv = 0; wv < 256 / 64; ++wv) s += red[wv][tid];
-    part[((size_t)p * gridDim.x + blockIdx.x) * 7 + tid] = s;
-  }
-}
-
-// Serving path, pass 2: for query b and one strip of G columns, the x FFT of
-// each of the 4 channels (u, m_x, m_y, m_z; x not yet transformed) and the
-// partial sums over the strip of w(kz) Re[P_o(k) exp(+2 pi i k.t/N)] of the 7
-// products of eq. 5, 6a, 6b, in float64. The sums are linear in each channel,
-// so the channels pass through one LDS strip in turn:
-//   u:    E += Re z, F_a += 2 pi w_a Im z,           z = A conj(u) e
-//   m_b:  Q_b = Re[2 pi i conj(m_b) A e] = -2 pi Im z_b
-//         tau_x = w_y Q_z - w_z Q_y, tau_y = w_z Q_x - w_x Q_z,
-//         tau_z = w_x Q_y - w_y Q_x.
-// part[(b*nblk + blk)*7 + o]; grid = (nblk, batch).
-template <int N, int G>
-__global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_single(const float2* __restrict__ B4,
-                                                                         const QueryItem* __restrict__ items,
-                                                                         double* __restrict__ part,
-                                                                         const float2* __restrict__ table) {
-  using T = Strip<N, G>;
-  __shared__ float2 S[T::SIZE];
-  __shared__ float2 As[T::SIZE];
-  __shared__ float2 tab[N];
-  __shared__ double red[T::WAVES][7];
-  const int tid = threadIdx.x, b = blockIdx.y;
-  const QueryItem& it = items[b];
-  const int t0 = it.t[0], t1 = it.t[1], t2 = it.t[2];
-  const size_t spec = (size_t)N * T::C;
-  const int c0 = blockIdx.x * G;
-  for (int i = tid; i < N; i += T::THREADS) tab[i] = table[i];
-  strip_load<N, G>(As, it.Ahat, c0);
-  Twiddles<N> tw;
-  load_twiddles<N>(tw, table, (tid & 63) % T::L);
-  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-#pragma unroll 1
-  for (int ch = 0; ch < 4; ++ch) {
-    strip_load<N, G>(S, B4 + ((size_t)b * 4 + ch) * spec, c0);
-    __syncthreads();
-    strip_fft<N, G, -1>(S, tw);
-    __syncthreads();
-    for (int i = tid; i < N * G; i += T::THREADS) {
-      const int x = i / G, g = i % G, c = c0 + g;
-      if (c < T::C) {
-        const int ky = c / T::H, kz = c % T::H;
-        const int m = (int)(((long long)x * t0 + (long long)ky * t1 + (long long)kz * t2) % N);
-        const float2 e = make_float2(tab[m].x, -tab[m].y);  // exp(+2 pi i m / N)
-        const float2 z = cmul(cmulc(As[T::idx(x, g)], S[T::idx(x, g)]), e);
-        const double wgt = (kz == 0 || kz == N / 2) ? 1.0 : 2.0;
-        const float wx = omega_of<N>(x), wy = omega_of<N>(ky), wz = omega_of<N>(kz);
-        if (ch == 0) {
-          acc[0] += wgt * z.x;
-          acc[1] += wgt * (kTwoPi * wx * z.y);
-          acc[2] += wgt * (kTwoPi * wy * z.y);
-          acc[3] += wgt * (kTwoPi * wz * z.y);
-        } else {
-          const double q = wgt * (-kTwoPi * z.y);
-          if (ch == 1) {
-            acc[5] += wz * q;
-            acc[6] -= wy * q;
-          } else if (ch == 2) {
-            acc[4] -= wz * q;
-            acc[6] += wx * q;
-          } else {
-            acc[4] += wy * q;
-            acc[5] -= wx * q;
-          }
-        }
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int o = 0; o < 7; ++o) {
-    double v = acc[o];
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if ((tid & 63) == 0) red[tid >> 6][o] = v;
-  }
-  __syncthreads();
-  if (tid < 7) {
-    double sum = 0;
-    for (int wv = 0; wv < T::WAVES; ++wv) sum += red[wv][tid];
-    part[((size_t)b * gridDim.x + blockIdx.x) * 7 + tid] = sum;
+    part[((size_t)p * gridDim.x + blockIdx.x) * 7 + tid] = bad_pose ? __longlong_as_double(0x7ff8000000000000ll) : s;
   }
 }
 
@@ -2174,9 +2323,18 @@ __global__ void k_zero4(float4* __restrict__ p, long long n4) {
 // The periodic lattice cell of coordinate t: lower corner i0 and upper corner
 // i1 = i0 + 1 (both mod n, in [0, n)) and the fraction a = t - floor(t). The
 // quotient by n comes from a float division, off by at most one for
-// |t| < 2^24 n and then corrected; any other value (huge or not finite)
-// takes a 64-bit remainder, so the corners are always inside the grid.
+// |t| < 2^24 n and then corrected (a 64-bit remainder as the last resort), so
+// the corners are always inside the grid.
+// A coordinate that is not finite or whose magnitude reaches 2^24 n (beyond
+// which float32 holds no fraction) is not converted at all: corners 0 and 1
+// and a NaN fraction, so that the interpolated outputs are NaN.
 __device__ __forceinline__ void lattice_cell(float t, int n, int& i0, int& i1, float& a) {
+  if (!(fabsf(t) < 16777216.0f * (float)n)) {  // also false for NaN
+    i0 = 0;
+    i1 = 1 % n;
+    a = __int_as_float(0x7fc00000);
+    return;
+  }
   const float fl = floorf(t);
   a = t - fl;
   long long m = (long long)fl - (long long)floorf(fl / (float)n) * n;
@@ -2269,7 +2427,7 @@ __global__ void k_lowpass(const float2* __restrict__ in, float2* __restrict__ ou
 // Sum of the per-strip partials of each pose in a fixed order, times scale.
 // grid = n_poses, block = 64.
 __global__ void __launch_bounds__(64) k_reduce_partials(const double* __restrict__ part, int nblk, float* __restrict__ out7,
-                                                        double scale) {
+                                                        double scale, const QueryItem* __restrict__ items) {
   __shared__ double red[7][64];
   const int p = blockIdx.x, tid = threadIdx.x;
   for (int o = 0; o < 7; ++o) {
@@ -2281,7 +2439,8 @@ __global__ void __launch_bounds__(64) k_reduce_partials(const double* __restrict
   if (tid < 7) {
     double s = 0;
     for (int i = 0; i < 64; ++i) s += red[tid][i];
-    out7[p * 7 + tid] = (float)(s * scale);
+    const bool bad = items && items[p].pad != 0;  // a translation that could not be converted
+    out7[p * 7 + tid] = bad ? __int_as_float(0x7fc00000) : (float)(s * scale);
   }
 }
 
@@ -2330,7 +2489,7 @@ __global__ void k_pack8(const float* __restrict__ f7, float4* __restrict__ out, 
 // Query descriptors for a batch of (rotation, translation) poses of one part:
 // t rounded to the nearest lattice point (ties away from zero) mod n.
 __global__ void k_make_items(QueryItem* __restrict__ items, int batch, const float4* xyzr, const float* w,
-                             long long n_pts, const float4* FA, const float* __restrict__ R,
+                             long long n_pts, const float4* FA, const float2* AX, const float* __restrict__ R,
                              const float* __restrict__ t, float c0, float c1, float c2, int n) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= batch) return;
@@ -2338,17 +2497,20 @@ __global__ void k_make_items(QueryItem* __restrict__ items, int batch, const flo
   it.xyzr = xyzr;
   it.w = w;
   it.n_pts = n_pts;
-  it.Ahat = nullptr;
+  it.AX = AX;
   it.FA = FA;
   for (int i = 0; i < 9; ++i) it.R[i] = R[b * 9 + i];
   it.c[0] = c0;
   it.c[1] = c1;
   it.c[2] = c2;
-  for (int a = 0; a < 3; ++a) {
-    long long v = (long long)roundf(t[b * 3 + a]) % n;
-    it.t[a] = (int)(v < 0 ? v + n : v);
-  }
   it.pad = 0;
+  for (int a = 0; a < 3; ++a) {
+    const float tf = t[b * 3 + a];
+    const bool ok = fabsf(tf) < 1073741824.0f;  // finite and convertible
+    long long v = ok ? (long long)roundf(tf) % n : 0;
+    it.t[a] = (int)(v < 0 ? v + n : v);
+    if (!ok) it.pad = 1;  // the pose's outputs become NaN (k_reduce_partials)
+  }
   items[b] = it;
 }
 

@@ -146,6 +146,23 @@ template <int N> struct Launch {
         hipLaunchKernelGGL((k_plane_fwd<N, false, 1>), dim3(N, batch), dim3(P::THREADS), 0, s, sp, nullptr, out, tw);
     }
   }
+  // Re-correlated single-translation sums of `batch` queries (binned samples
+  // sp.rec, sp.cand; items with the pair's AX): part = batch x
+  // single_blocks() x 7 partial sums.
+  static int single_blocks() { return PlaneP<N>::ok ? N : 3 * N; }
+  static void plane_single(const SplatParams& sp, const QueryItem* items, double* part, int batch, const float2* tw,
+                           hipStream_t s) {
+    if constexpr (PlaneP<N>::ok)
+      hipLaunchKernelGGL(k_plane_single<N>, dim3(N, batch), dim3(PlaneP<N>::THREADS), 0, s, sp, items, part, tw);
+    else
+      hipLaunchKernelGGL(k_plane_single_gen<N>, dim3(N, batch, 3), dim3(P::THREADS), 0, s, sp, items, part, tw);
+  }
+  // AX = x-inverse transforms of Ahat and of 2 pi i omega(kx) Ahat (2 spectra)
+  static void ax_prepare(const float2* A, float2* ax2, const float2* tw, hipStream_t s) {
+    const size_t spec = (size_t)N * N * (N / 2 + 1);
+    hipLaunchKernelGGL(k_ax_inputs<N>, dim3((unsigned)((spec + 255) / 256)), dim3(256), 0, s, A, ax2);
+    strip_fft(+1, ax2, ax2, 2, tw, s);
+  }
   static void plane_inv(const float2* in, float* out, float scale, int batch, const float2* tw, hipStream_t s) {
     hipLaunchKernelGGL(k_plane_inv<N>, dim3(N, batch), dim3(P::THREADS), 0, s, in, out, scale, tw);
   }
@@ -329,6 +346,11 @@ inline int nstrips_of(int n) {
   dispatch_axis(n, [&]<int N>() { v = Launch<N>::nstrips(); });
   return v;
 }
+inline int single_blocks_of(int n) {
+  int v = 0;
+  dispatch(n, [&]<int N>() { v = Launch<N>::single_blocks(); });
+  return v;
+}
 inline int nsingle_of(int n) {
   int v = 0;
   dispatch_axis(n, [&]<int N>() { v = Launch<N>::nsingle(); });
@@ -390,6 +412,21 @@ inline SplatParams make_splat(const float* xyzr, const float* w, int64_t n_pts, 
   p.e0 = (float)e0;
   p.inv1me0 = (float)(1.0 / (1.0 - e0));
   return p;
+}
+
+// Workspace of ga_pose_spectral: query items, the binned samples of every
+// query, the per-plane partial sums; 16-byte aligned parts.
+struct PoseSpectralLayout {
+  size_t items, bins, part, total;
+};
+inline PoseSpectralLayout pose_spectral_layout(int n, int n_poses, int64_t n_pts) {
+  auto up = [](size_t v) { return (v + 15) / 16 * 16; };
+  PoseSpectralLayout l;
+  l.items = 0;
+  l.bins = up((size_t)n_poses * sizeof(QueryItem));
+  l.part = l.bins + up(bin_bytes(n, n_poses, n_pts));
+  l.total = l.part + (size_t)n_poses * single_blocks_of(n) * 7 * sizeof(double);
+  return l;
 }
 
 inline bool rotation_ok(const float* R) {

@@ -51,7 +51,7 @@ void launch_single(const ga_plan* plan, const float2* A, const float2* B4, const
   dispatch_axis(n, [&]<int N>() { Launch<N>::single(A, B4, d_t, n_poses, part, plan->d_tw, stream); });
   const double scale = 1.0 / ((double)n * n * n);
   hipLaunchKernelGGL(k_reduce_partials, dim3(n_poses), dim3(64), 0, stream, (const double*)part, nsingle_of(n), d_out7,
-                     scale);
+                     scale, (const QueryItem*)nullptr);
 }
 
 }  // namespace
@@ -166,6 +166,9 @@ size_t ga_workspace_size(const ga_plan* plan, int32_t op, int32_t batch, int64_t
     case GA_OP_SCORE: return (n_items >= 1 && n_items <= 2) ? (size_t)batch * (size_t)n_items * spec : 0;
     case GA_OP_POSE_LOCAL:
       return (size_t)batch * sizeof(QueryItem) + (size_t)batch * nlocal_of(n_items) * 7 * sizeof(double);
+    case GA_OP_POSE_SPECTRAL:
+      if (!plane_edge(n)) return 0;
+      return pose_spectral_layout(n, batch, n_items).total;
     default: return 0;
   }
 }
@@ -579,14 +582,78 @@ ga_status ga_pose_local(const ga_plan* plan, const float* d_FA4, const float* d_
   ProfScope ps(plan, GA_K_READOUT, stream);
   hipLaunchKernelGGL(k_make_items, dim3((n_poses + 63) / 64), dim3(64), 0, stream, items, n_poses,
                      reinterpret_cast<const float4*>(d_xyzr), d_w, (long long)n_pts,
-                     reinterpret_cast<const float4*>(d_FA4), d_R, d_t, h_c[0], h_c[1], h_c[2], n);
+                     reinterpret_cast<const float4*>(d_FA4), (const float2*)nullptr, d_R, d_t, h_c[0], h_c[1],
+                     h_c[2], n);
   dispatch_axis(n, [&]<int N>() {
     if constexpr (N <= 256) {
     hipLaunchKernelGGL(k_local_query<N>, dim3(nblk, n_poses), dim3(256), 0, stream, (const QueryItem*)items, part,
                        sp.sig_c, sp.e0, sp.inv1me0);
     }
   });
-  hipLaunchKernelGGL(k_reduce_partials, dim3(n_poses), dim3(64), 0, stream, (const double*)part, nblk, d_out7, 1.0);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(n_poses), dim3(64), 0, stream, (const double*)part, nblk, d_out7, 1.0,
+                     (const QueryItem*)items);
+  return launch_status();
+}
+
+ga_status ga_pose_prepare(const ga_plan* plan, const float* d_Ahat, float* d_AX2, hipStream_t stream) {
+  if (!valid_stream_call(plan) || !d_Ahat || !d_AX2) return GA_EINVAL;
+  if (!all_aligned(d_Ahat, d_AX2)) return GA_EINVAL;
+  const int n = plan->n;
+  if (!plane_edge(n)) return GA_EUNSUPPORTED;
+  const size_t spec_b = spectrum_elems(n) * sizeof(float2);
+  if (overlaps(d_Ahat, spec_b, d_AX2, 2 * spec_b)) return GA_EINVAL;
+  ProfScope ps(plan, GA_K_READOUT, stream);
+  dispatch(n, [&]<int N>() {
+    Launch<N>::ax_prepare(reinterpret_cast<const float2*>(d_Ahat), reinterpret_cast<float2*>(d_AX2), plan->d_tw,
+                          stream);
+  });
+  return launch_status();
+}
+
+ga_status ga_pose_spectral(const ga_plan* plan, const float* d_AX2, const float* d_xyzr, const float* d_w,
+                           int64_t n_pts, const float* d_R, const float* h_c, float sigma, const float* d_t,
+                           int32_t n_poses, float* d_out7, void* d_work, size_t work_bytes, hipStream_t stream) {
+  if (!valid_stream_call(plan) || !d_AX2 || n_pts < 0 || (n_pts > 0 && (!d_xyzr || !d_w)) || !h_c ||
+      !valid_sigma(sigma) || n_poses < 0 || n_poses > 65535 || (n_poses > 0 && (!d_R || !d_t || !d_out7)))
+    return GA_EINVAL;
+  if (!all_aligned(d_AX2, d_xyzr, d_work)) return GA_EINVAL;
+  if (!(std::isfinite(h_c[0]) && std::isfinite(h_c[1]) && std::isfinite(h_c[2]))) return GA_EINVAL;
+  const int n = plan->n;
+  if (!plane_edge(n)) return GA_EUNSUPPORTED;
+  if (n_poses == 0) return GA_OK;
+  const PoseSpectralLayout ly = pose_spectral_layout(n, n_poses, n_pts);
+  if (!d_work || work_bytes < ly.total) return GA_ENOMEM;
+  if (overlaps(d_work, work_bytes, d_out7, sizeof(float) * 7 * (size_t)n_poses) ||
+      overlaps(d_work, work_bytes, d_AX2, 2 * spectrum_elems(n) * sizeof(float2)))
+    return GA_EINVAL;
+  char* wk = static_cast<char*>(d_work);
+  QueryItem* items = reinterpret_cast<QueryItem*>(wk + ly.items);
+  char* bins = wk + ly.bins;
+  const BinLayout bl(n, n_poses, n_pts);
+  double* part = reinterpret_cast<double*>(wk + ly.part);
+  SplatParams sp = make_splat(nullptr, nullptr, 0, nullptr, nullptr, nullptr, sigma);
+  ProfScope ps(plan, GA_K_READOUT, stream);
+  hipLaunchKernelGGL(k_make_items, dim3((n_poses + 63) / 64), dim3(64), 0, stream, items, n_poses,
+                     reinterpret_cast<const float4*>(d_xyzr), d_w, (long long)n_pts, (const float4*)nullptr,
+                     reinterpret_cast<const float2*>(d_AX2), d_R, d_t, h_c[0], h_c[1], h_c[2], n);
+  dispatch(n, [&]<int N>() {
+    Placed* rec = reinterpret_cast<Placed*>(bins + bl.rec);
+    int* off = reinterpret_cast<int*>(bins + bl.off);
+    float* rmax = reinterpret_cast<float*>(bins + bl.rmax);
+    int4* cand = reinterpret_cast<int4*>(bins + bl.cand);
+    hipLaunchKernelGGL(k_bin_items<N>, dim3(n_poses), dim3(256), 0, stream, (const QueryItem*)items, sp,
+                       (long long)n_pts, rec, off, rmax, cand);
+    SplatParams sq = sp;
+    sq.rec = rec;
+    sq.off = off;
+    sq.rmax = rmax;
+    sq.cand = cand;
+    sq.n_pts = n_pts;
+    Launch<N>::plane_single(sq, items, part, n_poses, plan->d_tw, stream);
+  });
+  const double scale = 1.0 / ((double)n * n * n);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(n_poses), dim3(64), 0, stream, (const double*)part, single_blocks_of(n),
+                     d_out7, scale, (const QueryItem*)items);
   return launch_status();
 }
 

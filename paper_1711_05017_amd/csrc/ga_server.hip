@@ -1,16 +1,20 @@
-// ga_server.hip -- serving loop of libga.so: resident pair spectra, queued
+// ga_server.hip -- serving loop of libga.so: resident pair data, queued
 // pose queries, continuous batching per grid size (see include/ga.h).
 //
 // Host side: one mutex guards pairs, queues, tickets and byte accounting; a
 // scheduler thread owns the launch groups. Per grid size there are up to two
-// launch groups, each with its own stream and scratch; a group takes up to
-// max_slots queued queries as soon as it is free, so new arrivals are
-// admitted while the other group (and the groups of other sizes) run.
-// Device side per group: k_bin_items (placement of every query's rotated
-// samples), k_plane_fwd<N, binned, 4 channels> with one workgroup per
-// (x-plane, query, channel pass), k_strip_single (x FFT of the 4 channels
-// and the 7 single-translation partial sums), k_reduce_partials, then one
-// copy of the results to pinned host memory and an event.
+// launch groups sharing the size's stream, each with its own scratch; a group
+// takes up to max_slots queued queries as soon as it is free, so new arrivals
+// are admitted while the other group (and the groups of other sizes) run.
+// A group's completion is signalled by a host function enqueued after its
+// result copy; the scheduler sleeps on its condition variable in between
+// (no polling loop), and checks the groups' events only on a timeout.
+// Device side per group, spectral mode: k_bin_items (placement of every
+// query's rotated samples), the fused single-translation pass
+// (k_plane_single: splat, z and y transforms of the 4 channels and each
+// plane's share of the 7 sums against the pair's resident AX), the sum over
+// planes, one copy of the results to pinned host memory. Local mode:
+// k_local_query and the sum over sample blocks.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -50,8 +54,8 @@ struct Pair {
   float* d_xyzr = nullptr;  // moving part's samples (device copy)
   float* d_w = nullptr;
   int64_t n_pts = 0;
-  float2* d_Ahat = nullptr;  // stationary part's spectrum
-  float* d_FA = nullptr;     // local mode: (u_A, grad u_A) per voxel
+  float2* d_AX = nullptr;  // spectral mode: AX and DX of the stationary part (ga_pose_prepare)
+  float* d_FA = nullptr;   // local mode: (u_A, grad u_A) per voxel
   size_t bytes = 0;
   int inflight = 0;  // queued or running queries
   bool released = false;
@@ -66,8 +70,11 @@ struct Pending {
 };
 
 struct Group {
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;  // the size class's stream
   hipEvent_t done = nullptr;
+  void* server = nullptr;        // for the completion callback
+  bool completed = false;        // set by the callback under the server's mutex
+  bool callback = false;         // the launch enqueued its completion callback
   QueryItem* h_items = nullptr;  // pinned
   QueryItem* d_items = nullptr;
   float* h_out = nullptr;  // pinned, slots x 7
@@ -76,7 +83,6 @@ struct Group {
   int* off = nullptr;
   float* rmax = nullptr;
   int4* cand = nullptr;
-  float2* spec4 = nullptr;  // slots x 4 spectra (x not yet transformed)
   double* part = nullptr;
   std::vector<Pending> batch;
   uint64_t t_start = 0;
@@ -90,6 +96,7 @@ struct SizeClass {
   int slots = 0;
   int64_t max_pts = 0;  // record capacity per query
   int ngroups = 0;
+  hipStream_t stream = nullptr;  // shared by the class's groups
   Group groups[2];
   std::deque<Pending> queue;
   size_t bytes = 0;
@@ -104,10 +111,9 @@ struct Ticket {
 size_t group_bytes(uint32_t mode, int n, int slots, int64_t max_pts) {
   const size_t common = (size_t)slots * (7 * sizeof(float) + sizeof(QueryItem));
   if (mode == GA_SERVE_LOCAL) return common + (size_t)slots * nlocal_of(max_pts) * 7 * sizeof(double);
-  const size_t spec = spectrum_elems(n) * sizeof(float2);
-  const size_t nblk = (size_t)nstrips_of(n);
-  return common + (size_t)slots * (4 * spec + (size_t)max_pts * sizeof(Placed) + (size_t)(n + 1) * sizeof(int) +
-                                   sizeof(float) + (size_t)n * sizeof(int4) + nblk * 7 * sizeof(double));
+  const size_t nblk = (size_t)single_blocks_of(n);
+  return common + (size_t)slots * ((size_t)max_pts * sizeof(Placed) + (size_t)(n + 1) * sizeof(int) + sizeof(float) +
+                                   (size_t)n * sizeof(int4) + nblk * 7 * sizeof(double));
 }
 
 void free_group(Group& g) {
@@ -115,16 +121,16 @@ void free_group(Group& g) {
   if (g.h_items) (void)hipHostFree(g.h_items);
   if (g.h_out) (void)hipHostFree(g.h_out);
   for (void* p : {(void*)g.d_items, (void*)g.d_out, (void*)g.rec, (void*)g.off, (void*)g.rmax, (void*)g.cand,
-                  (void*)g.spec4, (void*)g.part})
+                  (void*)g.part})
     if (p) (void)hipFree(p);
   if (g.done) (void)hipEventDestroy(g.done);
-  if (g.stream) (void)hipStreamDestroy(g.stream);
   g = Group{};
 }
 
-bool alloc_group(Group& g, uint32_t mode, int n, int slots, int64_t max_pts) {
-  bool ok = hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking) == hipSuccess &&
-            hipEventCreateWithFlags(&g.done, hipEventDisableTiming) == hipSuccess &&
+bool alloc_group(Group& g, hipStream_t stream, void* server, uint32_t mode, int n, int slots, int64_t max_pts) {
+  g.stream = stream;
+  g.server = server;
+  bool ok = hipEventCreateWithFlags(&g.done, hipEventDisableTiming) == hipSuccess &&
             hipHostMalloc((void**)&g.h_items, sizeof(QueryItem) * slots, hipHostMallocDefault) == hipSuccess &&
             hipHostMalloc((void**)&g.h_out, sizeof(float) * 7 * slots, hipHostMallocDefault) == hipSuccess &&
             hipMalloc(&g.d_items, sizeof(QueryItem) * slots) == hipSuccess &&
@@ -132,13 +138,11 @@ bool alloc_group(Group& g, uint32_t mode, int n, int slots, int64_t max_pts) {
   if (ok && mode == GA_SERVE_LOCAL) {
     ok = hipMalloc(&g.part, sizeof(double) * (size_t)nlocal_of(max_pts) * 7 * slots) == hipSuccess;
   } else if (ok) {
-    const size_t spec = spectrum_elems(n);
-    const size_t nblk = (size_t)nstrips_of(n);
+    const size_t nblk = (size_t)single_blocks_of(n);
     ok = hipMalloc(&g.rec, sizeof(Placed) * (size_t)max_pts * slots) == hipSuccess &&
          hipMalloc(&g.off, sizeof(int) * (size_t)(n + 1) * slots) == hipSuccess &&
          hipMalloc(&g.rmax, sizeof(float) * slots) == hipSuccess &&
          hipMalloc(&g.cand, sizeof(int4) * (size_t)n * slots) == hipSuccess &&
-         hipMalloc(&g.spec4, sizeof(float2) * spec * 4 * slots) == hipSuccess &&
          hipMalloc(&g.part, sizeof(double) * nblk * 7 * slots) == hipSuccess;
   }
   if (!ok) free_group(g);
@@ -186,7 +190,7 @@ struct ga_server {
     return nullptr;
   }
   void free_pair_locked(Pair& p) {
-    for (void* q : {(void*)p.d_xyzr, (void*)p.d_w, (void*)p.d_Ahat, (void*)p.d_FA})
+    for (void* q : {(void*)p.d_xyzr, (void*)p.d_w, (void*)p.d_AX, (void*)p.d_FA})
       if (q) (void)hipFree(q);
     bytes -= p.bytes;
   }
@@ -209,6 +213,7 @@ struct ga_server {
   }
   void run();
   void launch(SizeClass& c, Group& g);
+  void harvest_locked(Group& g, bool ok, uint64_t t_done);
 };
 
 // Fills the pinned descriptors of a group from its batch (caller holds mu).
@@ -220,7 +225,7 @@ static void fill_items(ga_server* s, SizeClass& c, Group& g) {
     it.xyzr = reinterpret_cast<const float4*>(p.d_xyzr);
     it.w = p.d_w;
     it.n_pts = p.n_pts;
-    it.Ahat = p.d_Ahat;
+    it.AX = p.d_AX;
     it.FA = reinterpret_cast<const float4*>(p.d_FA);
     std::memcpy(it.R, q.R, sizeof(it.R));
     std::memcpy(it.c, p.cB, sizeof(it.c));
@@ -228,6 +233,19 @@ static void fill_items(ga_server* s, SizeClass& c, Group& g) {
     g.h_items[i] = it;
   }
   (void)c;
+}
+
+// Host function enqueued after a group's result copy: marks the group
+// complete and wakes the scheduler. Runs on a HIP runtime thread and makes
+// no HIP call.
+static void group_done_cb(void* arg) {
+  Group* g = static_cast<Group*>(arg);
+  ga_server* s = static_cast<ga_server*>(g->server);
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    g->completed = true;
+  }
+  s->cv.notify_all();
 }
 
 void ga_server::launch(SizeClass& c, Group& g) {
@@ -245,10 +263,9 @@ void ga_server::launch(SizeClass& c, Group& g) {
                          base.sig_c, base.e0, base.inv1me0);
     });
   } else {
-    nblk = nstrips_of(n);
+    nblk = single_blocks_of(n);
     scale = 1.0 / ((double)n * n * n);
     dispatch(n, [&]<int N>() {
-      using L = Launch<N>;
       hipLaunchKernelGGL(k_bin_items<N>, dim3(k), dim3(256), 0, g.stream, g.d_items, base, (long long)c.max_pts, g.rec,
                          g.off, g.rmax, g.cand);
       SplatParams sp = base;
@@ -257,92 +274,109 @@ void ga_server::launch(SizeClass& c, Group& g) {
       sp.rmax = g.rmax;
       sp.cand = g.cand;
       sp.n_pts = c.max_pts;
-      L::plane_splat(sp, 4, g.spec4, k, tw, g.stream);
-      hipLaunchKernelGGL((k_strip_single<N, L::G>), dim3(L::nstrips(), k), dim3(L::T::THREADS), 0, g.stream,
-                         (const float2*)g.spec4, (const QueryItem*)g.d_items, g.part, tw);
+      Launch<N>::plane_single(sp, g.d_items, g.part, k, tw, g.stream);
     });
   }
-  hipLaunchKernelGGL(k_reduce_partials, dim3(k), dim3(64), 0, g.stream, (const double*)g.part, nblk, g.d_out, scale);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(k), dim3(64), 0, g.stream, (const double*)g.part, nblk, g.d_out, scale,
+                     (const QueryItem*)nullptr);  // translations were checked by ga_submit
   (void)hipMemcpyAsync(g.h_out, g.d_out, sizeof(float) * 7 * k, hipMemcpyDeviceToHost, g.stream);
   (void)hipEventRecord(g.done, g.stream);
+  const bool cb = hipLaunchHostFunc(g.stream, group_done_cb, &g) == hipSuccess;
+  std::lock_guard<std::mutex> lk(mu);
+  g.callback = cb;
+  if (!cb) sticky = GA_EDEVICE;  // the scheduler's timeout check retires the group through its event
+}
+
+// Results of a finished group to its tickets; frees released pairs whose
+// last query this was (caller holds mu).
+void ga_server::harvest_locked(Group& g, bool ok, uint64_t t_done) {
+  for (size_t i = 0; i < g.batch.size(); ++i) {
+    const Pending& q = g.batch[i];
+    auto it = tickets.find(q.ticket);
+    if (it != tickets.end() && ok) {
+      ga_result& r = it->second.r;
+      const float* o = g.h_out + 7 * i;
+      r.E = o[0];
+      r.F[0] = o[1];
+      r.F[1] = o[2];
+      r.F[2] = o[3];
+      r.tau[0] = o[4];
+      r.tau[1] = o[5];
+      r.tau[2] = o[6];
+      r.t_submit_ns = q.t_submit;
+      r.t_start_ns = g.t_start;
+      r.t_done_ns = t_done;
+      it->second.done = true;
+    }
+    auto pit = pairs.find(q.pair);
+    if (pit != pairs.end() && --pit->second.inflight == 0 && pit->second.released) {
+      free_pair_locked(pit->second);
+      pairs.erase(pit);
+    }
+  }
+  stats.completed += g.batch.size();
+  g.batch.clear();
+  g.busy = false;
+  g.completed = false;
+  --busy_groups;
 }
 
 void ga_server::run() {
   (void)hipSetDevice(device);
+  std::unique_lock<std::mutex> lk(mu);
   for (;;) {
+    if (sticky != GA_OK && queued > 0) fail_queued_locked();
+    bool progress = false;
     std::vector<std::pair<SizeClass*, Group*>> to_launch;
-    std::vector<std::pair<SizeClass*, Group*>> busy;
-    {
-      std::unique_lock<std::mutex> lk(mu);
-      if (sticky != GA_OK && queued > 0) fail_queued_locked();
-      if (queued == 0 && busy_groups == 0) {
-        if (stop) break;
-        cv.wait_for(lk, std::chrono::milliseconds(20));
-        if (queued == 0 && busy_groups == 0) continue;
+    for (auto& cp : classes) {
+      SizeClass& c = *cp;
+      for (int gi = 0; gi < c.ngroups; ++gi) {
+        Group& g = c.groups[gi];
+        if (g.busy && g.completed) {
+          harvest_locked(g, true, now_ns());
+          progress = true;
+        }
+        if (!g.busy && !c.paused && !c.queue.empty() && sticky == GA_OK) {
+          const int k = (int)std::min<size_t>(c.queue.size(), (size_t)c.slots);
+          g.batch.assign(c.queue.begin(), c.queue.begin() + k);
+          c.queue.erase(c.queue.begin(), c.queue.begin() + k);
+          queued -= k;
+          fill_items(this, c, g);
+          g.busy = true;
+          g.completed = false;
+          g.callback = true;  // until launch() reports otherwise
+          g.t_start = now_ns();
+          ++busy_groups;
+          stats.launches += 1;
+          to_launch.push_back({&c, &g});
+        }
       }
-      for (auto& cp : classes) {
-        SizeClass& c = *cp;
-        for (int gi = 0; gi < c.ngroups; ++gi) {
-          Group& g = c.groups[gi];
-          if (g.busy) {
-            busy.push_back({&c, &g});
-          } else if (!c.paused && !c.queue.empty() && sticky == GA_OK) {
-            const int k = (int)std::min<size_t>(c.queue.size(), (size_t)c.slots);
-            g.batch.assign(c.queue.begin(), c.queue.begin() + k);
-            c.queue.erase(c.queue.begin(), c.queue.begin() + k);
-            queued -= k;
-            fill_items(this, c, g);
-            g.busy = true;
-            g.t_start = now_ns();
-            ++busy_groups;
-            stats.launches += 1;
-            to_launch.push_back({&c, &g});
+    }
+    if (!to_launch.empty()) {
+      lk.unlock();
+      for (auto& [c, g] : to_launch) launch(*c, *g);
+      lk.lock();
+      continue;
+    }
+    if (progress) continue;
+    if (stop && queued == 0 && busy_groups == 0) break;
+    // sleep until a submission, a completion or stop; after a quiet while,
+    // look at the busy groups' events for device errors (a failed stream
+    // never runs its completion callback)
+    if (cv.wait_for(lk, std::chrono::milliseconds(50)) == std::cv_status::timeout) {
+      for (auto& cp : classes)
+        for (int gi = 0; gi < cp->ngroups; ++gi) {
+          Group& g = cp->groups[gi];
+          if (!g.busy || g.completed) continue;
+          const hipError_t e = hipEventQuery(g.done);
+          if (e != hipSuccess && e != hipErrorNotReady) {
+            sticky = GA_EDEVICE;
+            harvest_locked(g, false, now_ns());
+          } else if (e == hipSuccess && !g.callback) {
+            harvest_locked(g, true, now_ns());  // no callback will come
           }
         }
-      }
     }
-    for (auto& [c, g] : to_launch) {
-      launch(*c, *g);
-      busy.push_back({c, g});
-    }
-    bool harvested = false;
-    for (auto& [c, g] : busy) {
-      const hipError_t e = hipEventQuery(g->done);
-      if (e == hipErrorNotReady) continue;
-      const uint64_t t_done = now_ns();
-      std::lock_guard<std::mutex> lk(mu);
-      if (e != hipSuccess) sticky = GA_EDEVICE;
-      for (size_t i = 0; i < g->batch.size(); ++i) {
-        const Pending& q = g->batch[i];
-        auto it = tickets.find(q.ticket);
-        if (it != tickets.end() && e == hipSuccess) {
-          ga_result& r = it->second.r;
-          const float* o = g->h_out + 7 * i;
-          r.E = o[0];
-          r.F[0] = o[1];
-          r.F[1] = o[2];
-          r.F[2] = o[3];
-          r.tau[0] = o[4];
-          r.tau[1] = o[5];
-          r.tau[2] = o[6];
-          r.t_submit_ns = q.t_submit;
-          r.t_start_ns = g->t_start;
-          r.t_done_ns = t_done;
-          it->second.done = true;
-        }
-        auto pit = pairs.find(q.pair);
-        if (pit != pairs.end() && --pit->second.inflight == 0 && pit->second.released) {
-          free_pair_locked(pit->second);
-          pairs.erase(pit);
-        }
-      }
-      stats.completed += g->batch.size();
-      g->batch.clear();
-      g->busy = false;
-      --busy_groups;
-      harvested = true;
-    }
-    if (to_launch.empty() && !harvested) std::this_thread::yield();
   }
 }
 
@@ -379,6 +413,7 @@ ga_status ga_server_destroy(ga_server* s) {
   (void)hipSetDevice(s->device);
   for (auto& cp : s->classes) {
     for (int gi = 0; gi < cp->ngroups; ++gi) free_group(cp->groups[gi]);
+    if (cp->stream) (void)hipStreamDestroy(cp->stream);
     if (cp->plan) ga_plan_destroy(cp->plan);
   }
   for (auto& kv : s->pairs) s->free_pair_locked(kv.second);
@@ -395,8 +430,7 @@ ga_status ga_pair_register(ga_server* s, const ga_part* A, const ga_part* B, con
   if (hipSetDevice(s->device) != hipSuccess) return GA_EDEVICE;
   const size_t spec_bytes = spectrum_elems(n) * sizeof(float2);
   const size_t n3 = (size_t)n * n * n;
-  const size_t pair_bytes = spec_bytes + (size_t)B->n_pts * 5 * sizeof(float) +
-                            (s->mode == GA_SERVE_LOCAL ? 16 * n3 : 0);
+  const size_t pair_bytes = (size_t)B->n_pts * 5 * sizeof(float) + (s->mode == GA_SERVE_LOCAL ? 16 * n3 : 2 * spec_bytes);
   SizeClass* c = nullptr;
   {
     std::unique_lock<std::mutex> lk(s->mu);
@@ -415,9 +449,14 @@ ga_status ga_pair_register(ga_server* s, const ga_part* A, const ga_part* B, con
         else return GA_ENOMEM;
       }
       if (ga_plan_create(&nc->plan, n, slots, 0) != GA_OK) return GA_EDEVICE;
+      if (hipStreamCreateWithFlags(&nc->stream, hipStreamNonBlocking) != hipSuccess) {
+        ga_plan_destroy(nc->plan);
+        return GA_EDEVICE;
+      }
       for (int gi = 0; gi < ngroups; ++gi)
-        if (!alloc_group(nc->groups[gi], s->mode, n, slots, nc->max_pts)) {
+        if (!alloc_group(nc->groups[gi], nc->stream, s, s->mode, n, slots, nc->max_pts)) {
           for (int gj = 0; gj < gi; ++gj) free_group(nc->groups[gj]);
+          (void)hipStreamDestroy(nc->stream);
           ga_plan_destroy(nc->plan);
           return GA_ENOMEM;
         }
@@ -446,7 +485,7 @@ ga_status ga_pair_register(ga_server* s, const ga_part* A, const ga_part* B, con
       bool ok = !(fail && fail[0] == '1');
       for (int gi = 0; gi < c->ngroups; ++gi) {
         free_group(c->groups[gi]);
-        ok = ok && alloc_group(c->groups[gi], s->mode, n, c->slots, B->n_pts);
+        ok = ok && alloc_group(c->groups[gi], c->stream, s, s->mode, n, c->slots, B->n_pts);
       }
       if (!ok) {
         s->sticky = GA_ENOMEM;
@@ -474,13 +513,14 @@ ga_status ga_pair_register(ga_server* s, const ga_part* A, const ga_part* B, con
   bool ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
             hipMalloc(&p.d_xyzr, sizeof(float) * 4 * B->n_pts) == hipSuccess &&
             hipMalloc(&p.d_w, sizeof(float) * B->n_pts) == hipSuccess &&
-            hipMalloc(&p.d_Ahat, spec_bytes) == hipSuccess &&
+
             hipMemcpy(p.d_xyzr, B->xyzr, sizeof(float) * 4 * B->n_pts, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(p.d_w, B->w, sizeof(float) * B->n_pts, hipMemcpyHostToDevice) == hipSuccess;
   float* dgrid = nullptr;
   void* dwork = nullptr;
+  float2* dAhat = nullptr;  // the stationary spectrum, needed only to derive the resident data
   if (ok) {
-    ok = hipMalloc(&dgrid, sizeof(float) * n3) == hipSuccess;
+    ok = hipMalloc(&dgrid, sizeof(float) * n3) == hipSuccess && hipMalloc(&dAhat, spec_bytes) == hipSuccess;
     if (ok && A->n_pts > 0) {
       ok = hipMalloc(&dA, sizeof(float) * 4 * A->n_pts) == hipSuccess &&
            hipMalloc(&dAw, sizeof(float) * A->n_pts) == hipSuccess &&
@@ -488,20 +528,24 @@ ga_status ga_pair_register(ga_server* s, const ga_part* A, const ga_part* B, con
            hipMemcpy(dAw, A->w, sizeof(float) * A->n_pts, hipMemcpyHostToDevice) == hipSuccess;
     }
     ok = ok && ga_splat(c->plan, dA, dAw, A->n_pts, nullptr, nullptr, sigma, 1, dgrid, st) == GA_OK &&
-         ga_fft3d(c->plan, GA_R2C, dgrid, p.d_Ahat, 1, nullptr, 0, st) == GA_OK;
+         ga_fft3d(c->plan, GA_R2C, dgrid, dAhat, 1, nullptr, 0, st) == GA_OK;
     if (ok && s->mode == GA_SERVE_LOCAL) {
       const size_t wb = ga_workspace_size(c->plan, GA_OP_FIELD_GRAD, 1, 0);
       ok = hipMalloc(&p.d_FA, 16 * n3) == hipSuccess && hipMalloc(&dwork, wb) == hipSuccess &&
-           ga_field_grad(c->plan, dgrid, reinterpret_cast<const float*>(p.d_Ahat), p.d_FA, dwork, wb, st) == GA_OK;
+           ga_field_grad(c->plan, dgrid, reinterpret_cast<const float*>(dAhat), p.d_FA, dwork, wb, st) == GA_OK;
+    } else if (ok) {
+      ok = hipMalloc(&p.d_AX, 2 * spec_bytes) == hipSuccess &&
+           ga_pose_prepare(c->plan, reinterpret_cast<const float*>(dAhat), reinterpret_cast<float*>(p.d_AX), st) ==
+               GA_OK;
     }
     ok = ok && hipStreamSynchronize(st) == hipSuccess;
   }
-  for (void* q : {(void*)dA, (void*)dAw, (void*)dgrid, dwork})
+  for (void* q : {(void*)dA, (void*)dAw, (void*)dgrid, dwork, (void*)dAhat})
     if (q) (void)hipFree(q);
   if (st) (void)hipStreamDestroy(st);
   std::lock_guard<std::mutex> lk(s->mu);
   if (!ok) {
-    for (void* q : {(void*)p.d_xyzr, (void*)p.d_w, (void*)p.d_Ahat, (void*)p.d_FA})
+    for (void* q : {(void*)p.d_xyzr, (void*)p.d_w, (void*)p.d_AX, (void*)p.d_FA})
       if (q) (void)hipFree(q);
     s->bytes -= pair_bytes;
     return GA_EDEVICE;

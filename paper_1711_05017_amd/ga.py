@@ -21,7 +21,7 @@ GA_OK, GA_PENDING = 0, 1
 GA_R2C, GA_C2R = -1, 1
 GA_FIELDS, GA_SINGLE = 0, 1
 GA_OP_FFT_C2R, GA_OP_CORRELATE, GA_OP_ENERGY, GA_OP_FORCE_FIELDS, GA_OP_FORCE_SINGLE = 1, 2, 3, 4, 5
-GA_OP_FIELD_GRAD, GA_OP_POSE_LOCAL, GA_OP_SCORE = 6, 7, 8
+GA_OP_FIELD_GRAD, GA_OP_POSE_LOCAL, GA_OP_SCORE, GA_OP_POSE_SPECTRAL = 6, 7, 8, 9
 GA_SCORE_RE, GA_SCORE_IM = 1, 2
 GA_SERVE_LOCAL, GA_SERVE_SPECTRAL = 0, 1
 GA_PLAN_AXIS_PASSES = 1
@@ -36,7 +36,7 @@ EXPORTS = [
     "ga_server_get_stats", "ga_batch_create", "ga_batch_launch", "ga_batch_destroy",
     "ga_plan_autotune", "ga_plan_set_tuning", "ga_plan_get_tuning", "ga_lowpass",
     "ga_spectral_rotate", "ga_field_table", "ga_field_table_query", "ga_score", "ga_plan_set_overlap",
-    "ga_plan_get_overlap", "ga_force_torque_noalloc",
+    "ga_plan_get_overlap", "ga_force_torque_noalloc", "ga_pose_prepare", "ga_pose_spectral",
 ]
 GA_K_SPLAT, GA_K_PLANE_FWD, GA_K_STRIP, GA_K_PLANE_INV, GA_K_READOUT, GA_K_BIN = 0, 1, 2, 3, 4, 5
 KERNEL_KINDS = {"splat": 0, "plane_fwd": 1, "strip": 2, "plane_inv": 3, "readout": 4, "bin": 5}
@@ -94,6 +94,9 @@ _SIGS = {
                                          _vp]),
     "ga_force_torque_noalloc": (ctypes.c_int32, [_vp, _vp, _vp, _vp, ctypes.c_int32, _vp, _vp]),
     "ga_field_grad": (ctypes.c_int32, [_vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "ga_pose_prepare": (ctypes.c_int32, [_vp, _vp, _vp, _vp]),
+    "ga_pose_spectral": (ctypes.c_int32, [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_float, _vp,
+                                          ctypes.c_int32, _vp, _vp, ctypes.c_size_t, _vp]),
     "ga_pose_local": (ctypes.c_int32, [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_float, _vp,
                                        ctypes.c_int32, _vp, _vp, ctypes.c_size_t, _vp]),
     "ga_profile_enable": (ctypes.c_int32, [_vp, ctypes.c_int32]),
@@ -454,6 +457,40 @@ def ga_pose_local(plan: Plan, FA4: torch.Tensor, xyzr: torch.Tensor, w: torch.Te
     st = load().ga_pose_local(plan.handle, _ptr(FA4), _ptr(xyzr), _ptr(w), m, _ptr(R), _host_f32(c, 3), float(sigma),
                               _ptr(t), n_poses, _ptr(out), _ptr(work), int(work.numel()), _stream(stream))
     _check("ga_pose_local", st)
+    return out
+
+
+def ga_pose_prepare(plan: Plan, Ahat: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Resident AX, DX of the stationary part (2 x half spectrum) for ga_pose_spectral."""
+    n = plan.n
+    _need(Ahat, torch.complex64, _spec_elems(n), "Ahat")
+    if out is None:
+        out = torch.empty((2,) + spectrum_shape(n), dtype=torch.complex64, device=Ahat.device)
+    _need(out, torch.complex64, 2 * _spec_elems(n), "out")
+    _check("ga_pose_prepare", load().ga_pose_prepare(plan.handle, _ptr(Ahat), _ptr(out), _stream(stream)))
+    return out
+
+
+def ga_pose_spectral(plan: Plan, AX2: torch.Tensor, xyzr: torch.Tensor, w: torch.Tensor, R: torch.Tensor, c,
+                     t: torch.Tensor, sigma: float = 0.5, out: Optional[torch.Tensor] = None, work=None,
+                     stream=None) -> torch.Tensor:
+    """(E, F, tau) at n_poses single poses by re-correlation: splat and z/y
+    transforms of the rotated part per pose, the x transform folded into AX2."""
+    n = plan.n
+    m = _samples(xyzr, w)
+    n_poses = int(t.shape[0])
+    _need(AX2, torch.complex64, 2 * _spec_elems(n), "AX2")
+    _need(R, torch.float32, 9 * n_poses, "R", exact=True)
+    _need(t, torch.float32, 3 * n_poses, "t", exact=True)
+    if out is None:
+        out = torch.empty((n_poses, 7), dtype=torch.float32, device=t.device)
+    _need(out, torch.float32, 7 * n_poses, "out")
+    if work is None:
+        work = plan.workspace(GA_OP_POSE_SPECTRAL, n_poses, m, device=t.device)
+    st = load().ga_pose_spectral(plan.handle, _ptr(AX2), _ptr(xyzr), _ptr(w), m, _ptr(R), _host_f32(c, 3),
+                                 float(sigma), _ptr(t), n_poses, _ptr(out), _ptr(work), int(work.numel()),
+                                 _stream(stream))
+    _check("ga_pose_spectral", st)
     return out
 
 

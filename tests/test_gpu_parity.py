@@ -278,6 +278,67 @@ def test_pose_local_matches_oracle(G, n, npts, nrot):
     assert O.rel_l2(got[:, 4:7], ref[:, 4:7]) < FORCE_TOL
 
 
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("n,npts,nrot", [(16, 40, 2), (24, 120, 3), (48, 400, 3), (64, 600, 2), (96, 1000, 2),
+                                         (128, 2500, 3), (192, 1500, 2)])
+def test_pose_spectral_matches_oracle(G, n, npts, nrot):
+    """Re-correlated single poses (splat and z/y transforms of the rotated
+    part per pose, each x-plane's share of the single-translation sums
+    against the resident AX, DX): every pose its own rotation, translations
+    at both ends of the lattice, negative and fractional (rounded half away
+    from zero); against the oracle's single-pose sums and the local-sum
+    entry point. 128 runs the two-stage kernel, the other edges the general
+    one (with its radix-3 schedules at 24, 48, 96, 192)."""
+    A = _part(n, 1600 + n, npts, 1.0, 4.0)
+    B = _part(n, 1700 + n, npts // 2 + 1, 1.0, 4.0, conf=n / 6)
+    cB = B.ref_point()
+    rots = synth.shoemake_rotations(1800 + n, nrot)
+    rng = np.random.default_rng(n + 1)
+    ts = np.array([n / 2 + rng.uniform(-3, 3, 3) for _ in range(nrot)], np.float32)
+    ts[0] = [n / 2 - 0.5, n / 2 + 1.5, -n + n / 2]  # ties and a negative translation
+    plan = G.Plan(n, max_batch=4)
+    u = G.ga_splat(plan, _dev(A.xyzr), _dev(A.w))
+    Ahat = G.ga_fft3d(plan, G.GA_R2C, u)[0].contiguous()
+    AX = G.ga_pose_prepare(plan, Ahat)
+    R = _dev(rots.reshape(nrot, 9).astype(np.float32))
+    got = G.ga_pose_spectral(plan, AX, _dev(B.xyzr), _dev(B.w), R, cB, _dev(ts)).cpu().numpy().astype(np.float64)
+    FA = G.ga_field_grad(plan, u[0], Ahat)
+    loc = G.ga_pose_local(plan, FA, _dev(B.xyzr), _dev(B.w), R, cB, _dev(ts)).cpu().numpy().astype(np.float64)
+    uA = O.splat(A.xyzr[:, :3].astype(np.float64), A.xyzr[:, 3], A.w, n)
+    g = O.grad_spectral(uA)
+    ref = []
+    for r in range(nrot):
+        uB = O.splat(O.place(B.xyzr[:, :3], rots[r], cB), B.xyzr[:, 3], B.w, n)
+        t_lat = [np.floor(abs(v) + 0.5) * np.sign(v) for v in ts[r]]
+        ref.append(O.local_pose_sum(uA, uB, t_lat, grad=g))
+    ref = np.array(ref)
+    assert np.abs(ref[:, 0]).max() > 0
+    for out in (got, loc):
+        assert O.rel_l2(out[:, 0], ref[:, 0]) < FIELD_TOL
+        assert O.rel_l2(out[:, 1:4], ref[:, 1:4]) < FORCE_TOL
+        assert O.rel_l2(out[:, 4:7], ref[:, 4:7]) < FORCE_TOL
+
+
+def test_pose_spectral_rejects_bad_arguments(G):
+    n = 32
+    plan = G.Plan(n)
+    AX = torch.zeros((2, n, n, n // 2 + 1), dtype=torch.complex64, device="cuda")
+    x = torch.zeros((4, 4), device="cuda")
+    w = torch.ones(4, device="cuda")
+    R = torch.eye(3, device="cuda").reshape(1, 9)
+    t = torch.zeros((1, 3), device="cuda")
+    with pytest.raises(G.GaError):  # sigma <= 0
+        G.ga_pose_spectral(plan, AX, x, w, R, [0, 0, 0], t, sigma=0.0)
+    with pytest.raises(G.GaError):  # workspace too small
+        G.ga_pose_spectral(plan, AX, x, w, R, [0, 0, 0], t, work=torch.empty(16, dtype=torch.uint8, device="cuda"))
+    big = G.Plan(256)
+    with pytest.raises(G.GaError):  # the separate-axis edges have no fused pass
+        G.ga_pose_prepare(big, torch.zeros((256, 256, 129), dtype=torch.complex64, device="cuda"))
+    # no poses: nothing to do
+    out = G.ga_pose_spectral(plan, AX, x, w, R[:0], [0, 0, 0], t[:0])
+    assert out.shape == (0, 7)
+
+
 def test_pose_local_edge_cases(G):
     n = 32
     A = _part(n, 31, 80, 1.0, 3.0)
@@ -305,6 +366,40 @@ def test_pose_local_edge_cases(G):
         G.ga_pose_local(plan, FA, _dev(B.xyzr), _dev(B.w), R, B.ref_point(), t, sigma=0.0)
     with pytest.raises(G.GaError):
         G.ga_pose_local(plan, FA, _dev(B.xyzr), _dev(B.w), R, [np.nan, 0, 0], t)
+
+
+def test_translations_that_are_not_finite_give_nan_outputs(G):
+    """Device-resident translations are never converted to integers when they
+    are NaN, infinite or beyond the float32 lattice: every readout gives NaN
+    for such a pose and the usual values for the others."""
+    n = 32
+    A = _part(n, 41, 80, 1.0, 3.0)
+    B = _part(n, 42, 60, 1.0, 3.0, conf=5.0)
+    cB = B.ref_point()
+    plan = G.Plan(n, max_batch=4)
+    u = G.ga_splat(plan, _dev(A.xyzr), _dev(A.w))
+    Ahat = G.ga_fft3d(plan, G.GA_R2C, u)[0].contiguous()
+    Bhat4 = G.ga_fft3d(plan, G.GA_R2C, G.ga_splat(plan, _dev(B.xyzr), _dev(B.w), R=np.eye(3), c=cB, channels=4))
+    poses = np.array([[16, 16, 16], [np.nan, 16, 16], [16, np.inf, 16], [16, 16, -np.inf], [3e38, 0, 0],
+                      [15, 17, 16]], np.float32)
+    good = [0, 5]
+    bad = [1, 2, 3, 4]
+    R = _dev(np.eye(3, dtype=np.float32)[None].repeat(len(poses), 0).reshape(-1, 9))
+    FA = G.ga_field_grad(plan, u[0], Ahat)
+    outs = {
+        "fields": G.ga_force_torque(plan, Ahat, Bhat4, _dev(poses), G.GA_FIELDS),
+        "single": G.ga_force_torque(plan, Ahat, Bhat4, _dev(poses), G.GA_SINGLE),
+        "local": G.ga_pose_local(plan, FA, _dev(B.xyzr), _dev(B.w), R, cB, _dev(poses)),
+        "spectral": G.ga_pose_spectral(plan, G.ga_pose_prepare(plan, Ahat), _dev(B.xyzr), _dev(B.w), R, cB,
+                                       _dev(poses)),
+    }
+    ref = outs["single"].cpu().numpy()[good]
+    for name, o in outs.items():
+        o = o.cpu().numpy()
+        assert np.all(np.isnan(o[bad])), name
+        assert np.all(np.isfinite(o[good])), name
+        assert O.rel_l2(o[good, 0], ref[:, 0]) < FIELD_TOL, name
+        assert O.rel_l2(o[good, 1:], ref[:, 1:]) < FORCE_TOL, name
 
 
 # ---------------------------------------------------------------------------
