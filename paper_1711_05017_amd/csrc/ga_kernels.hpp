@@ -286,9 +286,10 @@ struct QueryItem {
 };
 
 // Binning of heterogeneous queries: item b's samples, placed with its own
-// rotation, into rec[b*stride ...]. grid = batch, block = 256.
+// rotation, into rec[b*stride ...]. grid = batch, block = 1024 (a serving
+// launch has few queries: the block's width sets its latency).
 template <int N>
-__global__ void __launch_bounds__(256) k_bin_items(const QueryItem* __restrict__ items, SplatParams base,
+__global__ void __launch_bounds__(1024) k_bin_items(const QueryItem* __restrict__ items, SplatParams base,
                                                    long long stride, Placed* __restrict__ rec, int* __restrict__ off,
                                                    float* __restrict__ rmax, int4* __restrict__ cand) {
   const int b = blockIdx.x;
@@ -706,13 +707,11 @@ __device__ __forceinline__ void wave_splat(const SplatParams& p, bool hit, const
   }
 }
 
-// Pass 1. grid = (N planes, batch, NCH == 4 ? 3 : 1). GRID: real grids
-// `grid` [batch][N^3] (NCH = 1). Otherwise splat from the binned samples
-// (p.rec, p.cand) of each batch member; with NCH = 4 workgroup z splats channel
-// pass z (u, then yhat_y u, then yhat_z u; yhat_x u is u scaled per plane). Writes NCH spectra planes per batch member,
-// out[((b*NCH + c)*N + x)*N*H]: u, and with NCH = 4 the moment densities
-// yhat_x u, yhat_y u, yhat_z u.
-template <int N, bool GRID, int NCH>
+// Pass 1. grid = (N planes, batch). GRID: real grids `grid` [batch][N^3].
+// Otherwise splat from the binned samples (p.rec, p.cand) of each batch
+// member. Writes the plane spectra of every batch member,
+// out[(b*N + x)*N*H].
+template <int N, bool GRID>
 __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_fwd(SplatParams p,
                                                                                const float* __restrict__ grid,
                                                                                float2* __restrict__ out,
@@ -725,63 +724,50 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_fwd
   // the y transforms store the spectrum straight to global memory up to
   // edge 128; the 192 transforms need their registers (copy-out from LDS)
   constexpr bool kDirect = N <= 128;
-  auto run_pass = [&](int pass) {
-    const int chan = (pass == 0) ? 0 : pass + 1;  // 0, 2, 3
-    float2* dst0 = out + (((size_t)b * NCH + chan) * N + x) * plane_sz;
-    float2* dst1 = (NCH == 4 && chan == 0) ? out + (((size_t)b * NCH + 1) * N + x) * plane_sz : nullptr;
-    if constexpr (GRID) {
-      const float2* src = reinterpret_cast<const float2*>(grid + ((size_t)b * N + x) * N * N);
-      // two adjacent z values of one row land in one pair-region entry each
-      batched_copy<N * N / 2, P::THREADS, float2>([&](int i) { return src[i]; }, [&](int i, float2 v) {
-        const int y = (2 * i) / N, z = (2 * i) % N;
-        Wf[P::zs(y >> 1, z) * 2 + (y & 1)] = v.x;
-        Wf[P::zs(y >> 1, z + 1) * 2 + (y & 1)] = v.y;
-      });
-    } else {
-      // binned samples (p.rec, p.cand): each wavefront tests its candidates
-      // and splats its hits (wave_splat); a plane no sample reaches has a
-      // zero spectrum, written directly
-      const int4 rg = p.cand[(size_t)b * N + x];
-      const int ncand = rg.y + rg.w;
-      const Placed* rb = p.rec + (size_t)b * p.n_pts;
-      const int lane = tid & 63, wave = tid >> 6;
-      auto pidx = [](int yy, int zz) { return P::zs(yy >> 1, zz) * 2 + (yy & 1); };
-      Placed q;
-      const bool is_cand = wave_cand(rb, rg, lane * P::WAVES + wave, q);
-      float4* W4 = reinterpret_cast<float4*>(W);
-      for (int i = tid; i < P::SIZE / 2; i += P::THREADS) W4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-      WaveHit h;
-      bool hit = is_cand && wave_hit<N>(p, q, x, h);
-      if (!__syncthreads_or(hit) && ncand <= 64 * P::WAVES) {
-        float4* d0 = reinterpret_cast<float4*>(dst0);
-        float4* d1 = reinterpret_cast<float4*>(dst1);
-        for (int i = tid; i < (int)(plane_sz / 2); i += P::THREADS) {
-          d0[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-          if (dst1) d1[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-        return;
-      }
-      for (int c0 = 0;;) {
-        wave_splat<N>(p, hit, h, chan, Wf, pidx);
-        c0 += 64 * P::WAVES;
-        if (c0 >= ncand) break;  // uniform
-        const bool more = wave_cand(rb, rg, c0 + lane * P::WAVES + wave, q);
-        hit = more && wave_hit<N>(p, q, x, h);
-      }
+  float2* dst0 = out + ((size_t)b * N + x) * plane_sz;
+  if constexpr (GRID) {
+    const float2* src = reinterpret_cast<const float2*>(grid + ((size_t)b * N + x) * N * N);
+    // two adjacent z values of one row land in one pair-region entry each
+    batched_copy<N * N / 2, P::THREADS, float2>([&](int i) { return src[i]; }, [&](int i, float2 v) {
+      const int y = (2 * i) / N, z = (2 * i) % N;
+      Wf[P::zs(y >> 1, z) * 2 + (y & 1)] = v.x;
+      Wf[P::zs(y >> 1, z + 1) * 2 + (y & 1)] = v.y;
+    });
+  } else {
+    // binned samples (p.rec, p.cand): each wavefront tests its candidates
+    // and splats its hits (wave_splat); a plane no sample reaches has a zero
+    // spectrum, written directly
+    const int4 rg = p.cand[(size_t)b * N + x];
+    const int ncand = rg.y + rg.w;
+    const Placed* rb = p.rec + (size_t)b * p.n_pts;
+    const int lane = tid & 63, wave = tid >> 6;
+    auto pidx = [](int yy, int zz) { return P::zs(yy >> 1, zz) * 2 + (yy & 1); };
+    Placed q;
+    const bool is_cand = wave_cand(rb, rg, lane * P::WAVES + wave, q);
+    float4* W4 = reinterpret_cast<float4*>(W);
+    for (int i = tid; i < P::SIZE / 2; i += P::THREADS) W4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    WaveHit h;
+    bool hit = is_cand && wave_hit<N>(p, q, x, h);
+    if (!__syncthreads_or(hit) && ncand <= 64 * P::WAVES) {
+      float4* d0 = reinterpret_cast<float4*>(dst0);
+      for (int i = tid; i < (int)(plane_sz / 2); i += P::THREADS) d0[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+      return;
     }
-    __syncthreads();
-    {
-      Twiddles<N> tw;
-      load_twiddles<N>(tw, table, (tid & 63) % P::L);
-      plane_forward_out<N, kDirect>(W, tw, dst0, dst1, yhat(x, N));
+    for (int c0 = 0;;) {
+      wave_splat<N>(p, hit, h, 0, Wf, pidx);
+      c0 += 64 * P::WAVES;
+      if (c0 >= ncand) break;  // uniform
+      const bool more = wave_cand(rb, rg, c0 + lane * P::WAVES + wave, q);
+      hit = more && wave_hit<N>(p, q, x, h);
     }
-    if constexpr (!kDirect) {
-      plane_to_global<N>(dst0, W, 1.0f);
-      if (dst1) plane_to_global<N>(dst1, W, yhat(x, N));
-    }
-  };
-  if constexpr (NCH == 1) run_pass(0);
-  else run_pass(blockIdx.z);  // one channel pass per workgroup: grid z = 3
+  }
+  __syncthreads();
+  {
+    Twiddles<N> tw;
+    load_twiddles<N>(tw, table, (tid & 63) % P::L);
+    plane_forward_out<N, kDirect>(W, tw, dst0, nullptr, 1.0f);
+  }
+  if constexpr (!kDirect) plane_to_global<N>(dst0, W, 1.0f);
 }
 
 // ---------------------------------------------------------------------------
@@ -905,36 +891,48 @@ __device__ __forceinline__ void block_sum7(const SingleAcc& acc, double* red /* 
 }
 
 // Body of the pass-1 kernels of the two-stage layout: splat the binned
-// samples of batch member blockIdx.y (p.rec, p.cand) into plane x = blockIdx.x
-// once, then transform NCH = 1 or 4 channels: u, and the moment densities
-// yhat_x u (u's spectrum times yhat(x)), yhat_y u and yhat_z u, whose
-// transforms start from the lane's saved inputs scaled per element.
-// SINGLE = false: the plane spectra go to out[((b*NCH + c)*N + x)*N*H].
-// SINGLE = true (NCH = 4): each plane adds its share of the 7
+// samples of batch member blockIdx.y (p.rec, p.cand) into plane x =
+// blockIdx.x, transform it along z and y.
+// SINGLE = false: the plane spectrum of u goes to out[(b*N + x)*N*H].
+// SINGLE = true: channel pass z = blockIdx.z (u, then yhat_y u, then
+// yhat_z u; yhat_x u is u times yhat(x)) adds the plane's share of the 7
 // single-translation sums of query items[b] (SingleAcc) and writes them to
-// part[(b*N + x)*7 ..]; nothing else is written.
-template <int N, int NCH, bool SINGLE>
+// part[((b*3 + z)*N + x)*7 ..]; nothing else is written.
+template <int N, bool SINGLE>
 __device__ __forceinline__ void plane_splat_body(const SplatParams& p, float2* __restrict__ out,
                                                  const QueryItem* __restrict__ items, double* __restrict__ part,
                                                  const float2* __restrict__ table) {
   using P = PlaneP<N>;
   constexpr int H = P::H, L = P::L, R1 = P::R1, NB1 = P::NB1, T = N / 2;
   static_assert(P::R0 == 16 && R1 == 8 && L == 8 && NB1 == 2, "schedule of the code below");
-  static_assert(NCH == 1 || NCH == 4, "channels");
-  static_assert(!SINGLE || NCH == 4, "single-translation sums need the 4 channels");
   __shared__ __attribute__((aligned(16))) float2 W[P::SIZE];
   __shared__ float2 tabc[SINGLE ? N : 1];  // exp(+2 pi i m / N)
   __shared__ double red[SINGLE ? 7 * P::WAVES : 1];
   const int x = blockIdx.x, b = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tau = lane / L, l = lane % L;
-  // stage-1 twiddles exp(-2 pi i r j / N), j = l + L bb (both transforms)
-  float2 tw[NB1][R1];
+  const int pass = SINGLE ? (int)blockIdx.z : 0;
+  const int chan = (pass == 0) ? 0 : pass + 1;  // splat multiplier: 0 none, 2 yhat_y, 3 yhat_z
+  // stage-1 twiddles exp(-2 pi i r j / N), j = l + L bb (both transforms):
+  // in registers, or (single-translation mode, whose sums take registers)
+  // read from the LDS table when needed
+  float2 tw[SINGLE ? 1 : NB1][R1];
+  if constexpr (!SINGLE) {
 #pragma unroll
-  for (int bb = 0; bb < NB1; ++bb)
+    for (int bb = 0; bb < NB1; ++bb)
 #pragma unroll
-    for (int r = 1; r < R1; ++r) tw[bb][r] = table[r * (l + L * bb)];
+      for (int r = 1; r < R1; ++r) tw[bb][r] = table[r * (l + L * bb)];
+  }
+  auto twid = [&](int bb, int r) -> float2 {
+    if constexpr (SINGLE) {
+      const float2 e = tabc[r * (l + L * bb)];
+      return make_float2(e.x, -e.y);
+    } else {
+      return tw[bb][r];
+    }
+  };
   const size_t plane_sz = (size_t)N * H;
-  auto dst = [&](int c) { return out + (((size_t)b * NCH + c) * N + x) * plane_sz; };
+  float2* dst0 = SINGLE ? nullptr : out + ((size_t)b * N + x) * plane_sz;
+  double* dstp = SINGLE ? part + (((size_t)b * 3 + pass) * N + x) * 7 : nullptr;
   const float s1 = yhat(x, N);
   // single-translation sums: the query's translation and plane x + t_x of
   // the resident AX and DX
@@ -945,8 +943,7 @@ __device__ __forceinline__ void plane_splat_body(const SplatParams& p, float2* _
     const QueryItem& it = items[b];
     ty = it.t[1];
     tz = it.t[2];
-    const int xs = (x + it.t[0]) % N;
-    AXp = it.AX + (size_t)xs * plane_sz;
+    AXp = it.AX + (size_t)((x + it.t[0]) % N) * plane_sz;
     for (int i = tid; i < N; i += P::THREADS) tabc[i] = make_float2(table[i].x, -table[i].y);
   }
 
@@ -965,23 +962,20 @@ __device__ __forceinline__ void plane_splat_body(const SplatParams& p, float2* _
   for (int i = tid; i < P::SIZE / 2; i += P::THREADS) W4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
   WaveHit h;
   bool hit = is_cand && wave_hit<N>(sp, q, x, h);
-  // A plane that no sample reaches is zero, and so are its spectra: they are
-  // written directly, without the transforms.
+  // A plane that no sample reaches is zero, and so is its spectrum: it is
+  // written directly (or adds nothing), without the transforms.
   if (!__syncthreads_or(hit) && ncand <= 64 * P::WAVES) {
     if constexpr (SINGLE) {
-      if (tid < 7) part[((size_t)b * N + x) * 7 + tid] = 0.0;
+      if (tid < 7) dstp[tid] = 0.0;
     } else {
-#pragma unroll
-      for (int c = 0; c < NCH; ++c) {
-        float4* d = reinterpret_cast<float4*>(dst(c));
-        for (int i = tid; i < (int)(plane_sz / 2); i += P::THREADS) d[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-      }
+      float4* d = reinterpret_cast<float4*>(dst0);
+      for (int i = tid; i < (int)(plane_sz / 2); i += P::THREADS) d[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     return;
   }
   float* Wf = reinterpret_cast<float*>(W);
   for (int c0 = 0;;) {
-    wave_splat<N>(sp, hit, h, 0, Wf, pidx);
+    wave_splat<N>(sp, hit, h, chan, Wf, pidx);
     c0 += 64 * P::WAVES;
     if (c0 >= ncand) break;  // uniform
     const bool more = wave_cand(rb, rg, c0 + lane * P::WAVES + wave, q);
@@ -989,113 +983,100 @@ __device__ __forceinline__ void plane_splat_body(const SplatParams& p, float2* _
   }
   __syncthreads();
 
-  // the z-transform inputs of this lane: row pair t = 8 wave + tau at
-  // positions l + 8 r (every plane value is read by exactly one lane)
-  const int t = P::TPW * wave + tau;
-  float2* zb = W + P::al(t) + l;  // position l + m (m a multiple of 8) at zb[be(m)]
-  float2 vs[16];
+  // z: complex transform of row pair t = 8 wave + tau (rows t and t + N/2)
+  {
+    const int t = P::TPW * wave + tau;
+    float2* zb = W + P::al(t) + l;  // position l + m (m a multiple of 8) at zb[be(m)]
+    float2 v[16];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) vs[r] = zb[P::be(8 * r)];
-  const float hy0 = yhat(t, N), hy1 = yhat(t + T, N);
-
-#pragma unroll 1
-  for (int pass = 0; pass < (NCH == 4 ? 3 : 1); ++pass) {
-    // pass 0: u; pass 1: yhat_y u; pass 2: yhat_z u
-    if (pass > 0) __syncthreads();  // the previous pass's y transforms are done with LDS
-    // z: complex transform of row pair t
-    {
-      float2 v[16];
+    for (int r = 0; r < 16; ++r) v[r] = zb[P::be(8 * r)];
+    Bfly<16, -1>::run(v);
+    float2* zw = W + P::al(t) + 17 * l;  // position 16 l + r at be(16 l + r) = 17 l + r
+    wave_sync();
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        v[r] = vs[r];
-        if (pass == 1) v[r] = make_float2(v[r].x * hy0, v[r].y * hy1);
-        if (pass == 2) v[r] = make_float2(v[r].x * yhat(l + 8 * r, N), v[r].y * yhat(l + 8 * r, N));
-      }
-      Bfly<16, -1>::run(v);
-      float2* zw = W + P::al(t) + 17 * l;  // position 16 l + r at be(16 l + r) = 17 l + r
-      wave_sync();
+    for (int r = 0; r < 16; ++r) zw[r] = v[r];
+    wave_sync();
+    float2 u[NB1][R1];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) zw[r] = v[r];
-      wave_sync();
-      float2 u[NB1][R1];
+    for (int bb = 0; bb < NB1; ++bb)
 #pragma unroll
-      for (int bb = 0; bb < NB1; ++bb)
+      for (int r = 0; r < R1; ++r) u[bb][r] = zb[P::be(8 * bb + 16 * r)];
+    wave_sync();
 #pragma unroll
-        for (int r = 0; r < R1; ++r) u[bb][r] = zb[P::be(8 * bb + 16 * r)];
-      wave_sync();
+    for (int bb = 0; bb < NB1; ++bb) {
 #pragma unroll
-      for (int bb = 0; bb < NB1; ++bb) {
-#pragma unroll
-        for (int r = 1; r < R1; ++r) u[bb][r] = cmul(u[bb][r], tw[bb][r]);
-        Bfly<8, -1>::run(u[bb]);
-      }
-#pragma unroll
-      for (int bb = 0; bb < NB1; ++bb)
-#pragma unroll
-        for (int r = 0; r < R1; ++r) zb[P::be(8 * bb + 16 * r)] = u[bb][r];  // Z_t(k), k = l + 8 bb + 16 r
+      for (int r = 1; r < R1; ++r) u[bb][r] = cmul(u[bb][r], twid(bb, r));
+      Bfly<8, -1>::run(u[bb]);
     }
-    __syncthreads();
+#pragma unroll
+    for (int bb = 0; bb < NB1; ++bb)
+#pragma unroll
+      for (int r = 0; r < R1; ++r) zb[P::be(8 * bb + 16 * r)] = u[bb][r];  // Z_t(k), k = l + 8 bb + 16 r
+  }
+  __syncthreads();
 
-    // y: column transform c = 8 wave + tau over rows 0 .. N-1
-    float2* dst0 = SINGLE ? nullptr : dst(pass == 0 ? 0 : pass + 1);
-    float2* dst1 = (!SINGLE && NCH == 4 && pass == 0) ? dst(1) : nullptr;
+  // y: column transform c = 8 wave + tau over rows 0 .. N-1
+  {
+    const int c = P::TPW * wave + tau;
+    const int b1 = P::be(c), b2 = P::be(c == 0 ? T : N - c);
+    float2* r1 = W + P::al(l) + b1;  // row l + 8 m of column c at r1[al(8 m)]
+    float2* r2 = W + P::al(l) + b2;  // ... of column N - c (or N/2)
+    float2 v[16];
     {
-      const int c = P::TPW * wave + tau;
-      const int b1 = P::be(c), b2 = P::be(c == 0 ? T : N - c);
-      float2* r1 = W + P::al(l) + b1;  // row l + 8 m of column c at r1[al(8 m)]
-      float2* r2 = W + P::al(l) + b2;  // ... of column N - c (or N/2)
-      float2 v[16];
-      {
-        float2 z1[8], z2[8];
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          z1[r] = r1[P::al(8 * r)];
-          z2[r] = r2[P::al(8 * r)];
-        }
-        if (c != 0) {
-#pragma unroll
-          for (int r = 0; r < 8; ++r) {
-            v[r] = make_float2(z1[r].x + z2[r].x, z1[r].y - z2[r].y);      // row l + 8 r
-            v[r + 8] = make_float2(z1[r].y + z2[r].y, z2[r].x - z1[r].x);  // row l + 8 r + N/2
-          }
-        } else {
-          // real columns kz = 0 (real part) and kz = N/2 (imaginary part)
-#pragma unroll
-          for (int r = 0; r < 8; ++r) {
-            v[r] = make_float2(z1[r].x + z1[r].x, z2[r].x + z2[r].x);
-            v[r + 8] = make_float2(z1[r].y + z1[r].y, z2[r].y + z2[r].y);
-          }
-        }
-      }
-      Bfly<16, -1>::run(v);
-      float2* w1 = W + P::al(8 * l) + b1;  // position 16 l + r: row 8 l + (r & 7)
-      float2* w2 = W + P::al(8 * l) + b2;
-      wave_sync();
+      float2 z1[8], z2[8];
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
-        w1[P::al(r)] = v[r];
-        w2[P::al(r)] = v[r + 8];
+        z1[r] = r1[P::al(8 * r)];
+        z2[r] = r2[P::al(8 * r)];
       }
-      wave_sync();
-      float2 u[NB1][R1];
+      if (c != 0) {
 #pragma unroll
-      for (int r = 0; r < R1; ++r) {
-        u[0][r] = r1[P::al(8 * r)];  // position l + 16 r
-        u[1][r] = r2[P::al(8 * r)];  // position l + 8 + 16 r
+        for (int r = 0; r < 8; ++r) {
+          v[r] = make_float2(z1[r].x + z2[r].x, z1[r].y - z2[r].y);      // row l + 8 r
+          v[r + 8] = make_float2(z1[r].y + z2[r].y, z2[r].x - z1[r].x);  // row l + 8 r + N/2
+        }
+      } else {
+        // real columns kz = 0 (real part) and kz = N/2 (imaginary part)
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          v[r] = make_float2(z1[r].x + z1[r].x, z2[r].x + z2[r].x);
+          v[r + 8] = make_float2(z1[r].y + z1[r].y, z2[r].y + z2[r].y);
+        }
       }
+    }
+    Bfly<16, -1>::run(v);
+    float2* w1 = W + P::al(8 * l) + b1;  // position 16 l + r: row 8 l + (r & 7)
+    float2* w2 = W + P::al(8 * l) + b2;
+    wave_sync();
 #pragma unroll
-      for (int bb = 0; bb < NB1; ++bb) {
+    for (int r = 0; r < 8; ++r) {
+      w1[P::al(r)] = v[r];
+      w2[P::al(r)] = v[r + 8];
+    }
+    wave_sync();
+    float2 u[NB1][R1];
 #pragma unroll
-        for (int r = 1; r < R1; ++r) u[bb][r] = cmul(u[bb][r], tw[bb][r]);
-        Bfly<8, -1>::run(u[bb]);
-      }
-      // outputs Y(ky), ky = l + 8 bb + 16 r
-      if (SINGLE && c != 0) {
-        // Y(ky) at ky = l + 8 bb + 16 r, column kz = c (weight 2)
+    for (int r = 0; r < R1; ++r) {
+      u[0][r] = r1[P::al(8 * r)];  // position l + 16 r
+      u[1][r] = r2[P::al(8 * r)];  // position l + 8 + 16 r
+    }
+#pragma unroll
+    for (int bb = 0; bb < NB1; ++bb) {
+#pragma unroll
+      for (int r = 1; r < R1; ++r) u[bb][r] = cmul(u[bb][r], twid(bb, r));
+      Bfly<8, -1>::run(u[bb]);
+    }
+    // outputs Y(ky), ky = l + 8 bb + 16 r
+    if (c != 0) {
+      if constexpr (SINGLE) {
+        // column kz = c, weight 2
         const int m0 = l * ty + c * tz;
         const float2* ap = AXp + l * H + c;
 #pragma unroll
-        for (int bb = 0; bb < NB1; ++bb)
+        for (int bb = 0; bb < NB1; ++bb) {
+          // one half's loads at a time: all of them at once would take the
+          // registers the transform still holds
+          __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int r = 0; r < R1; ++r) {
             const int ky = l + 8 * bb + 16 * r;
@@ -1104,79 +1085,68 @@ __device__ __forceinline__ void plane_splat_body(const SplatParams& p, float2* _
             const float2 d = cmul(ap[plane_sz * N + (8 * bb + 16 * r) * H], ph);
             acc.add(u[bb][r], a, d, omega_of<N>(ky));
           }
+        }
         acc.fold(pass, 2.f, omega_of<N>(c), s1);
-      } else if (c != 0) {
+      } else {
         const int lo = (l * H + c) * (int)sizeof(float2);
         const auto rs0 = buffer_rsrc(dst0, (unsigned)(plane_sz * sizeof(float2)));
 #pragma unroll
         for (int bb = 0; bb < NB1; ++bb)
 #pragma unroll
           for (int r = 0; r < R1; ++r) buffer_store2(u[bb][r], rs0, lo, (8 * bb + 16 * r) * H * (int)sizeof(float2));
-        if (dst1) {
-          const auto rs1 = buffer_rsrc(dst1, (unsigned)(plane_sz * sizeof(float2)));
+      }
+    } else {
+      // C = P + i Q with P, Q the spectra of the real columns kz = 0 and N/2:
+      // P(k) = (C(k) + conj C(N-k))/2, Q(k) = -i (C(k) - conj C(N-k))/2
+      wave_sync();
 #pragma unroll
-          for (int bb = 0; bb < NB1; ++bb)
+      for (int r = 0; r < R1; ++r) {
+        r1[P::al(8 * r)] = u[0][r];
+        r2[P::al(8 * r)] = u[1][r];
+      }
+      wave_sync();
 #pragma unroll
-            for (int r = 0; r < R1; ++r)
-              buffer_store2(make_float2(u[bb][r].x * s1, u[bb][r].y * s1), rs1, lo,
-                            (8 * bb + 16 * r) * H * (int)sizeof(float2));
-        }
-      } else {
-        // C = P + i Q with P, Q the spectra of the real columns kz = 0 and N/2:
-        // P(k) = (C(k) + conj C(N-k))/2, Q(k) = -i (C(k) - conj C(N-k))/2
-        wave_sync();
+      for (int bb = 0; bb < NB1; ++bb)
 #pragma unroll
         for (int r = 0; r < R1; ++r) {
-          r1[P::al(8 * r)] = u[0][r];
-          r2[P::al(8 * r)] = u[1][r];
-        }
-        wave_sync();
-#pragma unroll
-        for (int bb = 0; bb < NB1; ++bb)
-#pragma unroll
-          for (int r = 0; r < R1; ++r) {
-            const int k = l + 8 * bb + 16 * r, m = (N - k) & (N - 1);
-            const float2 a = u[bb][r];
-            const float2 z = W[P::al((m & 7) | ((m >> 4) << 3)) + (((m >> 3) & 1) ? b2 : b1)];
-            const float2 pk = make_float2(0.5f * (a.x + z.x), 0.5f * (a.y - z.y));
-            const float2 qk = make_float2(0.5f * (a.y + z.y), -0.5f * (a.x - z.x));
-            if constexpr (SINGLE) {
-              // (k, kz = 0) and (k, kz = N/2), weight 1, omega_z = 0
-              const float2* ap = AXp + (size_t)k * H;
-              const float2 ph0 = tabc[(k * ty) & (N - 1)], ph1 = tabc[(k * ty + T * tz) & (N - 1)];
-              acc.add(pk, cmul(ap[0], ph0), cmul(ap[plane_sz * N], ph0), omega_of<N>(k));
-              acc.add(qk, cmul(ap[T], ph1), cmul(ap[plane_sz * N + T], ph1), omega_of<N>(k));
-            } else {
-              dst0[(size_t)k * H] = pk;
-              dst0[(size_t)k * H + T] = qk;
-              if (dst1) {
-                dst1[(size_t)k * H] = make_float2(pk.x * s1, pk.y * s1);
-                dst1[(size_t)k * H + T] = make_float2(qk.x * s1, qk.y * s1);
-              }
-            }
+          const int k = l + 8 * bb + 16 * r, m = (N - k) & (N - 1);
+          const float2 a = u[bb][r];
+          const float2 z = W[P::al((m & 7) | ((m >> 4) << 3)) + (((m >> 3) & 1) ? b2 : b1)];
+          const float2 pk = make_float2(0.5f * (a.x + z.x), 0.5f * (a.y - z.y));
+          const float2 qk = make_float2(0.5f * (a.y + z.y), -0.5f * (a.x - z.x));
+          if constexpr (SINGLE) {
+            // (k, kz = 0) and (k, kz = N/2), weight 1, omega_z = 0
+            const float2* ap = AXp + (size_t)k * H;
+            const float2 ph0 = tabc[(k * ty) & (N - 1)], ph1 = tabc[(k * ty + T * tz) & (N - 1)];
+            acc.add(pk, cmul(ap[0], ph0), cmul(ap[plane_sz * N], ph0), omega_of<N>(k));
+            acc.add(qk, cmul(ap[T], ph1), cmul(ap[plane_sz * N + T], ph1), omega_of<N>(k));
+          } else {
+            dst0[(size_t)k * H] = pk;
+            dst0[(size_t)k * H + T] = qk;
           }
-        if constexpr (SINGLE) acc.fold(pass, 1.f, 0.f, s1);
-      }
+        }
+      if constexpr (SINGLE) acc.fold(pass, 1.f, 0.f, s1);
     }
   }
-  if constexpr (SINGLE) block_sum7<P::THREADS>(acc, red, part + ((size_t)b * N + x) * 7);
+  if constexpr (SINGLE) block_sum7<P::THREADS>(acc, red, dstp);
 }
 
 // grid = (N planes, batch); block = 512. Pass 1 from binned samples: the
-// plane spectra of NCH = 1 or 4 channels (plane_splat_body).
-template <int N, int NCH>
-__global__ void __launch_bounds__(PlaneP<N>::THREADS, NCH == 4 ? 2 : 4) k_plane_splat_fwd(SplatParams p, float2* __restrict__ out,
+// plane spectra of u (plane_splat_body).
+template <int N>
+__global__ void __launch_bounds__(PlaneP<N>::THREADS, 4) k_plane_splat_fwd(SplatParams p, float2* __restrict__ out,
                                                                           const float2* __restrict__ table) {
-  plane_splat_body<N, NCH, false>(p, out, nullptr, nullptr, table);
+  plane_splat_body<N, false>(p, out, nullptr, nullptr, table);
 }
 
-// grid = (N planes, queries); block = 512. Re-correlated single-translation
-// sums of query b over plane x: part[(b*N + x)*7 + o] (plane_splat_body).
+// grid = (N planes, queries, 3 channel passes); block = 512. Re-correlated
+// single-translation sums of query b over plane x and channel pass z:
+// part[((b*3 + z)*N + x)*7 + o] (plane_splat_body).
 template <int N>
-__global__ void __launch_bounds__(PlaneP<N>::THREADS, 2) k_plane_single(SplatParams p, const QueryItem* __restrict__ items,
+__global__ void __launch_bounds__(PlaneP<N>::THREADS, 4) k_plane_single(SplatParams p, const QueryItem* __restrict__ items,
                                                                      double* __restrict__ part,
                                                                      const float2* __restrict__ table) {
-  plane_splat_body<N, 4, true>(p, nullptr, items, part, table);
+  plane_splat_body<N, true>(p, nullptr, items, part, table);
 }
 
 // Single-translation sums of one x-plane for grid edges without the
@@ -1206,6 +1176,8 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_sin
   const size_t plane_sz = (size_t)N * H;
   const float2* AXp = it.AX + (size_t)((x + it.t[0]) % N) * plane_sz;
   const int ty = it.t[1], tz = it.t[2];
+  Twiddles<N> tw;  // first: their loads overlap the splat
+  load_twiddles<N>(tw, table, (tid & 63) % P::L);
   for (int i = tid; i < N; i += P::THREADS) tabc[i] = make_float2(table[i].x, -table[i].y);
   // splat: as the binned branch of k_plane_fwd
   const int4 rg = p.cand[(size_t)b * N + x];
@@ -1231,19 +1203,51 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_sin
     const bool more = wave_cand(rb, rg, c0 + lane * P::WAVES + wave, q);
     hit = more && wave_hit<N>(p, q, x, h);
   }
-  __syncthreads();
-  {
-    Twiddles<N> tw;
-    load_twiddles<N>(tw, table, (tid & 63) % P::L);
-    plane_forward_out<N, false>(W, tw, nullptr, nullptr, 0.f);  // spectrum stays in W
+  // this thread's column and first rows of AX, DX: loaded before the
+  // transforms so that their latency overlaps them (issued before the
+  // barrier that ends the splat)
+  constexpr int NJ = (N + GR - 1) / GR, CH = 8;  // rows per thread, rows per load batch
+  const bool active = tid < GR * H;
+  const int kz = tid % H, ky0 = tid / H;
+  float2 ra[CH], rd[CH];
+#pragma unroll
+  for (int j = 0; j < CH; ++j) {
+    const int ky = ky0 + j * GR;
+    const bool in = active && j < NJ && ky < N;
+    ra[j] = in ? AXp[ky * H + kz] : make_float2(0.f, 0.f);
+    rd[j] = in ? AXp[plane_sz * N + ky * H + kz] : make_float2(0.f, 0.f);
   }
+  __syncthreads();  // every wave's splat atomics land before any transform reads the plane
+  plane_forward_out<N, false>(W, tw, nullptr, nullptr, 0.f);  // spectrum stays in W
   SingleAcc acc;
-  if (tid < GR * H) {
-    const int kz = tid % H;
-    for (int ky = tid / H; ky < N; ky += GR) {
-      const int e = ky * H + kz;
-      const float2 ph = tabc[(ky * ty + kz * tz) % N];
-      acc.add(W[P::yc(ky, kz)], cmul(AXp[e], ph), cmul(AXp[plane_sz * N + e], ph), omega_of<N>(ky));
+  if (active) {
+#pragma unroll 1
+    for (int j0 = 0; j0 < NJ; j0 += CH) {
+      float2 na[CH], nd[CH];
+#pragma unroll
+      for (int j = 0; j < CH; ++j) na[j] = nd[j] = make_float2(0.f, 0.f);
+      if (j0 + CH < NJ) {  // next batch in flight while this one is summed
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+          const int ky = ky0 + (j0 + CH + j) * GR;
+          const bool in = j0 + CH + j < NJ && ky < N;
+          na[j] = in ? AXp[ky * H + kz] : make_float2(0.f, 0.f);
+          nd[j] = in ? AXp[plane_sz * N + ky * H + kz] : make_float2(0.f, 0.f);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        const int ky = ky0 + (j0 + j) * GR;
+        if (j0 + j < NJ && ky < N) {
+          const float2 ph = tabc[(ky * ty + kz * tz) % N];
+          acc.add(W[P::yc(ky, kz)], cmul(ra[j], ph), cmul(rd[j], ph), omega_of<N>(ky));
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        ra[j] = na[j];
+        rd[j] = nd[j];
+      }
     }
     acc.fold(pass, (kz == 0 || kz == N / 2) ? 1.f : 2.f, omega_of<N>(kz), yhat(x, N));
   }

@@ -123,37 +123,29 @@ template <int N> struct Launch {
     // one workgroup per member: 1024 threads, as a batch has far fewer members than CUs
     hipLaunchKernelGGL(k_bin_samples<N>, dim3(batch), dim3(1024), 0, s, sp, rec, off, rmax, cand);
   }
-  // pass 1 from real grids (nch = 1) or from binned samples (nch = 1 or 4)
-  static void plane_fwd(const SplatParams& sp, const float* grid, int nch, float2* out, int batch, const float2* tw,
+  // pass 1 from real grids, or from binned samples when grid is null
+  static void plane_fwd(const SplatParams& sp, const float* grid, float2* out, int batch, const float2* tw,
                         hipStream_t s) {
     if (grid)
-      hipLaunchKernelGGL((k_plane_fwd<N, true, 1>), dim3(N, batch), dim3(P::THREADS), 0, s, sp, grid, out, tw);
+      hipLaunchKernelGGL((k_plane_fwd<N, true>), dim3(N, batch), dim3(P::THREADS), 0, s, sp, grid, out, tw);
     else
-      plane_splat(sp, nch, out, batch, tw, s);
+      plane_splat(sp, out, batch, tw, s);
   }
-  // pass 1 from binned samples (sp.rec, sp.cand): nch = 1 or 4
-  static void plane_splat(const SplatParams& sp, int nch, float2* out, int batch, const float2* tw, hipStream_t s) {
-    if constexpr (PlaneP<N>::ok) {
-      constexpr int TH = PlaneP<N>::THREADS;
-      if (nch == 4)
-        hipLaunchKernelGGL((k_plane_splat_fwd<N, 4>), dim3(N, batch), dim3(TH), 0, s, sp, out, tw);
-      else
-        hipLaunchKernelGGL((k_plane_splat_fwd<N, 1>), dim3(N, batch), dim3(TH), 0, s, sp, out, tw);
-    } else {
-      if (nch == 4)
-        hipLaunchKernelGGL((k_plane_fwd<N, false, 4>), dim3(N, batch, 3), dim3(P::THREADS), 0, s, sp, nullptr, out, tw);
-      else
-        hipLaunchKernelGGL((k_plane_fwd<N, false, 1>), dim3(N, batch), dim3(P::THREADS), 0, s, sp, nullptr, out, tw);
-    }
+  // pass 1 from binned samples (sp.rec, sp.cand): the spectra of u
+  static void plane_splat(const SplatParams& sp, float2* out, int batch, const float2* tw, hipStream_t s) {
+    if constexpr (PlaneP<N>::ok)
+      hipLaunchKernelGGL((k_plane_splat_fwd<N>), dim3(N, batch), dim3(PlaneP<N>::THREADS), 0, s, sp, out, tw);
+    else
+      hipLaunchKernelGGL((k_plane_fwd<N, false>), dim3(N, batch), dim3(P::THREADS), 0, s, sp, nullptr, out, tw);
   }
   // Re-correlated single-translation sums of `batch` queries (binned samples
   // sp.rec, sp.cand; items with the pair's AX): part = batch x
   // single_blocks() x 7 partial sums.
-  static int single_blocks() { return PlaneP<N>::ok ? N : 3 * N; }
+  static int single_blocks() { return 3 * N; }
   static void plane_single(const SplatParams& sp, const QueryItem* items, double* part, int batch, const float2* tw,
                            hipStream_t s) {
     if constexpr (PlaneP<N>::ok)
-      hipLaunchKernelGGL(k_plane_single<N>, dim3(N, batch), dim3(PlaneP<N>::THREADS), 0, s, sp, items, part, tw);
+      hipLaunchKernelGGL(k_plane_single<N>, dim3(N, batch, 3), dim3(PlaneP<N>::THREADS), 0, s, sp, items, part, tw);
     else
       hipLaunchKernelGGL(k_plane_single_gen<N>, dim3(N, batch, 3), dim3(P::THREADS), 0, s, sp, items, part, tw);
   }

@@ -246,7 +246,7 @@ ga_status ga_fft3d(const ga_plan* plan, int32_t dir, const void* d_in, void* d_o
     dispatch(n, [&]<int N>() {
       {
         ProfScope ps(plan, GA_K_PLANE_FWD, stream);
-        Launch<N>::plane_fwd(sp, static_cast<const float*>(d_in), 1, out, batch, plan->d_tw, stream);
+        Launch<N>::plane_fwd(sp, static_cast<const float*>(d_in), out, batch, plan->d_tw, stream);
       }
       ProfScope ps(plan, GA_K_STRIP, stream);
       Launch<N>::strip_fft(-1, out, out, batch, plan->d_tw, stream);
@@ -443,7 +443,7 @@ ga_status ga_energy_fields(const ga_plan* plan, const float* d_Ahat, const float
       spc.cand = cc;
       {
         ProfScope ps(plan, GA_K_PLANE_FWD, sc);
-        Launch<N>::plane_fwd(spc, nullptr, 1, tc, nb, plan->d_tw, sc);
+        Launch<N>::plane_fwd(spc, nullptr, tc, nb, plan->d_tw, sc);
       }
       {
         ProfScope ps(plan, GA_K_STRIP, sc);
@@ -641,7 +641,7 @@ ga_status ga_pose_spectral(const ga_plan* plan, const float* d_AX2, const float*
     int* off = reinterpret_cast<int*>(bins + bl.off);
     float* rmax = reinterpret_cast<float*>(bins + bl.rmax);
     int4* cand = reinterpret_cast<int4*>(bins + bl.cand);
-    hipLaunchKernelGGL(k_bin_items<N>, dim3(n_poses), dim3(256), 0, stream, (const QueryItem*)items, sp,
+    hipLaunchKernelGGL(k_bin_items<N>, dim3(n_poses), dim3(1024), 0, stream, (const QueryItem*)items, sp,
                        (long long)n_pts, rec, off, rmax, cand);
     SplatParams sq = sp;
     sq.rec = rec;
