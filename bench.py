@@ -397,7 +397,8 @@ def batch_leg(G, synth, np, torch, dev, batch, chunks, steps=10):
 def next_rows_leg(G, synth, np, torch, dev, reps=20):
     """The widened rows at 128^3 (parts of the 128^3 batched workload): low-pass
     filtering of the 4 moving-part spectra to the 16^3 box (coarse grid and
-    zero-padded), spectral rotation of the 4 spectra by 16 rotations, the
+    zero-padded), spectral rotation of the 4 spectra by 16 rotations (from the
+    packed resident layout, once packed per part, and from planar spectra), the
     complex-affinity score (Re and Im) of 16 moving parts, and 100k trilinear
     queries of 4 orientation field tables. Average microseconds per call
     (HIP events on the calling stream over `reps` calls) and algorithmic bytes
@@ -416,6 +417,7 @@ def next_rows_leg(G, synth, np, torch, dev, reps=20):
     coarse_out = torch.empty((4, L, L, L // 2 + 1), dtype=torch.complex64, device=dev)
     pad_out = torch.empty_like(Bhat4)
     rot_out = torch.empty((nb, 4, n, n, n // 2 + 1), dtype=torch.complex64, device=dev)
+    packed = G.ga_spectral_pack4(plan, Bhat4)  # resident once per part
     A2 = torch.stack([Ahat, Bhat4[1]]).contiguous()
     B2 = Bhat4[None, :2].expand(nb, 2, n, n, n // 2 + 1).contiguous()
     score_out = torch.empty((nb, 2, n, n, n), dtype=torch.float32, device=dev)
@@ -431,8 +433,11 @@ def next_rows_leg(G, synth, np, torch, dev, reps=20):
                                   4 * 8 * (kept + L * L * (L // 2 + 1))),
         "f1_lowpass_zeropad_4ch": (lambda: G.ga_lowpass(plan, Bhat4, L, G.GA_LOWPASS_ZEROPAD, out=pad_out),
                                    4 * 8 * (kept + H)),
-        "f2_spectral_rotate_4ch_x16": (lambda: G.ga_spectral_rotate(plan, Bhat4, R, out=rot_out),
-                                       4 * 8 * H + nb * 4 * 8 * H),
+        "f2_spectral_rotate_packed_4ch_x16": (lambda: G.ga_spectral_rotate_packed(plan, packed, R, out=rot_out),
+                                              4 * 8 * H + nb * 4 * 8 * H),
+        "f2_spectral_rotate_planar_4ch_x16": (lambda: G.ga_spectral_rotate(plan, Bhat4, R, out=rot_out),
+                                              4 * 8 * H + nb * 4 * 8 * H),
+        "f2_spectral_pack_4ch": (lambda: G.ga_spectral_pack4(plan, Bhat4, out=packed), 2 * 4 * 8 * H),
         "f3_score_re_im_x16": (lambda: G.ga_score(plan, A2, B2, out=score_out, work=score_work),
                                2 * 8 * H + nb * (2 * 8 * H + 2 * 8 * H) + nb * 2 * (8 * H + 4 * n ** 3)),
         "f4_table_query_100k": (lambda: G.ga_field_table_query(plan, tables, orient, tq, out=q_out),
@@ -598,9 +603,9 @@ def main():
                     "kernel_ms": {k: round(v, 4) for k, v in kern_timed.items()}},
         "kernel_ms": {k: round(v, 4) for k, v in kern.items()},
         "autotune": {"strip_groups": tuned[0], "members_per_workgroup": tuned[1],
-                     "xcd_aware_grid": tuned[2] == 1,
-                     "candidates_us": {f"{'xcd' if x == 1 else 'plain'}/{g}x{k}": v
-                                       for (g, k, x), v in tune_us.items()}},
+                     "xcd_aware_grid": tuned[2] == 1, "radix_schedule": tuned[3],
+                     "candidates_us": {f"{'xcd' if x == 1 else 'plain'}/r{r}/{g}x{k}": v
+                                       for (g, k, x, r), v in tune_us.items()}},
         "roofline": {"bound": roofline_bound(dom, kern[dom], counter_traffic(dom)), "kernel": dom,
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": counter_traffic(dom),

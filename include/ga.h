@@ -349,6 +349,23 @@ ga_status ga_spectral_rotate(const ga_plan* plan, const float* d_in, int32_t cha
                              float* d_out, hipStream_t stream);
 
 /*
+ * Packed resident spectra for repeated spectral rotation (Sec. 3.2, step 1:
+ * the moving part's spectra stay resident and are rotated every frame).
+ * ga_spectral_pack4 writes the 4 half spectra d_in4 (u, yhat_x u, yhat_y u,
+ * yhat_z u, as ga_spectral_rotate with channels = 4 takes them) as one
+ * 32-byte record per frequency: d_packed[8 e .. 8 e + 7] = Re, Im of the 4
+ * channels at element e of the half-spectrum layout (4 n^2 (n/2+1) float2,
+ * the same size as d_in4; owned by the caller). ga_spectral_rotate_packed
+ * then gives the outputs of ga_spectral_rotate with channels = 4 (batch x 4
+ * half spectra in d_out, the same definition and arithmetic) reading one
+ * record per interpolation corner for all 4 channels. Errors: GA_EINVAL
+ * (overlapping or misaligned buffers, batch < 1).
+ */
+ga_status ga_spectral_pack4(const ga_plan* plan, const float* d_in4, float* d_packed, hipStream_t stream);
+ga_status ga_spectral_rotate_packed(const ga_plan* plan, const float* d_packed, const float* d_R, int32_t batch,
+                                    float* d_out, hipStream_t stream);
+
+/*
  * Low-pass filtering (Sec. 3.3): of the n-grid half spectra only the modes
  * of the symmetric low-frequency box |kappa(k_a)| <= L/2 - 1 (kappa the signed
  * frequency index, every axis) are kept, times `scale`; L even, 4 <= L <= n.
@@ -371,27 +388,78 @@ ga_status ga_lowpass(const ga_plan* plan, int32_t L, uint32_t mode, const float*
 
 /*
  * Autotuning of the fused correlation pass of ga_energy_fields (the x
- * transform, product with the shared stationary spectrum and inverse x
- * transform). Candidates: the strip width (groups = 4 or 8 groups of
- * transforms per wavefront, i.e. 4 or 8 wavefronts per workgroup), the
- * number of batch members k a workgroup takes in turn while keeping its
- * stationary-spectrum elements in registers (1, 2, 4, 8), and the grid
- * mapping xcd: 1 = XCD-aware (the member groups of one strip run back to
- * back on one XCD, whose L2 then serves the shared spectrum), 2 = plain.
- * Each candidate runs once plus three timed times on d_work (zeroed first;
- * at least batch * n^2 (n/2+1) * 8 bytes, the first part of a GA_OP_ENERGY
- * workspace) against d_Ahat; the fastest is kept in the plan and used by
- * later ga_energy_fields calls. The call synchronises `stream`. h_us (may be
- * null when n_us = 0) receives up to n_us per-launch times in microseconds,
- * in the order xcd (1, 2) x groups (4, 8) x k (1, 2, 4, 8), k fastest.
- * ga_plan_set_tuning restores a stored choice (0 = default: 4 groups, 4
- * members, plain grid); ga_plan_get_tuning reports the one in use. Not for
- * graph capture.
+ * transform, product with the stationary spectrum and inverse x transform).
+ * Knobs: the strip width (groups = 4 or 8 groups of transforms per
+ * wavefront, i.e. 4 or 8 wavefronts per workgroup), the number of batch
+ * members k a workgroup takes in turn while keeping its stationary-spectrum
+ * elements in registers (1, 2, 4, 8), and the grid mapping xcd: 1 =
+ * XCD-aware (the member groups of one strip run back to back on one XCD,
+ * whose L2 then serves the shared spectrum), 2 = plain; and the radix
+ * schedule of the x transforms: 0 = the edge's default order of radices, 1 =
+ * its alternative (n = 32: 4 x 8 instead of 8 x 4; 64: 4 x 16 instead of
+ * 8 x 8; 96: 3 x 8 x 4 instead of 3 x 4 x 8; 128: 16 x 8 instead of 8 x 16;
+ * 192: 8 x 8 x 3 instead of 3 x 8 x 8; other edges have none).
+ * ga_plan_autotune times the plain-grid candidates, radix (0, 1) x groups
+ * (4, 8) x k (1, 2, 4, 8) (the XCD-aware grid measured slower at every
+ * setting on the 128^3 x 64 workload; ga_plan_tune can include it), each once
+ * plus three timed launches on d_work (zeroed first; at least
+ * batch * n^2 (n/2+1) * 8 bytes, the first part of a GA_OP_ENERGY workspace)
+ * against d_Ahat; the fastest is kept in the plan and used by later
+ * ga_energy_fields calls. The call synchronises `stream`. h_us (may be null
+ * when n_us = 0) receives up to n_us = 16 per-launch times in microseconds
+ * in that order, k fastest (0 for the radix-1 slots of an edge without an
+ * alternative). ga_plan_set_tuning sets groups, k and xcd (0 = default: 4
+ * groups, 4 members, plain grid) and ga_plan_set_radix the schedule
+ * (GA_EINVAL for 1 on an edge without an alternative; ga_plan_has_alt_radix
+ * says which); ga_plan_get_tuning and ga_plan_get_radix report the ones in
+ * use. Not for graph capture.
  */
 ga_status ga_plan_autotune(ga_plan* plan, const float* d_Ahat, int32_t batch, void* d_work, size_t work_bytes,
                            hipStream_t stream, float* h_us, int32_t n_us);
 ga_status ga_plan_set_tuning(ga_plan* plan, int32_t groups, int32_t k, int32_t xcd);
 ga_status ga_plan_get_tuning(const ga_plan* plan, int32_t* groups, int32_t* k, int32_t* xcd);
+ga_status ga_plan_set_radix(ga_plan* plan, int32_t radix);
+int32_t ga_plan_get_radix(const ga_plan* plan);
+int32_t ga_plan_has_alt_radix(const ga_plan* plan);
+
+/*
+ * Tuning of a whole ga_energy_fields call for one (architecture, n, batch)
+ * with a persisted cache (the real-time sequence of Sec. 3.2 repeats the
+ * same call shape every frame, so a choice made once is reused). The key is
+ * "<arch>/<n>/<batch>/1" (arch: the device's architecture name up to its
+ * first ':', e.g. gfx950; 1 channel: the energy field). With cache_path set
+ * and the key present in that file, the stored choice is applied without
+ * timing (result->from_cache = 1). Otherwise the fused x pass's candidates
+ * (radix, groups, k) are timed as by ga_plan_autotune (with flags &
+ * GA_TUNE_XCD also on the XCD-aware grid), then, with flags & GA_TUNE_OVERLAP, whole calls on the
+ * caller's inputs in 1, 2 and 4 parts over two streams (ga_plan_set_overlap;
+ * two rounds of 2 warm-up and 5 timed calls each, the best time kept); the
+ * fastest is applied to the plan, reported in *result (us = time per call)
+ * and, with cache_path set, written to the file (other keys kept; written to
+ * a temporary file and renamed over it). The arguments d_Ahat .. stream are
+ * those of ga_energy_fields (d_E is overwritten). The file is a JSON object
+ * with one line per key, {"groups": g, "k": k, "xcd": x, "radix": r,
+ * "overlap": p, "us": t}. Errors: GA_EINVAL (arguments; a cache file that cannot be read,
+ * is not in that layout, or cannot be written: it is left as it was),
+ * GA_ENOMEM (workspace), GA_EUNSUPPORTED (separate-axis plans: their knobs
+ * are not tuned), GA_EDEVICE. The call synchronises `stream`; not for graph
+ * capture.
+ */
+#define GA_TUNE_XCD 1u
+#define GA_TUNE_OVERLAP 2u
+typedef struct ga_tuning {
+  int32_t groups;     /* wavefronts of transforms per workgroup of the fused x pass */
+  int32_t k;          /* batch members per workgroup */
+  int32_t xcd;        /* 1 XCD-aware grid, 2 plain */
+  int32_t radix;      /* 0 default radix schedule, 1 the alternative */
+  int32_t overlap;    /* parts of the batch over two streams */
+  float us;           /* time per ga_energy_fields call of this choice, microseconds */
+  int32_t from_cache; /* 1 when read from the cache file */
+} ga_tuning;
+ga_status ga_plan_tune(ga_plan* plan, const float* d_Ahat, const float* d_xyzr, const float* d_w, int64_t n_pts,
+                       const float* d_R, const float* h_c, float sigma, int32_t batch, float* d_E, void* d_work,
+                       size_t work_bytes, uint32_t flags, const char* cache_path, hipStream_t stream,
+                       ga_tuning* result);
 
 /*
  * Overlapped execution of ga_energy_fields on the plane path (grid edges up

@@ -30,7 +30,9 @@ from .ga import (  # noqa: F401
     ga_force_torque,
     ga_force_torque_noalloc,
     ga_lowpass,
+    ga_spectral_pack4,
     ga_spectral_rotate,
+    ga_spectral_rotate_packed,
     ga_pose_local,
     ga_pose_prepare,
     ga_pose_spectral,

@@ -143,9 +143,13 @@ template <int DIR> struct Bfly<16, DIR> {
 
 // ---- radix schedules --------------------------------------------------------
 // E elements per lane; every radix divides E; the product of radices is N.
+// Shape<N> is the default schedule of edge N; ShapeAlt<N> another order of
+// radices (same or different E) that the autotuner can pick for the strip
+// pass; where none is defined it is the default schedule (kDistinct false).
 template <int N> struct Shape;
 #define GA_SHAPE(NN, EE, NSTAGES, ...)                       \
   template <> struct Shape<NN> {                             \
+    static constexpr bool kDistinct = true;                  \
     static constexpr int E = EE;                             \
     static constexpr int NST = NSTAGES;                      \
     static constexpr int R[NSTAGES] = {__VA_ARGS__};         \
@@ -162,56 +166,73 @@ GA_SHAPE(256, 8, 3, 8, 8, 4)
 GA_SHAPE(384, 24, 4, 3, 8, 8, 2)
 GA_SHAPE(512, 8, 3, 8, 8, 8)
 #undef GA_SHAPE
+template <int N> struct ShapeAlt : Shape<N> {
+  static constexpr bool kDistinct = false;
+};
+#define GA_SHAPE_ALT(NN, EE, NSTAGES, ...)                   \
+  template <> struct ShapeAlt<NN> {                          \
+    static constexpr bool kDistinct = true;                  \
+    static constexpr int E = EE;                             \
+    static constexpr int NST = NSTAGES;                      \
+    static constexpr int R[NSTAGES] = {__VA_ARGS__};         \
+  };
+GA_SHAPE_ALT(32, 8, 2, 4, 8)
+GA_SHAPE_ALT(64, 16, 2, 4, 16)
+GA_SHAPE_ALT(96, 24, 3, 3, 8, 4)
+GA_SHAPE_ALT(128, 16, 2, 16, 8)
+GA_SHAPE_ALT(192, 24, 3, 8, 8, 3)
+#undef GA_SHAPE_ALT
 
-template <int N> constexpr int lanes_per_fft() { return N / Shape<N>::E; }
-template <int N> constexpr int ffts_per_wave() { return 64 / lanes_per_fft<N>(); }
-template <int N> constexpr int ns_before(int s) {
+template <int N, class SH = Shape<N>> constexpr int lanes_per_fft() { return N / SH::E; }
+template <int N, class SH = Shape<N>> constexpr int ffts_per_wave() { return 64 / lanes_per_fft<N, SH>(); }
+template <int N, class SH> constexpr int ns_before(int s) {
   int p = 1;
-  for (int i = 0; i < s; ++i) p *= Shape<N>::R[i];
+  for (int i = 0; i < s; ++i) p *= SH::R[i];
   return p;
 }
-template <int N> constexpr int tw_off(int s) {
+template <int N, class SH> constexpr int tw_off(int s) {
   int o = 0;
-  for (int i = 1; i < s; ++i) o += (Shape<N>::E / Shape<N>::R[i]) * (Shape<N>::R[i] - 1);
+  for (int i = 1; i < s; ++i) o += (SH::E / SH::R[i]) * (SH::R[i] - 1);
   return o;
 }
-template <int N> constexpr int tw_count() { return tw_off<N>(Shape<N>::NST); }
+template <int N, class SH> constexpr int tw_count() { return tw_off<N, SH>(SH::NST); }
 
-template <int N> struct Twiddles {
-  float2 v[tw_count<N>()];
+template <int N, class SH = Shape<N>> struct Twiddles {
+  float2 v[tw_count<N, SH>()];
 };
 
 // Per-lane twiddles: stage s > 0, butterfly b, element r uses
 // exp(-2 pi i r k / (NS R)) with k = j mod NS, j = lane + L b.
-template <int N, int S>
-__device__ __forceinline__ void load_twiddles_stage(Twiddles<N>& tw, const float2* __restrict__ table, int lane) {
-  if constexpr (S < Shape<N>::NST) {
+template <int N, int S, class SH>
+__device__ __forceinline__ void load_twiddles_stage(Twiddles<N, SH>& tw, const float2* __restrict__ table, int lane) {
+  if constexpr (S < SH::NST) {
     if constexpr (S > 0) {
-      constexpr int E = Shape<N>::E, L = N / E, R = Shape<N>::R[S], NS = ns_before<N>(S), NB = E / R;
+      constexpr int E = SH::E, L = N / E, R = SH::R[S], NS = ns_before<N, SH>(S), NB = E / R;
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int j = lane + L * b;
         const int k = j % NS;
 #pragma unroll
-        for (int r = 1; r < R; ++r) tw.v[tw_off<N>(S) + b * (R - 1) + r - 1] = table[r * k * (N / (NS * R))];
+        for (int r = 1; r < R; ++r) tw.v[tw_off<N, SH>(S) + b * (R - 1) + r - 1] = table[r * k * (N / (NS * R))];
       }
     }
-    load_twiddles_stage<N, S + 1>(tw, table, lane);
+    load_twiddles_stage<N, S + 1, SH>(tw, table, lane);
   }
 }
-template <int N>
-__device__ __forceinline__ void load_twiddles(Twiddles<N>& tw, const float2* __restrict__ table, int lane) {
-  load_twiddles_stage<N, 0>(tw, table, lane);
+template <int N, class SH>
+__device__ __forceinline__ void load_twiddles(Twiddles<N, SH>& tw, const float2* __restrict__ table, int lane) {
+  load_twiddles_stage<N, 0, SH>(tw, table, lane);
 }
 
 // One Stockham stage, in place in LDS: element `pos` of the transform lives
 // at at(pos) (a float2 pointer; any layout, e.g. strided or swizzled against
 // bank conflicts). Stage 0 takes its inputs from ld(pos) and the last stage
-// hands its outputs to st(pos, v); positions are natural indices.
-template <int N, int S, int DIR, class At, class Ld, class St>
-__device__ __forceinline__ void fft_stage(int lane, const Twiddles<N>& tw, At& at, Ld& ld, St& st) {
-  constexpr int E = Shape<N>::E, L = N / E, R = Shape<N>::R[S], NS = ns_before<N>(S), NB = E / R;
-  constexpr bool first = (S == 0), last = (S == Shape<N>::NST - 1);
+// hands its outputs to st(pos, v); positions are natural indices. The
+// schedule SH comes with the twiddles.
+template <int N, int S, int DIR, class SH, class At, class Ld, class St>
+__device__ __forceinline__ void fft_stage(int lane, const Twiddles<N, SH>& tw, At& at, Ld& ld, St& st) {
+  constexpr int E = SH::E, L = N / E, R = SH::R[S], NS = ns_before<N, SH>(S), NB = E / R;
+  constexpr bool first = (S == 0), last = (S == SH::NST - 1);
   float2 v[E];
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
@@ -228,7 +249,7 @@ __device__ __forceinline__ void fft_stage(int lane, const Twiddles<N>& tw, At& a
   for (int b = 0; b < NB; ++b) {
     if constexpr (S > 0) {
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[b * R + r] = twmul<DIR>(v[b * R + r], tw.v[tw_off<N>(S) + b * (R - 1) + r - 1]);
+      for (int r = 1; r < R; ++r) v[b * R + r] = twmul<DIR>(v[b * R + r], tw.v[tw_off<N, SH>(S) + b * (R - 1) + r - 1]);
     }
     Bfly<R, DIR>::run(&v[b * R]);
   }
@@ -250,25 +271,25 @@ __device__ __forceinline__ void fft_stage(int lane, const Twiddles<N>& tw, At& a
 
 // Transform of length N on the L lanes [0, L) of this transform (`lane` is
 // the index within the transform), element pos at at(pos).
-template <int N, int DIR, class At, class Ld, class St>
-__device__ __forceinline__ void fft_at(int lane, const Twiddles<N>& tw, At at, Ld ld, St st) {
+template <int N, int DIR, class SH, class At, class Ld, class St>
+__device__ __forceinline__ void fft_at(int lane, const Twiddles<N, SH>& tw, At at, Ld ld, St st) {
   fft_stage<N, 0, DIR>(lane, tw, at, ld, st);
 }
-template <int N, int DIR, class At>
-__device__ __forceinline__ void fft_inplace_at(int lane, const Twiddles<N>& tw, At at) {
+template <int N, int DIR, class SH, class At>
+__device__ __forceinline__ void fft_inplace_at(int lane, const Twiddles<N, SH>& tw, At at) {
   auto ld = [&](int pos) { return *at(pos); };
   auto st = [&](int pos, float2 v) { *at(pos) = v; };
   fft_stage<N, 0, DIR>(lane, tw, at, ld, st);
 }
 
 // The same with data in buf[pos * es].
-template <int N, int DIR, class Ld, class St>
-__device__ __forceinline__ void fft_lanes(int lane, const Twiddles<N>& tw, float2* buf, int es, Ld ld, St st) {
+template <int N, int DIR, class SH, class Ld, class St>
+__device__ __forceinline__ void fft_lanes(int lane, const Twiddles<N, SH>& tw, float2* buf, int es, Ld ld, St st) {
   auto at = [=](int pos) { return buf + pos * es; };
   fft_stage<N, 0, DIR>(lane, tw, at, ld, st);
 }
-template <int N, int DIR>
-__device__ __forceinline__ void fft_inplace(int lane, const Twiddles<N>& tw, float2* buf, int es) {
+template <int N, int DIR, class SH>
+__device__ __forceinline__ void fft_inplace(int lane, const Twiddles<N, SH>& tw, float2* buf, int es) {
   auto at = [=](int pos) { return buf + pos * es; };
   fft_inplace_at<N, DIR>(lane, tw, at);
 }

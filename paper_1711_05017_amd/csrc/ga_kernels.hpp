@@ -1396,11 +1396,11 @@ GA_STRIP_SWZ(128, 2, 3, 2, 7)
 GA_STRIP_SWZ(192, 2, 0, 0, 0)
 #undef GA_STRIP_SWZ
 
-template <int N, int G> struct Strip {
+template <int N, int G, class SH = Shape<N>> struct Strip {
   static constexpr int H = N / 2 + 1;
   static constexpr int C = N * H;  // columns per x-plane
-  static constexpr int L = lanes_per_fft<N>();
-  static constexpr int TPW = ffts_per_wave<N>();
+  static constexpr int L = lanes_per_fft<N, SH>();
+  static constexpr int TPW = ffts_per_wave<N, SH>();
   static constexpr int WAVES = G / TPW;
   static constexpr int THREADS = 64 * WAVES;
   using Z = StripSwz<N>;
@@ -1411,9 +1411,9 @@ template <int N, int G> struct Strip {
   __device__ __forceinline__ static int idx(int x, int g) { return x * LD + (g ^ (((x >> Z::SH) & Z::MASK) * Z::MUL)); }
 };
 
-template <int N, int G>
+template <int N, int G, class SH = Shape<N>>
 __device__ __forceinline__ void strip_load(float2* S, const float2* src, int c0) {
-  using T = Strip<N, G>;
+  using T = Strip<N, G, SH>;
   batched_copy<N * G, T::THREADS, float2>(
       [&](int i) {
         const int x = i / G, c = c0 + i % G;
@@ -1421,17 +1421,17 @@ __device__ __forceinline__ void strip_load(float2* S, const float2* src, int c0)
       },
       [&](int i, float2 v) { S[T::idx(i / G, i % G)] = v; });
 }
-template <int N, int G>
+template <int N, int G, class SH = Shape<N>>
 __device__ __forceinline__ void strip_store(const float2* S, float2* dst, int c0) {
-  using T = Strip<N, G>;
+  using T = Strip<N, G, SH>;
   for (int i = threadIdx.x; i < N * G; i += T::THREADS) {
     const int x = i / G, g = i % G, c = c0 + g;
     if (c < T::C) dst[(size_t)x * T::C + c] = S[T::idx(x, g)];
   }
 }
-template <int N, int G, int DIR>
-__device__ __forceinline__ void strip_fft(float2* S, const Twiddles<N>& tw) {
-  using T = Strip<N, G>;
+template <int N, int G, int DIR, class SH>
+__device__ __forceinline__ void strip_fft(float2* S, const Twiddles<N, SH>& tw) {
+  using T = Strip<N, G, SH>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = wave * T::TPW + lane / T::L;
   fft_inplace_at<N, DIR>(lane % T::L, tw, [=](int x) { return S + T::idx(x, g); });
@@ -1470,11 +1470,12 @@ __global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_fft(const floa
 // workgroup id runs on XCD id % 8; the xcd_m member groups of one strip are
 // given consecutive ids on the same XCD (strip (id / 8 / xcd_m) * 8 + id % 8,
 // group (id / 8) % xcd_m), and the strip of A they share stays in that L2.
-template <int N, int G, bool FWD, int K = 1>
-__global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_corr(const float2* __restrict__ A, long long a_stride,
-                                                                     const float2* B, float2* out, int batch,
-                                                                     int xcd_m, const float2* __restrict__ table) {
-  using T = Strip<N, G>;
+template <int N, int G, bool FWD, int K = 1, class SH = Shape<N>>
+__global__ void __launch_bounds__((Strip<N, G, SH>::THREADS)) k_strip_corr(const float2* __restrict__ A,
+                                                                         long long a_stride, const float2* B,
+                                                                         float2* out, int batch, int xcd_m,
+                                                                         const float2* __restrict__ table) {
+  using T = Strip<N, G, SH>;
   constexpr int IT = (N * G + T::THREADS - 1) / T::THREADS;  // strip elements per thread
   constexpr int NSTRIPS = (T::C + G - 1) / G;
   int sx = blockIdx.x, my = blockIdx.y;
@@ -1485,7 +1486,7 @@ __global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_corr(const flo
     if (sx >= NSTRIPS) return;  // whole workgroup
   }
   __shared__ float2 S[T::SIZE];
-  Twiddles<N> tw;
+  Twiddles<N, SH> tw;
   load_twiddles<N>(tw, table, (threadIdx.x & 63) % T::L);
   const int c0 = sx * G;
   auto a_at = [&](const float2* Ab, int i) {
@@ -1507,7 +1508,7 @@ __global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_corr(const flo
     const size_t boff = (size_t)b * N * T::C;
     const float2* Ab = A + (size_t)b * (size_t)a_stride;
     if constexpr (FWD) {
-      strip_load<N, G>(S, B + boff, c0);
+      strip_load<N, G, SH>(S, B + boff, c0);
       __syncthreads();
       strip_fft<N, G, -1>(S, tw);
       __syncthreads();
@@ -1537,7 +1538,7 @@ __global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_corr(const flo
     __syncthreads();
     strip_fft<N, G, +1>(S, tw);
     __syncthreads();
-    strip_store<N, G>(S, out + boff, c0);
+    strip_store<N, G, SH>(S, out + boff, c0);
     __syncthreads();
   }
 }
@@ -2121,196 +2122,6 @@ __global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_pencil_fft(const flo
   for (int i = threadIdx.x; i < N * G; i += T::THREADS) {
     const int x = i / G, g = i % G, c = c0 + g;
     if (c < ncols) out[off + (size_t)x * stride + c] = S[T::idx(x, g)];
-  }
-}
-
-// Value of a real grid's spectrum at signed integer frequency (a, b, c) from
-// its half spectrum X [N][N][N/2+1]: X(-k) = conj X(k) supplies c < 0; zero
-// beyond the band (|component| > N/2).
-template <int N>
-__device__ __forceinline__ float2 spec_at(const float2* __restrict__ X, int a, int b, int c) {
-  constexpr int h = N / 2;
-  if (a > h || a < -h || b > h || b < -h || c > h || c < -h) return make_float2(0.f, 0.f);
-  const bool mirror = c < 0;
-  if (mirror) {
-    a = -a;
-    b = -b;
-    c = -c;
-  }
-  a += (a < 0) ? N : 0;
-  b += (b < 0) ? N : 0;
-  const float2 v = X[((size_t)a * N + (size_t)b) * (h + 1) + c];
-  return mirror ? make_float2(v.x, -v.y) : v;
-}
-
-// Trilinear interpolation of X at q (signed frequency coordinates, corner
-// indices i0 + {0, 1}, weights from the fractions a): the corner loop shared
-// by both rotation kernels. at(ix, iy, iz) returns the value at a corner.
-template <class At>
-__device__ __forceinline__ float2 trilinear_at(const int* i0, const float* a, At at) {
-  float2 acc = make_float2(0.f, 0.f);
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const int dx = c >> 2, dy = (c >> 1) & 1, dz = c & 1;
-    const float w = (dx ? a[0] : 1.f - a[0]) * (dy ? a[1] : 1.f - a[1]) * (dz ? a[2] : 1.f - a[2]);
-    if (w == 0.f) continue;
-    const float2 v = at(i0[0] + dx, i0[1] + dy, i0[2] + dz);
-    acc.x += w * v.x;
-    acc.y += w * v.y;
-  }
-  return acc;
-}
-
-// q = R^T kappa in float64, split into the lower corner and the fractions.
-__device__ __forceinline__ void rotate_frequency(const double* R, double k0, double k1, double k2, int* i0, float* a) {
-  const double q[3] = {R[0] * k0 + R[3] * k1 + R[6] * k2, R[1] * k0 + R[4] * k1 + R[7] * k2,
-                       R[2] * k0 + R[5] * k1 + R[8] * k2};
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const double f = floor(q[d]);
-    a[d] = (float)(q[d] - f);
-    i0[d] = (int)f;
-  }
-}
-
-// The moment channels rotate as a vector: o[1 + a] = sum_b R[a][b] acc[1 + b].
-__device__ __forceinline__ void store_rotated(float2* o, size_t spec, int nch, const double* R, const float2* acc) {
-  o[0] = acc[0];
-  if (nch == 4) {
-    for (int a = 0; a < 3; ++a) {
-      const float ra = (float)R[3 * a], rb = (float)R[3 * a + 1], rc = (float)R[3 * a + 2];
-      o[(size_t)(1 + a) * spec] = make_float2(ra * acc[1].x + rb * acc[2].x + rc * acc[3].x,
-                                              ra * acc[1].y + rb * acc[2].y + rc * acc[3].y);
-    }
-  }
-}
-
-// Spectral rotation (Sec. 3.2, step 1): out_b(k) = X(R_b^T kappa(k)) by
-// trilinear interpolation; with nch = 4 (u, yhat_x u, yhat_y u, yhat_z u) the
-// moment channels rotate as a vector, M_R(k) = R M(R^T kappa). in: nch half
-// spectra of the unrotated part about the grid origin; out: batch x nch half
-// spectra. The signed frequency of index N/2 is -N/2 on every axis.
-//
-// A workgroup (256 threads) owns an 8 x 8 x 8 tile of outputs, two per
-// thread. Per rotation it bounds the tile's preimage R^T kappa (a rotated
-// cube), loads that box of each channel into LDS with rows along kz (coalesced
-// reads, spec_at supplying the mirrored half and the zero band edge), and
-// interpolates from LDS. Corners outside the box (possible only through
-// rounding at the box edge) are read from global memory. Needs N/2 divisible by 8 (signed frequencies contiguous in
-// every tile). grid = (tiles, min(batch, 65535)).
-template <int N>
-__global__ void __launch_bounds__(256) k_spectral_rotate(const float2* __restrict__ in, int nch,
-                                                         const float* __restrict__ Rm, int batch,
-                                                         float2* __restrict__ out) {
-  constexpr int HN = N / 2 + 1, T = 8, NT = N / T, NTZ = (HN + T - 1) / T;
-  constexpr int BOX = 17;  // largest box edge: floor(7 sqrt(3)) + 2 = 14, with room for rounding
-  constexpr size_t SPEC = (size_t)N * N * HN;
-  static_assert((N / 2) % T == 0, "tiles must not straddle the sign change of the frequencies");
-  __shared__ float2 box[BOX * BOX * BOX];
-  const int t = blockIdx.x, tid = threadIdx.x;
-  const int tz = t % NTZ, ty = (t / NTZ) % NT, tx = t / (NTZ * NT);
-  auto signed_k = [](int k) { return k < N / 2 ? k : k - N; };
-  // signed frequency range of the tile per axis (kz beyond HN does not exist)
-  const int klo[3] = {signed_k(tx * T), signed_k(ty * T), signed_k(tz * T)};
-  const int kz_last = min(tz * T + T - 1, HN - 1);
-  const int khi[3] = {klo[0] + T - 1, klo[1] + T - 1, signed_k(tz * T) + (kz_last - tz * T)};
-  // this thread's two outputs
-  int kk[2][3];
-  bool valid[2];
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int o = tid + 256 * j;
-    kk[j][0] = tx * T + (o >> 6);
-    kk[j][1] = ty * T + ((o >> 3) & 7);
-    kk[j][2] = tz * T + (o & 7);
-    valid[j] = kk[j][2] < HN;
-  }
-  for (int b = blockIdx.y; b < batch; b += gridDim.y) {
-    double R[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) R[i] = (double)Rm[(size_t)b * 9 + i];
-    // integer box holding every corner: [lo, lo + ext) per axis
-    int lo[3], ext[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      double qmin = 0.0, qmax = 0.0;
-#pragma unroll
-      for (int e = 0; e < 3; ++e) {
-        const double r = R[3 * e + d], u = r * klo[e], v = r * khi[e];
-        qmin += fmin(u, v);
-        qmax += fmax(u, v);
-      }
-      lo[d] = (int)floor(qmin);
-      ext[d] = min((int)floor(qmax) + 2 - lo[d], BOX);
-    }
-    const int ez = ext[2], eyz = ext[1] * ext[2], etot = ext[0] * eyz;
-    const float inv_ez = 1.0f / (float)ez, inv_ey = 1.0f / (float)ext[1];
-    int i0[2][3];
-    float a[2][3];
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-      rotate_frequency(R, signed_k(kk[j][0]), signed_k(kk[j][1]), signed_k(kk[j][2]), i0[j], a[j]);
-    float2 acc[2][4];
-    for (int ch = 0; ch < nch; ++ch) {
-      const float2* X = in + (size_t)ch * SPEC;
-      __syncthreads();  // previous readers of the box are done
-      for (int i = tid; i < etot; i += 256) {
-        // i < 17^3 < 2^16: (i + 1/2) / e rounds down to the exact quotient
-        const int r = (int)(((float)i + 0.5f) * inv_ez), iz = i - r * ez;
-        const int ix = (int)(((float)r + 0.5f) * inv_ey), iy = r - ix * ext[1];
-        box[i] = spec_at<N>(X, lo[0] + ix, lo[1] + iy, lo[2] + iz);
-      }
-      __syncthreads();
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        if (!valid[j]) continue;
-        acc[j][ch] = trilinear_at(i0[j], a[j], [&](int x, int y, int z) {
-          const int ux = x - lo[0], uy = y - lo[1], uz = z - lo[2];
-          if ((unsigned)ux < (unsigned)ext[0] && (unsigned)uy < (unsigned)ext[1] && (unsigned)uz < (unsigned)ez)
-            return box[ux * eyz + uy * ez + uz];
-          return spec_at<N>(X, x, y, z);
-        });
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      if (!valid[j]) continue;
-      const size_t r = ((size_t)kk[j][0] * N + kk[j][1]) * HN + kk[j][2];
-      store_rotated(out + (size_t)b * nch * SPEC + r, SPEC, nch, R, acc[j]);
-    }
-  }
-}
-
-// The same rotation with every corner gathered from global memory: grid
-// edges whose N/2 is not a multiple of 8. A workgroup takes 2 (kx) x 8 (ky) x
-// 16 (kz) outputs. grid = (tiles, min(batch, 65535)).
-template <int N>
-__global__ void __launch_bounds__(256) k_spectral_rotate_gather(const float2* __restrict__ in, int nch,
-                                                                const float* __restrict__ Rm, int batch,
-                                                                float2* __restrict__ out) {
-  constexpr int HN = N / 2 + 1, TZ = 16, TY = 8;
-  constexpr int NTZ = (HN + TZ - 1) / TZ, NTY = N / TY;
-  constexpr size_t SPEC = (size_t)N * N * HN;
-  const int t = blockIdx.x;
-  const int kz = (t % NTZ) * TZ + (int)(threadIdx.x & 15);
-  const int ky = ((t / NTZ) % NTY) * TY + (int)((threadIdx.x >> 4) & 7);
-  const int kx = (t / (NTZ * NTY)) * 2 + (int)(threadIdx.x >> 7);
-  if (kz >= HN) return;  // no barrier below
-  const size_t r = ((size_t)kx * N + ky) * HN + kz;
-  const double k0 = kx < N / 2 ? kx : kx - N, k1 = ky < N / 2 ? ky : ky - N, k2 = kz < N / 2 ? kz : kz - N;
-  for (int b = blockIdx.y; b < batch; b += gridDim.y) {
-    double R[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) R[i] = (double)Rm[(size_t)b * 9 + i];
-    int i0[3];
-    float a[3];
-    rotate_frequency(R, k0, k1, k2, i0, a);
-    float2 acc[4];
-    for (int ch = 0; ch < nch; ++ch) {
-      const float2* X = in + (size_t)ch * SPEC;
-      acc[ch] = trilinear_at(i0, a, [&](int x, int y, int z) { return spec_at<N>(X, x, y, z); });
-    }
-    store_rotated(out + (size_t)b * nch * SPEC + r, SPEC, nch, R, acc);
   }
 }
 

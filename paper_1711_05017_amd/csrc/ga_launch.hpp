@@ -37,6 +37,9 @@ struct ga_plan {
   int tune_groups = 0;
   int tune_k = 0;
   int tune_xcd = 0;
+  // x transforms of the fused pass on the default radix schedule (0) or its
+  // alternative (1, where the edge has one)
+  int tune_radix = 0;
   // overlapped ga_energy_fields (ga_plan_set_overlap): the batch in `chunks`
   // parts, pass 1 on the caller's stream, the x pass and pass 3 on `aux`,
   // ordered by events ev[0 .. chunks) and joined back by ev[kMaxChunks]
@@ -166,49 +169,64 @@ template <int N> struct Launch {
   }
   // Fused correlation strip pass. With a shared stationary spectrum a
   // workgroup takes K batch members (default 4) on strips of G = groups x
-  // transforms-per-wave columns (default 4 groups); ga_plan_autotune picks
-  // both per plan.
+  // transforms-per-wave columns (default 4 groups), with the x transforms on
+  // the default radix schedule or its alternative (radix = 1); the
+  // autotuner picks all three per plan.
   static constexpr int kCorrK = 4;
-  template <int GG, int K>
+  template <int GG, int K, class SH>
   static void corr_fwd(const float2* A, long long a_stride, float2* buf, int batch, bool xcd, const float2* tw,
                        hipStream_t s) {
-    using TT = Strip<N, GG>;
+    using TT = Strip<N, GG, SH>;
     const int ns = (TT::C + GG - 1) / GG, m = (batch + K - 1) / K;
     if (xcd)
-      hipLaunchKernelGGL((k_strip_corr<N, GG, true, K>), dim3((unsigned)(((ns + 7) / 8) * 8 * m)), dim3(TT::THREADS), 0,
-                         s, A, a_stride, buf, buf, batch, m, tw);
+      hipLaunchKernelGGL((k_strip_corr<N, GG, true, K, SH>), dim3((unsigned)(((ns + 7) / 8) * 8 * m)),
+                         dim3(TT::THREADS), 0, s, A, a_stride, buf, buf, batch, m, tw);
     else
-      hipLaunchKernelGGL((k_strip_corr<N, GG, true, K>), dim3(ns, m), dim3(TT::THREADS), 0, s, A, a_stride, buf, buf,
-                         batch, 0, tw);
+      hipLaunchKernelGGL((k_strip_corr<N, GG, true, K, SH>), dim3(ns, m), dim3(TT::THREADS), 0, s, A, a_stride, buf,
+                         buf, batch, 0, tw);
   }
-  template <int GG>
+  template <int GG, class SH>
   static void corr_fwd_k(int k, const float2* A, long long a_stride, float2* buf, int batch, bool xcd,
                          const float2* tw, hipStream_t s) {
     switch (k) {
-      case 1: corr_fwd<GG, 1>(A, a_stride, buf, batch, xcd, tw, s); break;
-      case 2: corr_fwd<GG, 2>(A, a_stride, buf, batch, xcd, tw, s); break;
-      case 8: corr_fwd<GG, 8>(A, a_stride, buf, batch, xcd, tw, s); break;
-      default: corr_fwd<GG, 4>(A, a_stride, buf, batch, xcd, tw, s); break;
+      case 1: corr_fwd<GG, 1, SH>(A, a_stride, buf, batch, xcd, tw, s); break;
+      case 2: corr_fwd<GG, 2, SH>(A, a_stride, buf, batch, xcd, tw, s); break;
+      case 8: corr_fwd<GG, 8, SH>(A, a_stride, buf, batch, xcd, tw, s); break;
+      default: corr_fwd<GG, 4, SH>(A, a_stride, buf, batch, xcd, tw, s); break;
     }
   }
   // groups in {4, 8}, k in {1, 2, 4, 8}; k > 1 only with a shared spectrum.
   // Above 256 (few transforms per wavefront, large register footprint) the
   // strip keeps its default width and one member per workgroup.
-  static constexpr bool kTunable = N <= 256 && 4 * ffts_per_wave<N>() >= 16;
-  static void corr_fwd_tuned(int groups, int k, bool xcd, const float2* A, long long a_stride, float2* buf, int batch,
-                             const float2* tw, hipStream_t s) {
+  template <class SH>
+  static constexpr bool tunable() {
+    return N <= 256 && 4 * ffts_per_wave<N, SH>() >= 16;
+  }
+  static constexpr bool kTunable = tunable<Shape<N>>();
+  // whether the alternative radix schedule exists for this edge
+  static constexpr bool kAltRadix = ShapeAlt<N>::kDistinct && tunable<ShapeAlt<N>>();
+  static void corr_fwd_tuned(int groups, int k, bool xcd, int radix, const float2* A, long long a_stride, float2* buf,
+                             int batch, const float2* tw, hipStream_t s) {
     if (a_stride != 0 || batch == 1) k = 1;
     if constexpr (!kTunable) {
-      corr_fwd<G, 1>(A, a_stride, buf, batch, xcd, tw, s);
+      corr_fwd<G, 1, Shape<N>>(A, a_stride, buf, batch, xcd, tw, s);
     } else {
-      if (groups == 8) corr_fwd_k<8 * ffts_per_wave<N>()>(k, A, a_stride, buf, batch, xcd, tw, s);
-      else corr_fwd_k<4 * ffts_per_wave<N>()>(k, A, a_stride, buf, batch, xcd, tw, s);
+      if constexpr (kAltRadix) {
+        if (radix == 1) {
+          using SA = ShapeAlt<N>;
+          if (groups == 8) corr_fwd_k<8 * ffts_per_wave<N, SA>(), SA>(k, A, a_stride, buf, batch, xcd, tw, s);
+          else corr_fwd_k<4 * ffts_per_wave<N, SA>(), SA>(k, A, a_stride, buf, batch, xcd, tw, s);
+          return;
+        }
+      }
+      if (groups == 8) corr_fwd_k<8 * ffts_per_wave<N>(), Shape<N>>(k, A, a_stride, buf, batch, xcd, tw, s);
+      else corr_fwd_k<4 * ffts_per_wave<N>(), Shape<N>>(k, A, a_stride, buf, batch, xcd, tw, s);
     }
   }
   static void strip_corr(bool fwd, const float2* A, long long a_stride, const float2* B, float2* out, int batch,
                          const float2* tw, hipStream_t s) {
     if (fwd && B == out) {
-      corr_fwd_tuned(4, kCorrK, false, A, a_stride, out, batch, tw, s);
+      corr_fwd_tuned(4, kCorrK, false, 0, A, a_stride, out, batch, tw, s);
     } else if (fwd) {
       hipLaunchKernelGGL((k_strip_corr<N, G, true, 1>), dim3(nstrips(), batch), dim3(T::THREADS), 0, s, A, a_stride, B,
                          out, batch, 0, tw);

@@ -13,6 +13,8 @@
 
 #include "ga.h"
 #include "ga_launch.hpp"
+#include "ga_rotate.hpp"
+#include "ga_tune_cache.hpp"
 
 using namespace ga;
 using namespace ga_detail;
@@ -54,8 +56,34 @@ void launch_single(const ga_plan* plan, const float2* A, const float2* B4, const
                      scale, (const QueryItem*)nullptr);
 }
 
-}  // namespace
+// Whether edge n has an alternative radix schedule for the fused x pass.
+bool has_alt_radix(int n) {
+  bool alt = false;
+  if (n <= 192 && n >= 16) dispatch_axis(n, [&]<int N>() { alt = Launch<N>::kAltRadix; });
+  return alt;
+}
 
+// Launch of the rotation kernels for a source (PlanarSrc or PackedSrc).
+template <template <int> class SrcT, class MakeSrc>
+void launch_rotate(int n, MakeSrc make_src, const float* d_R, int32_t batch, float* d_out, hipStream_t stream) {
+  dispatch_axis(n, [&]<int N>() {
+    const dim3 block(256);
+    const auto out = reinterpret_cast<float2*>(d_out);
+    const unsigned nb = (unsigned)std::min(batch, 65535);
+    const SrcT<N> src = make_src.template operator()<N>();
+    if constexpr ((N / 2) % 8 == 0) {
+      constexpr int tiles = (N / 8) * (N / 8) * ((N / 2 + 1 + 7) / 8);  // 8 x 8 x 8 outputs per workgroup
+      hipLaunchKernelGGL((k_spectral_rotate<N, SrcT<N>>), dim3(tiles, nb), block, 0, stream, src, d_R, (int)batch,
+                         out);
+    } else {
+      constexpr int tiles = (N / 2) * (N / 8) * ((N / 2 + 1 + 15) / 16);  // 2 x 8 x 16 outputs per workgroup
+      hipLaunchKernelGGL((k_spectral_rotate_gather<N, SrcT<N>>), dim3(tiles, nb), block, 0, stream, src, d_R,
+                         (int)batch, out);
+    }
+  });
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -391,9 +419,8 @@ ga_status ga_energy_fields(const ga_plan* plan, const float* d_Ahat, const float
       }
       {
         ProfScope ps(plan, GA_K_STRIP, stream);
-        Launch<N>::corr_fwd_tuned(groups, k, plan->tune_xcd == 1, reinterpret_cast<const float2*>(d_Ahat), 0, tmp,
-                                  batch, plan->d_tw,
-                                  stream);
+        Launch<N>::corr_fwd_tuned(groups, k, plan->tune_xcd == 1, plan->tune_radix,
+                                  reinterpret_cast<const float2*>(d_Ahat), 0, tmp, batch, plan->d_tw, stream);
       }
       ProfScope ps(plan, GA_K_PLANE_INV, stream);
       Axis<N>::yz_inv(tmp, d_E, scale, batch, plan->d_tw, stream);
@@ -447,8 +474,8 @@ ga_status ga_energy_fields(const ga_plan* plan, const float* d_Ahat, const float
       }
       {
         ProfScope ps(plan, GA_K_STRIP, sc);
-        Launch<N>::corr_fwd_tuned(groups, k, plan->tune_xcd == 1, reinterpret_cast<const float2*>(d_Ahat), 0, tc, nb,
-                                  plan->d_tw, sc);
+        Launch<N>::corr_fwd_tuned(groups, k, plan->tune_xcd == 1, plan->tune_radix,
+                                  reinterpret_cast<const float2*>(d_Ahat), 0, tc, nb, plan->d_tw, sc);
       }
       ProfScope ps(plan, GA_K_PLANE_INV, sc);
       Launch<N>::plane_inv(tc, d_E + (size_t)c0 * n * n * n, scale, nb, plan->d_tw, sc);
@@ -657,18 +684,18 @@ ga_status ga_pose_spectral(const ga_plan* plan, const float* d_AX2, const float*
   return launch_status();
 }
 
-ga_status ga_plan_autotune(ga_plan* plan, const float* d_Ahat, int32_t batch, void* d_work, size_t work_bytes,
-                           hipStream_t stream, float* h_us, int32_t n_us) {
-  if (!valid_stream_call(plan) || !d_Ahat || batch < 1 || batch > plan->max_batch || n_us < 0 || (n_us > 0 && !h_us))
-    return GA_EINVAL;
-  if (!all_aligned(d_Ahat, d_work)) return GA_EINVAL;
+// Times the fused x-pass candidates groups (4, 8) x k (1, 2, 4, 8) on the
+// grids in xcds (plain 2, XCD-aware 1) on d_work (zeroed first) against
+// d_Ahat: one warm-up and three timed launches each. h_us (n_us entries) gets
+// the per-launch times in the order xcd x groups x k; the fastest is returned.
+static ga_status time_strip_candidates(const ga_plan* plan, const float* d_Ahat, int32_t batch, void* d_work,
+                                       hipStream_t stream, const int* xcds, int nx, float* h_us, int32_t n_us,
+                                       TuneEntry& best) {
+  int nradix = 1;
+  dispatch_axis(plan->n, [&]<int N>() { nradix = Launch<N>::kAltRadix ? 2 : 1; });
   const int n = plan->n;
-  const size_t spec_b = spectrum_elems(n) * sizeof(float2);
-  const size_t tmp_b = (size_t)batch * spec_b;
-  if (!d_work || work_bytes < tmp_b) return GA_ENOMEM;
-  if (overlaps(d_work, tmp_b, d_Ahat, spec_b)) return GA_EINVAL;
   float2* tmp = static_cast<float2*>(d_work);
-  const long long n4 = (long long)(tmp_b / sizeof(float4));
+  const long long n4 = (long long)((size_t)batch * spectrum_elems(n) * sizeof(float2) / sizeof(float4));
   hipLaunchKernelGGL(k_zero4, dim3((unsigned)std::min<long long>((n4 + 255) / 256, 65535)), dim3(256), 0, stream,
                      static_cast<float4*>(d_work), n4);
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -676,47 +703,157 @@ ga_status ga_plan_autotune(ga_plan* plan, const float* d_Ahat, int32_t batch, vo
     if (e0) (void)hipEventDestroy(e0);
     return GA_EDEVICE;
   }
-  static constexpr int kGroups[2] = {4, 8}, kKs[4] = {1, 2, 4, 8}, kX[2] = {1, 2};
-  float best = 0.f;
-  int best_g = 4, best_k = 4, best_x = 1, idx = 0;
+  static constexpr int kGroups[2] = {4, 8}, kKs[4] = {1, 2, 4, 8};
   ga_status st = GA_OK;
-  for (int xi = 0; xi < 2 && st == GA_OK; ++xi)
-  for (int gi = 0; gi < 2 && st == GA_OK; ++gi) {
-    for (int ki = 0; ki < 4 && st == GA_OK; ++ki, ++idx) {
-      const int g = kGroups[gi], k = kKs[ki], x = kX[xi];
-      auto run = [&]() {
-        dispatch_axis(n, [&]<int N>() {
-          Launch<N>::corr_fwd_tuned(g, k, x == 1, reinterpret_cast<const float2*>(d_Ahat), 0, tmp, batch, plan->d_tw,
-                                    stream);
-        });
-      };
-      run();  // warm-up
-      (void)hipEventRecord(e0, stream);
-      for (int r = 0; r < 3; ++r) run();
-      (void)hipEventRecord(e1, stream);
-      float ms = 0.f;
-      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-        st = GA_EDEVICE;
-        break;
+  int idx = 0;
+  for (int xi = 0; xi < nx && st == GA_OK; ++xi)
+    for (int rx = 0; rx < 2 && st == GA_OK; ++rx)
+    for (int gi = 0; gi < 2 && st == GA_OK; ++gi)
+      for (int ki = 0; ki < 4 && st == GA_OK; ++ki, ++idx) {
+        if (rx >= nradix) {  // no alternative schedule: the slot stays 0
+          if (idx < n_us) h_us[idx] = 0.f;
+          continue;
+        }
+        const int g = kGroups[gi], k = kKs[ki], x = xcds[xi];
+        auto run = [&]() {
+          dispatch_axis(n, [&]<int N>() {
+            Launch<N>::corr_fwd_tuned(g, k, x == 1, rx, reinterpret_cast<const float2*>(d_Ahat), 0, tmp, batch,
+                                      plan->d_tw, stream);
+          });
+        };
+        run();  // warm-up
+        (void)hipEventRecord(e0, stream);
+        for (int r = 0; r < 3; ++r) run();
+        (void)hipEventRecord(e1, stream);
+        float ms = 0.f;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          st = GA_EDEVICE;
+          break;
+        }
+        const float us = ms * 1000.f / 3.f;
+        if (idx < n_us) h_us[idx] = us;
+        if (idx == 0 || us < best.us) {
+          best.us = us;
+          best.groups = g;
+          best.k = k;
+          best.xcd = x;
+          best.radix = rx;
+        }
       }
-      const float us = ms * 1000.f / 3.f;
-      if (idx < n_us) h_us[idx] = us;
-      if (idx == 0 || us < best) {
-        best = us;
-        best_g = g;
-        best_k = k;
-        best_x = x;
-      }
-    }
-  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != GA_OK) return st;
-  st = launch_status();
+  return launch_status();
+}
+
+ga_status ga_plan_autotune(ga_plan* plan, const float* d_Ahat, int32_t batch, void* d_work, size_t work_bytes,
+                           hipStream_t stream, float* h_us, int32_t n_us) {
+  if (!valid_stream_call(plan) || !d_Ahat || batch < 1 || batch > plan->max_batch || n_us < 0 || (n_us > 0 && !h_us))
+    return GA_EINVAL;
+  if (!all_aligned(d_Ahat, d_work)) return GA_EINVAL;
+  const size_t spec_b = spectrum_elems(plan->n) * sizeof(float2);
+  const size_t tmp_b = (size_t)batch * spec_b;
+  if (!d_work || work_bytes < tmp_b) return GA_ENOMEM;
+  if (overlaps(d_work, tmp_b, d_Ahat, spec_b)) return GA_EINVAL;
+  static constexpr int kPlain[1] = {2};
+  TuneEntry best;
+  const ga_status st = time_strip_candidates(plan, d_Ahat, batch, d_work, stream, kPlain, 1, h_us, n_us, best);
   if (st != GA_OK) return st;
-  plan->tune_groups = best_g;
-  plan->tune_k = best_k;
-  plan->tune_xcd = best_x;
+  plan->tune_groups = best.groups;
+  plan->tune_k = best.k;
+  plan->tune_xcd = best.xcd;
+  plan->tune_radix = best.radix;
+  return GA_OK;
+}
+
+ga_status ga_plan_tune(ga_plan* plan, const float* d_Ahat, const float* d_xyzr, const float* d_w, int64_t n_pts,
+                       const float* d_R, const float* h_c, float sigma, int32_t batch, float* d_E, void* d_work,
+                       size_t work_bytes, uint32_t flags, const char* cache_path, hipStream_t stream,
+                       ga_tuning* result) {
+  if (!valid_stream_call(plan) || !result || (flags & ~(GA_TUNE_XCD | GA_TUNE_OVERLAP)) != 0) return GA_EINVAL;
+  if (plan->n > 192 || axis_mode(plan)) return GA_EUNSUPPORTED;
+  if (batch < 1 || batch > plan->max_batch) return GA_EINVAL;
+  if (!d_work || work_bytes < ga_workspace_size(plan, GA_OP_ENERGY, batch, n_pts)) return GA_ENOMEM;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, plan->device) != hipSuccess) return GA_EDEVICE;
+  const std::string key = tune_key(prop.gcnArchName, plan->n, batch, 1);
+  std::map<std::string, TuneEntry> cache;
+  bool exists = false;
+  if (cache_path && !tune_cache_load(cache_path, cache, exists)) return GA_EINVAL;  // unreadable or malformed
+  auto apply = [&](const TuneEntry& e, int from_cache) -> ga_status {
+    if (e.radix == 1 && !has_alt_radix(plan->n)) return GA_EINVAL;
+    plan->tune_groups = e.groups;
+    plan->tune_k = e.k;
+    plan->tune_xcd = e.xcd;
+    plan->tune_radix = e.radix;
+    const ga_status s = ga_plan_set_overlap(plan, e.overlap);
+    if (s != GA_OK) return s;
+    result->groups = e.groups;
+    result->k = e.k;
+    result->xcd = e.xcd;
+    result->radix = e.radix;
+    result->overlap = e.overlap;
+    result->us = (float)e.us;
+    result->from_cache = from_cache;
+    return GA_OK;
+  };
+  if (const auto it = cache.find(key); it != cache.end()) return apply(it->second, 1);
+  // the fused x pass alone, on the workspace's spectrum part
+  static constexpr int kPlain[1] = {2}, kBoth[2] = {2, 1};
+  TuneEntry best;
+  ga_status st = (flags & GA_TUNE_XCD) ? time_strip_candidates(plan, d_Ahat, batch, d_work, stream, kBoth, 2, nullptr, 0, best)
+                                       : time_strip_candidates(plan, d_Ahat, batch, d_work, stream, kPlain, 1, nullptr, 0, best);
+  if (st != GA_OK) return st;
+  plan->tune_groups = best.groups;
+  plan->tune_k = best.k;
+  plan->tune_xcd = best.xcd;
+  plan->tune_radix = best.radix;
+  // whole calls for the part counts: two rounds over the candidates, the
+  // best time of each kept
+  static constexpr int kParts[3] = {1, 2, 4};
+  const int nparts = (flags & GA_TUNE_OVERLAP) ? 3 : 1;
+  const int keep_overlap = plan->chunks;
+  float part_us[3] = {0.f, 0.f, 0.f};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return GA_EDEVICE;
+  }
+  for (int round = 0; round < 2 && st == GA_OK; ++round)
+    for (int pi = 0; pi < nparts && st == GA_OK; ++pi) {
+      st = ga_plan_set_overlap(plan, nparts == 1 ? keep_overlap : kParts[pi]);
+      auto call = [&]() {
+        return ga_energy_fields(plan, d_Ahat, d_xyzr, d_w, n_pts, d_R, h_c, sigma, batch, d_E, d_work, work_bytes,
+                                stream);
+      };
+      for (int r = 0; r < 2 && st == GA_OK; ++r) st = call();
+      if (st != GA_OK) break;
+      (void)hipEventRecord(e0, stream);
+      for (int r = 0; r < 5 && st == GA_OK; ++r) st = call();
+      (void)hipEventRecord(e1, stream);
+      float ms = 0.f;
+      if (st == GA_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        st = GA_EDEVICE;
+      const float us = ms * 1000.f / 5.f;
+      if (round == 0 || us < part_us[pi]) part_us[pi] = us;
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != GA_OK) {
+    (void)ga_plan_set_overlap(plan, keep_overlap);
+    return st;
+  }
+  int bi = 0;
+  for (int pi = 1; pi < nparts; ++pi)
+    if (part_us[pi] < part_us[bi]) bi = pi;
+  best.overlap = (nparts == 1) ? keep_overlap : kParts[bi];
+  best.us = part_us[bi];
+  st = apply(best, 0);
+  if (st != GA_OK) return st;
+  if (cache_path) {
+    cache[key] = best;
+    if (!tune_cache_store(cache_path, cache)) return GA_EINVAL;
+  }
   return GA_OK;
 }
 
@@ -729,6 +866,16 @@ ga_status ga_plan_set_tuning(ga_plan* plan, int32_t groups, int32_t k, int32_t x
   plan->tune_xcd = xcd;
   return GA_OK;
 }
+
+ga_status ga_plan_set_radix(ga_plan* plan, int32_t radix) {
+  if (!plan || (radix != 0 && radix != 1) || (radix == 1 && !has_alt_radix(plan->n))) return GA_EINVAL;
+  plan->tune_radix = radix;
+  return GA_OK;
+}
+
+int32_t ga_plan_get_radix(const ga_plan* plan) { return plan ? plan->tune_radix : -1; }
+
+int32_t ga_plan_has_alt_radix(const ga_plan* plan) { return (plan && has_alt_radix(plan->n)) ? 1 : 0; }
 
 ga_status ga_plan_get_tuning(const ga_plan* plan, int32_t* groups, int32_t* k, int32_t* xcd) {
   if (!plan || !groups || !k || !xcd) return GA_EINVAL;
@@ -802,21 +949,33 @@ ga_status ga_spectral_rotate(const ga_plan* plan, const float* d_in, int32_t cha
       overlaps(d_R, sizeof(float) * 9 * (size_t)batch, d_out, (size_t)batch * channels * spec_b))
     return GA_EINVAL;
   ProfScope ps(plan, GA_K_READOUT, stream);
-  dispatch_axis(n, [&]<int N>() {
-    const dim3 block(256);
-    const auto in = reinterpret_cast<const float2*>(d_in);
-    const auto out = reinterpret_cast<float2*>(d_out);
-    const unsigned nb = (unsigned)std::min(batch, 65535);
-    if constexpr ((N / 2) % 8 == 0) {
-      constexpr int tiles = (N / 8) * (N / 8) * ((N / 2 + 1 + 7) / 8);  // 8 x 8 x 8 outputs per workgroup
-      hipLaunchKernelGGL(k_spectral_rotate<N>, dim3(tiles, nb), block, 0, stream, in, (int)channels, d_R,
-                         (int)batch, out);
-    } else {
-      constexpr int tiles = (N / 2) * (N / 8) * ((N / 2 + 1 + 15) / 16);  // 2 x 8 x 16 outputs per workgroup
-      hipLaunchKernelGGL(k_spectral_rotate_gather<N>, dim3(tiles, nb), block, 0, stream, in, (int)channels, d_R,
-                         (int)batch, out);
-    }
-  });
+  const auto in = reinterpret_cast<const float2*>(d_in);
+  launch_rotate<PlanarSrc>(n, [&]<int N>() { return PlanarSrc<N>{in, (int)channels}; }, d_R, batch, d_out, stream);
+  return launch_status();
+}
+
+ga_status ga_spectral_pack4(const ga_plan* plan, const float* d_in4, float* d_packed, hipStream_t stream) {
+  if (!valid_stream_call(plan) || !d_in4 || !d_packed) return GA_EINVAL;
+  if (!all_aligned(d_in4, d_packed)) return GA_EINVAL;
+  const size_t spec = spectrum_elems(plan->n), bytes = 4 * spec * sizeof(float2);
+  if (overlaps(d_in4, bytes, d_packed, bytes)) return GA_EINVAL;
+  const long long blocks = std::min<long long>(((long long)spec + 255) / 256, 65535);
+  hipLaunchKernelGGL(k_pack4, dim3((unsigned)blocks), dim3(256), 0, stream, reinterpret_cast<const float2*>(d_in4),
+                     reinterpret_cast<float4*>(d_packed), (long long)spec);
+  return launch_status();
+}
+
+ga_status ga_spectral_rotate_packed(const ga_plan* plan, const float* d_packed, const float* d_R, int32_t batch,
+                                    float* d_out, hipStream_t stream) {
+  if (!valid_stream_call(plan) || !d_packed || !d_R || !d_out || batch < 1) return GA_EINVAL;
+  if (!all_aligned(d_packed, d_out)) return GA_EINVAL;
+  const int n = plan->n;
+  const size_t spec_b = spectrum_elems(n) * sizeof(float2), out_b = (size_t)batch * 4 * spec_b;
+  if (overlaps(d_packed, 4 * spec_b, d_out, out_b) || overlaps(d_R, sizeof(float) * 9 * (size_t)batch, d_out, out_b))
+    return GA_EINVAL;
+  ProfScope ps(plan, GA_K_READOUT, stream);
+  const auto P = reinterpret_cast<const float4*>(d_packed);
+  launch_rotate<PackedSrc>(n, [&]<int N>() { return PackedSrc<N>{P}; }, d_R, batch, d_out, stream);
   return launch_status();
 }
 

@@ -37,6 +37,8 @@ EXPORTS = [
     "ga_plan_autotune", "ga_plan_set_tuning", "ga_plan_get_tuning", "ga_lowpass",
     "ga_spectral_rotate", "ga_field_table", "ga_field_table_query", "ga_score", "ga_plan_set_overlap",
     "ga_plan_get_overlap", "ga_force_torque_noalloc", "ga_pose_prepare", "ga_pose_spectral",
+    "ga_spectral_pack4", "ga_spectral_rotate_packed", "ga_plan_tune", "ga_plan_set_radix", "ga_plan_get_radix",
+    "ga_plan_has_alt_radix",
 ]
 GA_K_SPLAT, GA_K_PLANE_FWD, GA_K_STRIP, GA_K_PLANE_INV, GA_K_READOUT, GA_K_BIN = 0, 1, 2, 3, 4, 5
 KERNEL_KINDS = {"splat": 0, "plane_fwd": 1, "strip": 2, "plane_inv": 3, "readout": 4, "bin": 5}
@@ -113,6 +115,13 @@ _SIGS = {
     "ga_field_table": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int32, _vp, _vp, ctypes.c_size_t, _vp]),
     "ga_field_table_query": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32, _vp, _vp]),
     "ga_spectral_rotate": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp]),
+    "ga_spectral_pack4": (ctypes.c_int32, [_vp, _vp, _vp, _vp]),
+    "ga_plan_set_radix": (ctypes.c_int32, [_vp, ctypes.c_int32]),
+    "ga_plan_get_radix": (ctypes.c_int32, [_vp]),
+    "ga_plan_has_alt_radix": (ctypes.c_int32, [_vp]),
+    "ga_plan_tune": (ctypes.c_int32, [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_float, ctypes.c_int32,
+                                      _vp, _vp, ctypes.c_size_t, ctypes.c_uint32, ctypes.c_char_p, _vp, _vp]),
+    "ga_spectral_rotate_packed": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int32, _vp, _vp]),
     "ga_lowpass": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_uint32, _vp, _vp, ctypes.c_int32, ctypes.c_float,
                                     _vp]),
     "ga_plan_autotune": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, _vp, ctypes.c_size_t, _vp,
@@ -128,6 +137,14 @@ _SIGS = {
 }
 
 _lib = None
+
+
+GA_TUNE_XCD, GA_TUNE_OVERLAP = 1, 2
+
+
+class GaTuning(ctypes.Structure):
+    _fields_ = [("groups", ctypes.c_int32), ("k", ctypes.c_int32), ("xcd", ctypes.c_int32), ("radix", ctypes.c_int32),
+                ("overlap", ctypes.c_int32), ("us", ctypes.c_float), ("from_cache", ctypes.c_int32)]
 
 
 class GaError(RuntimeError):
@@ -228,20 +245,59 @@ class Plan:
         nbytes = load().ga_workspace_size(self._h, op, batch, n_items)
         return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device or "cuda")
 
-    TUNE_CANDIDATES = [(g, k, x) for x in (1, 2) for g in (4, 8) for k in (1, 2, 4, 8)]
+    # every settable choice of the fused x pass (groups, members per
+    # workgroup, XCD-aware grid 1 / plain 2, radix schedule 0 / 1), and the
+    # ones ga_plan_autotune times (radix 1 only where the edge has it)
+    TUNE_CANDIDATES = [(g, k, x, r) for x in (1, 2) for r in (0, 1) for g in (4, 8) for k in (1, 2, 4, 8)]
+    AUTOTUNE_CANDIDATES = [(g, k, 2, r) for r in (0, 1) for g in (4, 8) for k in (1, 2, 4, 8)]
+
+    def has_alt_radix(self) -> bool:
+        return bool(load().ga_plan_has_alt_radix(self._h))
 
     def autotune(self, Ahat: torch.Tensor, batch: int, work: Optional[torch.Tensor] = None, stream=None):
-        """Time the fused x-pass candidates (groups, members per workgroup,
-        XCD-aware grid 1 / plain 2) and keep the fastest; returns (choice,
-        {candidate: microseconds})."""
+        """Time the plain-grid fused x-pass candidates and keep the fastest;
+        returns ((groups, k, xcd, radix), {candidate: microseconds}) over the
+        candidates that exist for this edge."""
         _need(Ahat, torch.complex64, _spec_elems(self.n), "Ahat")
         if work is None:
             work = torch.empty(int(batch) * _spec_elems(self.n) * 8, dtype=torch.uint8, device=Ahat.device)
-        nc = len(self.TUNE_CANDIDATES)
+        nc = len(self.AUTOTUNE_CANDIDATES)
         us = (ctypes.c_float * nc)()
         _check("ga_plan_autotune", load().ga_plan_autotune(self._h, _ptr(Ahat), int(batch), _ptr(work),
                                                            int(work.numel()), _stream(stream), us, nc))
-        return self.tuning(), {c: round(us[i], 2) for i, c in enumerate(self.TUNE_CANDIDATES)}
+        alt = self.has_alt_radix()
+        times = {c: round(us[i], 2) for i, c in enumerate(self.AUTOTUNE_CANDIDATES) if alt or c[3] == 0}
+        return self.tuning() + (self.radix(),), times
+
+    def set_radix(self, radix: int):
+        _check("ga_plan_set_radix", load().ga_plan_set_radix(self._h, int(radix)))
+
+    def radix(self) -> int:
+        return int(load().ga_plan_get_radix(self._h))
+
+    def tune(self, Ahat: torch.Tensor, xyzr: torch.Tensor, w: torch.Tensor, R: torch.Tensor, c, sigma: float = 0.5,
+             flags: int = 0, cache_path: Optional[str] = None, out: Optional[torch.Tensor] = None, work=None,
+             stream=None) -> dict:
+        """ga_plan_tune: tune a whole ga_energy_fields call of this shape (or
+        apply the choice stored under its key in cache_path); returns the
+        choice as a dict (groups, k, xcd, overlap, us, from_cache)."""
+        n = self.n
+        batch = int(R.shape[0])
+        m = _samples(xyzr, w)
+        _need(R, torch.float32, 9 * batch, "R", exact=True)
+        _need(Ahat, torch.complex64, _spec_elems(n), "Ahat")
+        if out is None:
+            out = torch.empty((batch, n, n, n), dtype=torch.float32, device=xyzr.device)
+        _need(out, torch.float32, batch * n ** 3, "out")
+        if work is None:
+            work = self.workspace(GA_OP_ENERGY, batch, m, device=xyzr.device)
+        res = GaTuning()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check("ga_plan_tune", load().ga_plan_tune(self._h, _ptr(Ahat), _ptr(xyzr), _ptr(w), m, _ptr(R), _host_f32(c, 3),
+                                                   float(sigma), batch, _ptr(out), _ptr(work), int(work.numel()),
+                                                   int(flags), path, _stream(stream), ctypes.byref(res)))
+        return {"groups": res.groups, "k": res.k, "xcd": res.xcd, "radix": res.radix, "overlap": res.overlap,
+                "us": round(res.us, 2), "from_cache": res.from_cache}
 
     def set_tuning(self, groups: int, k: int, xcd: int = 0):
         _check("ga_plan_set_tuning", load().ga_plan_set_tuning(self._h, int(groups), int(k), int(xcd)))
@@ -544,6 +600,35 @@ def ga_spectral_rotate(plan: Plan, X: torch.Tensor, R: torch.Tensor, out: Option
     _need(out, torch.complex64, batch * ch * _spec_elems(n), "out")
     _check("ga_spectral_rotate", load().ga_spectral_rotate(plan.handle, _ptr(X), ch, _ptr(R), batch, _ptr(out),
                                                            _stream(stream)))
+    return out
+
+
+def ga_spectral_pack4(plan: Plan, X4: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """The 4 half spectra X4 [4, n, n, n/2+1] as one 32-byte record per
+    frequency: returns [n, n, n/2+1, 4] complex64 (the 4 channels of a
+    frequency side by side), the source of ga_spectral_rotate_packed."""
+    n = plan.n
+    _need(X4, torch.complex64, 4 * _spec_elems(n), "X4", exact=True)
+    if out is None:
+        out = torch.empty((n, n, n // 2 + 1, 4), dtype=torch.complex64, device=X4.device)
+    _need(out, torch.complex64, 4 * _spec_elems(n), "out")
+    _check("ga_spectral_pack4", load().ga_spectral_pack4(plan.handle, _ptr(X4), _ptr(out), _stream(stream)))
+    return out
+
+
+def ga_spectral_rotate_packed(plan: Plan, P: torch.Tensor, R: torch.Tensor, out: Optional[torch.Tensor] = None,
+                              stream=None) -> torch.Tensor:
+    """ga_spectral_rotate of the 4 channels from packed spectra P
+    (ga_spectral_pack4); returns [batch, 4, n, n, n/2+1]."""
+    n = plan.n
+    _need(P, torch.complex64, 4 * _spec_elems(n), "P", exact=True)
+    batch = int(R.shape[0])
+    _need(R, torch.float32, 9 * batch, "R", exact=True)
+    if out is None:
+        out = torch.empty((batch, 4, n, n, n // 2 + 1), dtype=torch.complex64, device=P.device)
+    _need(out, torch.complex64, batch * 4 * _spec_elems(n), "out")
+    _check("ga_spectral_rotate_packed", load().ga_spectral_rotate_packed(plan.handle, _ptr(P), _ptr(R), batch,
+                                                                         _ptr(out), _stream(stream)))
     return out
 
 

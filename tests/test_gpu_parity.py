@@ -462,8 +462,11 @@ def test_c3_batched_rotations_full_size_sampled(G):
 # autotuned fused pass: every candidate gives the oracle's fields
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("n,npts,nrot", [(32, 200, 5), (96, 700, 3)])
+@pytest.mark.parametrize("n,npts,nrot", [(32, 200, 5), (64, 400, 3), (96, 700, 3), (48, 300, 2)])
 def test_every_tuning_candidate_matches_oracle(G, n, npts, nrot):
+    """Every strip width, member count, grid mapping and radix schedule of
+    the fused x pass gives the oracle's fields (48 has no alternative
+    schedule: radix 1 is refused there)."""
     A = _part(n, 900 + n, npts, 1.0, 3.0)
     B = _part(n, 950 + n, npts, 1.0, 3.0, conf=n / 6)
     rots = synth.shoemake_rotations(990 + n, nrot)
@@ -472,14 +475,22 @@ def test_every_tuning_candidate_matches_oracle(G, n, npts, nrot):
     Ahat = G.ga_fft3d(plan, G.GA_R2C, G.ga_splat(plan, _dev(A.xyzr), _dev(A.w)))[0].contiguous()
     refs = [O.pair_fields(A.xyzr, A.w, B.xyzr, B.w, rots[r], cB, n, want_torque=False)["E"] for r in range(nrot)]
     R = _dev(rots.reshape(nrot, 9).astype(np.float32))
-    for g, k, x in G.Plan.TUNE_CANDIDATES:
+    alt = plan.has_alt_radix()
+    assert alt == (n != 48)
+    for g, k, x, rx in G.Plan.TUNE_CANDIDATES:
+        if rx == 1 and not alt:
+            with pytest.raises(G.GaError):
+                plan.set_radix(1)
+            continue
         plan.set_tuning(g, k, x)
-        assert plan.tuning() == (g, k, x)
+        plan.set_radix(rx)
+        assert plan.tuning() == (g, k, x) and plan.radix() == rx
         E = G.ga_energy_fields(plan, Ahat, _dev(B.xyzr), _dev(B.w), R, cB).cpu().numpy()
         for r in range(nrot):
-            assert O.rel_l2(E[r], refs[r]) < FIELD_TOL, (g, k, r)
+            assert O.rel_l2(E[r], refs[r]) < FIELD_TOL, (g, k, x, rx, r)
     choice, times = plan.autotune(Ahat, nrot)
-    assert choice in G.Plan.TUNE_CANDIDATES and len(times) == 16 and all(t > 0 for t in times.values())
+    assert choice in G.Plan.AUTOTUNE_CANDIDATES and len(times) == (16 if alt else 8)
+    assert all(t > 0 for t in times.values())
     E = G.ga_energy_fields(plan, Ahat, _dev(B.xyzr), _dev(B.w), R, cB).cpu().numpy()
     assert O.rel_l2(E[0], refs[0]) < FIELD_TOL
     with pytest.raises(G.GaError):
@@ -488,6 +499,53 @@ def test_every_tuning_candidate_matches_oracle(G, n, npts, nrot):
         plan.set_tuning(4, 3)
     with pytest.raises(G.GaError):
         plan.set_tuning(4, 4, 3)
+
+
+def test_whole_call_tuning_is_cached_per_shape(G, tmp_path):
+    """ga_plan_tune times the fused x pass (with the XCD-aware grid) and the
+    part counts of whole calls, applies the fastest and stores it under
+    "<arch>/<n>/<batch>/1"; a second plan of the same shape takes the stored
+    choice without timing; the fields after tuning match the oracle; a cache
+    file in another layout is refused and left as it was."""
+    import json
+
+    n, npts, nrot = 64, 600, 4
+    A = _part(n, 1270, npts, 1.0, 3.0)
+    B = _part(n, 1271, npts, 1.0, 3.0, conf=n / 6)
+    rots = synth.shoemake_rotations(1272, nrot)
+    cB = B.ref_point()
+    R = _dev(rots.reshape(nrot, 9).astype(np.float32))
+    path = str(tmp_path / "tune.json")
+    plan = G.Plan(n, max_batch=nrot)
+    Ahat = G.ga_fft3d(plan, G.GA_R2C, G.ga_splat(plan, _dev(A.xyzr), _dev(A.w)))[0].contiguous()
+    got = plan.tune(Ahat, _dev(B.xyzr), _dev(B.w), R, cB, flags=G.ga.GA_TUNE_XCD | G.ga.GA_TUNE_OVERLAP,
+                    cache_path=path)
+    assert got["from_cache"] == 0 and got["us"] > 0
+    assert (got["groups"], got["k"], got["xcd"], got["radix"]) in G.Plan.TUNE_CANDIDATES and got["overlap"] in (1, 2, 4)
+    assert plan.tuning() == (got["groups"], got["k"], got["xcd"]) and plan.overlap() == got["overlap"]
+    assert plan.radix() == got["radix"]
+    stored = json.load(open(path))
+    (key, entry), = stored.items()
+    assert key.endswith(f"/{n}/{nrot}/1") and key.split("/")[0].startswith("gfx")
+    keys = ("groups", "k", "xcd", "radix", "overlap")
+    assert {k: entry[k] for k in keys} == {k: got[k] for k in keys}
+    E = G.ga_energy_fields(plan, Ahat, _dev(B.xyzr), _dev(B.w), R, cB).cpu().numpy()
+    for r in range(nrot):
+        ref = O.pair_fields(A.xyzr, A.w, B.xyzr, B.w, rots[r], cB, n, want_torque=False)["E"]
+        assert O.rel_l2(E[r], ref) < FIELD_TOL, r
+    plan2 = G.Plan(n, max_batch=nrot)
+    again = plan2.tune(Ahat, _dev(B.xyzr), _dev(B.w), R, cB, cache_path=path)
+    assert again["from_cache"] == 1 and {k: again[k] for k in keys} == {k: got[k] for k in keys}
+    assert plan2.tuning() == plan.tuning() and plan2.overlap() == plan.overlap() and plan2.radix() == plan.radix()
+    # another batch size is another key: both kept
+    plan3 = G.Plan(n, max_batch=nrot)
+    plan3.tune(Ahat, _dev(B.xyzr), _dev(B.w), R[:2].contiguous(), cB, cache_path=path)
+    assert len(json.load(open(path))) == 2
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"gfx950/64/4/1": {"groups": 5}}\n')
+    with pytest.raises(G.GaError):
+        plan.tune(Ahat, _dev(B.xyzr), _dev(B.w), R, cB, cache_path=str(bad))
+    assert bad.read_text() == '{"gfx950/64/4/1": {"groups": 5}}\n'
 
 
 # ---------------------------------------------------------------------------
