@@ -35,22 +35,57 @@ HBM_PEAK_GBPS = 8000.0
 
 # HBM bytes per launch of each field kernel at 128^3 x 64, from rocprofv3
 # counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, KiB -> bytes; the factors
-# make a plain 512 MiB device copy read and write 512 MiB). Valid only for the
-# kernel sources they were taken on: reported as null once those change.
+# make a plain 512 MiB device copy read and write 512 MiB). The fused x pass
+# is keyed by its tuned configuration (strip/g<groups>k<members>r<radix>, plain
+# grid). Valid only for the kernel sources they were taken on: reported as
+# null once those change.
 COUNTER_TRAFFIC = {
-    "sources_sha256": "148f02756871f781dd7e32fa34979225e1ffbf7debad30a9cddfc5d3cea9690b",
-    "bytes": {"bin": (182.1 * 2 + 4036.0) * 1024, "plane_fwd": (18570.1 * 2 + 537249.9) * 1024,
-              "strip": (395663.2 * 2 + 532480.0) * 1024, "plane_inv": (266319.8 * 2 + 525960.0) * 1024},
+    "sources_sha256": "ec54bf0276391c7141cc795f344571c02755d107ce882298022fd01d876b13e3",
+    "bytes": {"bin": (193.0 * 2 + 4164.0) * 1024, "plane_fwd": (18085.6 * 2 + 532823.4) * 1024,
+              "plane_inv": (266319.5 * 2 + 525984.1) * 1024,
+              "strip/g4k1r0": (486934.1 * 2 + 532480.0) * 1024,
+              "strip/g4k1r1": (487215.4 * 2 + 532480.0) * 1024,
+              "strip/g4k2r0": (396257.3 * 2 + 532480.0) * 1024,
+              "strip/g4k2r1": (396174.2 * 2 + 532480.0) * 1024,
+              "strip/g4k4r0": (329876.8 * 2 + 532480.0) * 1024,
+              "strip/g4k4r1": (329702.2 * 2 + 532480.0) * 1024,
+              "strip/g4k8r0": (296790.7 * 2 + 532480.0) * 1024,
+              "strip/g4k8r1": (296671.8 * 2 + 532480.0) * 1024,
+              "strip/g8k1r0": (531812.8 * 2 + 532480.0) * 1024,
+              "strip/g8k1r1": (531874.4 * 2 + 532480.0) * 1024,
+              "strip/g8k2r0": (399459.2 * 2 + 532480.0) * 1024,
+              "strip/g8k2r1": (399459.5 * 2 + 532480.0) * 1024,
+              "strip/g8k4r0": (332900.6 * 2 + 532480.0) * 1024,
+              "strip/g8k4r1": (332899.6 * 2 + 532480.0) * 1024,
+              "strip/g8k8r0": (299606.5 * 2 + 532480.0) * 1024,
+              "strip/g8k8r1": (299605.5 * 2 + 532480.0) * 1024},
 }
 # Wavefront VALU instructions per launch at 128^3 x 64 (rocprofv3
 # SQ_INSTS_VALU, same validity rule): against the issue rate of one VALU
 # instruction per CU per cycle they give each kernel's instruction-issue floor.
 COUNTER_VALU = {
-    "sources_sha256": "148f02756871f781dd7e32fa34979225e1ffbf7debad30a9cddfc5d3cea9690b",
-    "insts": {"plane_fwd": 110347150, "plane_inv": 58425344},
+    "sources_sha256": "ec54bf0276391c7141cc795f344571c02755d107ce882298022fd01d876b13e3",
+    "insts": {"bin": 359552, "plane_fwd": 62331895, "plane_inv": 58425344,
+              "strip/g4k1r0": 77675520,
+              "strip/g4k1r1": 76277760,
+              "strip/g4k2r0": 68556800,
+              "strip/g4k2r1": 67624960,
+              "strip/g4k4r0": 63914240,
+              "strip/g4k4r1": 63182080,
+              "strip/g4k8r0": 61543040,
+              "strip/g4k8r1": 60910720,
+              "strip/g8k1r0": 76876800,
+              "strip/g8k1r1": 75479040,
+              "strip/g8k2r0": 68224000,
+              "strip/g8k2r1": 67292160,
+              "strip/g8k4r0": 63747840,
+              "strip/g8k4r1": 63015680,
+              "strip/g8k8r0": 61459840,
+              "strip/g8k8r1": 60827520},
 }
 VALU_ISSUE_PER_S = 256 * 2.4e9  # CUs x clock: one wave64 VALU instruction per CU per cycle
 COPY_GBPS = 5390.0  # plain 512 MiB device copy, read + write (rocprofv3 calibration on the MI355X)
+# the field kernels and their launch shapes (the plan object lives elsewhere)
 KERNEL_SOURCES = ("ga_fft.hpp", "ga_kernels.hpp", "ga_launch.hpp")
 
 
@@ -63,9 +98,19 @@ def kernel_sources_sha256():
 
 
 def counter_traffic(kernel):
-    if COUNTER_TRAFFIC["sources_sha256"] != kernel_sources_sha256():
+    if COUNTER_TRAFFIC["sources_sha256"] != kernel_sources_sha256() or kernel not in COUNTER_TRAFFIC["bytes"]:
         return None
     return int(COUNTER_TRAFFIC["bytes"][kernel])
+
+
+def counter_key(kernel, tuned):
+    """The counter tables' key of a field kernel: the fused x pass by its
+    tuned (groups, members, xcd grid, radix); None for the XCD-aware grid,
+    which the tables do not hold."""
+    if kernel != "strip":
+        return kernel
+    g, k, x, r = tuned
+    return None if x == 1 else f"strip/g{g}k{k}r{r}"
 
 
 def valu_issue(kernel, ms):
@@ -580,6 +625,8 @@ def main():
     fields_per_s = batch * args.steps / wall
     abytes = algorithmic_bytes(n, batch, a.B.n)
     dom = max(kern, key=kern.get)
+    ckey = counter_key(dom, tuned)
+    traffic = counter_traffic(ckey) if ckey else None
     achieved = abytes[dom] / (kern[dom] * 1e-3) / 1e9
     step_bytes = sum(abytes.values())
     out = {
@@ -606,13 +653,13 @@ def main():
                      "xcd_aware_grid": tuned[2] == 1, "radix_schedule": tuned[3],
                      "candidates_us": {f"{'xcd' if x == 1 else 'plain'}/r{r}/{g}x{k}": v
                                        for (g, k, x, r), v in tune_us.items()}},
-        "roofline": {"bound": roofline_bound(dom, kern[dom], counter_traffic(dom)), "kernel": dom,
+        "roofline": {"bound": roofline_bound(ckey, kern[dom], traffic), "kernel": dom,
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": counter_traffic(dom),
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                      "algorithmic_bytes_per_launch": abytes[dom],
-                     "counted_GBps": (round(counter_traffic(dom) / (kern[dom] * 1e-3) / 1e9, 1)
-                                      if counter_traffic(dom) is not None else None),
-                     "valu_issue": valu_issue(dom, kern[dom]),
+                     "counted_GBps": (round(traffic / (kern[dom] * 1e-3) / 1e9, 1) if traffic is not None else None),
+                     "valu_issue": valu_issue(ckey, kern[dom]),
+                     "counters": ckey,
                      "timing": f"HIP events on the launch stream, {args.roofline_steps} one-stream steps of the "
                                f"same call after the timed region"},
     }

@@ -73,8 +73,8 @@ void launch_rotate(int n, MakeSrc make_src, const float* d_R, int32_t batch, flo
     const SrcT<N> src = make_src.template operator()<N>();
     if constexpr ((N / 2) % 8 == 0) {
       constexpr int tiles = (N / 8) * (N / 8) * ((N / 2 + 1 + 7) / 8);  // 8 x 8 x 8 outputs per workgroup
-      hipLaunchKernelGGL((k_spectral_rotate<N, SrcT<N>>), dim3(tiles, nb), block, 0, stream, src, d_R, (int)batch,
-                         out);
+      hipLaunchKernelGGL((k_spectral_rotate<N, SrcT<N>>), dim3(tiles, nb), dim3(SrcT<N>::THREADS), 0, stream, src, d_R,
+                         (int)batch, out);
     } else {
       constexpr int tiles = (N / 2) * (N / 8) * ((N / 2 + 1 + 15) / 16);  // 2 x 8 x 16 outputs per workgroup
       hipLaunchKernelGGL((k_spectral_rotate_gather<N, SrcT<N>>), dim3(tiles, nb), block, 0, stream, src, d_R,

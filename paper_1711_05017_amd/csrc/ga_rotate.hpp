@@ -62,7 +62,9 @@ constexpr unsigned kNoElem = 0xFFFFFF00u;
 template <int N>
 struct PlanarSrc {
   using V = float2;
-  static constexpr int MAX_PHASES = 4, REC = 8;
+  // phases, bytes per element, threads of the LDS rotation kernel (measured:
+  // 256 with 4 phases, 512 with the packed source's 2)
+  static constexpr int MAX_PHASES = 4, REC = 8, THREADS = 256;
   static constexpr size_t SPEC = (size_t)N * N * (N / 2 + 1);
   const float2* X;
   int nch;
@@ -84,7 +86,7 @@ struct PlanarSrc {
 template <int N>
 struct PackedSrc {
   using V = float4;
-  static constexpr int MAX_PHASES = 2, REC = 32;
+  static constexpr int MAX_PHASES = 2, REC = 32, THREADS = 512;
   static constexpr size_t SPEC = (size_t)N * N * (N / 2 + 1);
   const float4* P;
   __device__ int phases() const { return 2; }
@@ -176,10 +178,11 @@ __device__ __forceinline__ int xcd_tile(int bid, int tiles) {
 // moment channels rotated as a vector). The signed frequency of index N/2 is
 // -N/2 on every axis.
 //
-// A workgroup (256 threads) owns an 8 x 8 x 8 tile of outputs, two per
-// thread. Per rotation it bounds the tile's preimage R^T kappa (a rotated
-// cube) by an integer box of at most BOX per axis. Each thread locates its
-// box elements in the half spectrum once (element i = tid + 256 k; rows
+// A workgroup (Src::THREADS = 256 or 512 threads) owns an 8 x 8 x 8 tile of
+// outputs, two or one per thread. Per rotation it bounds the tile's preimage
+// R^T kappa (a rotated cube) by an integer box of at most BOX per axis. Each
+// thread locates its box elements in the half spectrum once (element
+// i = tid + THREADS k; rows
 // along kz, so reads are contiguous); per phase (a channel, or a channel pair
 // of the packed source) it loads them into registers with all loads in
 // flight, moves them to LDS, issues the next phase's loads and interpolates
@@ -189,14 +192,15 @@ __device__ __forceinline__ int xcd_tile(int bid, int tiles) {
 // reads them from global memory. Needs N/2 divisible by 8 (signed
 // frequencies contiguous in every tile). grid = (tiles, min(batch, 65535)).
 template <int N, class Src>
-__global__ void __launch_bounds__(256) k_spectral_rotate(Src src, const float* __restrict__ Rm, int batch,
-                                                         float2* __restrict__ out) {
+__global__ void __launch_bounds__(Src::THREADS) k_spectral_rotate(Src src, const float* __restrict__ Rm, int batch,
+                                                                  float2* __restrict__ out) {
   using V = typename Src::V;
   constexpr int PH = Src::MAX_PHASES;
   constexpr int HN = N / 2 + 1, T = 8, NT = N / T, NTZ = (HN + T - 1) / T;
   // box edge cap: the preimage of a tile spans at most floor(7 sqrt(3)) + 3 =
   // 15 lattice planes per axis, 14 or fewer for most rotations
-  constexpr int BOX = 14, BOXV = BOX * BOX * BOX, NV = (BOXV + 255) / 256;
+  constexpr int BOX = 14, BOXV = BOX * BOX * BOX, TH = Src::THREADS;
+  constexpr int NV = (BOXV + TH - 1) / TH, J = 512 / TH;
   constexpr size_t SPEC = (size_t)N * N * HN;
   static_assert((N / 2) % T == 0, "tiles must not straddle the sign change of the frequencies");
   static_assert(2 * SPEC * sizeof(float4) < kNoElem, "record offsets below kNoElem");
@@ -208,11 +212,11 @@ __global__ void __launch_bounds__(256) k_spectral_rotate(Src src, const float* _
   const int klo[3] = {signed_k(tx * T), signed_k(ty * T), signed_k(tz * T)};
   const int kz_last = min(tz * T + T - 1, HN - 1);
   const int khi[3] = {klo[0] + T - 1, klo[1] + T - 1, signed_k(tz * T) + (kz_last - tz * T)};
-  int kk[2][3];
-  bool valid[2];
+  int kk[J][3];
+  bool valid[J];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int o = tid + 256 * j;
+  for (int j = 0; j < J; ++j) {
+    const int o = tid + TH * j;
     kk[j][0] = tx * T + (o >> 6);
     kk[j][1] = ty * T + ((o >> 3) & 7);
     kk[j][2] = tz * T + (o & 7);
@@ -248,7 +252,7 @@ __global__ void __launch_bounds__(256) k_spectral_rotate(Src src, const float* _
     unsigned voff[NV], mir = 0;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-      const int i = tid + 256 * k;
+      const int i = tid + TH * k;
       voff[k] = kNoElem;
       if (i < etot) {
         // i < 14^3 < 2^16: (i + 1/2) / e rounds down to the exact quotient
@@ -270,10 +274,10 @@ __global__ void __launch_bounds__(256) k_spectral_rotate(Src src, const float* _
     load_phase(0);
     // per output: corner weights, lower corner, its LDS address when the
     // whole 2 x 2 x 2 cube lies in the box (else -1)
-    int i0[2][3], base[2];
-    float w[2][8];
+    int i0[J][3], base[J];
+    float w[J][8];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < J; ++j) {
       float a[3];
       rotate_frequency(R, signed_k(kk[j][0]), signed_k(kk[j][1]), signed_k(kk[j][2]), i0[j], a);
 #pragma unroll
@@ -285,7 +289,7 @@ __global__ void __launch_bounds__(256) k_spectral_rotate(Src src, const float* _
       base[j] = inside ? ux * eyz + uy * ez + uz : -1;
     }
     const int offs[8] = {0, 1, ez, ez + 1, eyz, eyz + 1, eyz + ez, eyz + ez + 1};
-    float2 acc[2][4];
+    float2 acc[J][4];
 #pragma unroll
     for (int ph = 0; ph < PH; ++ph) {
       if (ph >= nph) break;  // uniform
@@ -293,13 +297,13 @@ __global__ void __launch_bounds__(256) k_spectral_rotate(Src src, const float* _
       // slots from etot on are not part of this box: written, never read
 #pragma unroll
       for (int k = 0; k < NV; ++k) {
-        const int i = tid + 256 * k;
-        if (256 * (k + 1) <= BOXV || i < BOXV) box[i] = cur[k];
+        const int i = tid + TH * k;
+        if (TH * (k + 1) <= BOXV || i < BOXV) box[i] = cur[k];
       }
       __syncthreads();
       if (ph + 1 < nph) load_phase(ph + 1);  // in flight during this phase's interpolation
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < J; ++j) {
         if (!valid[j]) continue;
         V s = zero_value<V>();
         if (base[j] >= 0) {
@@ -315,7 +319,7 @@ __global__ void __launch_bounds__(256) k_spectral_rotate(Src src, const float* _
     }
     const int nch = (PH == 2) ? 4 : nph;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < J; ++j) {
       if (!valid[j]) continue;
       const size_t r = ((size_t)kk[j][0] * N + kk[j][1]) * HN + kk[j][2];
       store_rotated(out + (size_t)b * nch * SPEC + r, SPEC, nch, Rf, acc[j]);
