@@ -557,7 +557,7 @@ ga_status ga_profile_read(ga_plan* plan, int32_t kind, double* total_ms, int64_t
  *
  * Continuous batching: queries wait in a queue per grid size; a scheduler
  * thread moves up to max_slots of them into a free execution slot group
- * (two per grid size, each with its own stream) as soon as one is free, so
+ * (two per grid size, sharing the size's stream) as soon as one is free, so
  * queries that arrive while others run are admitted as slots free up and
  * the groups of different sizes run concurrently on the device. Every query
  * is computed independently of the others in its group: its result does not
@@ -572,12 +572,30 @@ typedef struct ga_server ga_server;
 #define GA_SERVE_LOCAL 0u    /* queries by ga_pose_local sums (resident u_A and grad u_A) */
 #define GA_SERVE_SPECTRAL 1u /* queries by splat, R2C and the GA_SINGLE partial sum (resident Ahat) */
 
+/*
+ * Test executor (for host-side tests of the scheduler, no device): with
+ * mock_fn set, the server schedules exactly as it does on the GPU (queues,
+ * launch groups, continuous batching, admission by budget and queue depth,
+ * the byte accounting of the device data it would hold, sticky errors) but
+ * holds no device memory and launches nothing: a launch group calls
+ * mock_fn(mock_user, pair_id, n, R, t, out7) for each of its queries on the
+ * scheduler thread (t: the lattice translation the kernels would use) and
+ * reports completion mock_launch_us microseconds after its launch. A
+ * nonzero return acts as a device error: the group fails and the server
+ * turns sticky (GA_EDEVICE). device is then not used. Null mock_fn: the GPU.
+ */
+typedef int32_t (*ga_mock_query_fn)(void* user, uint32_t pair_id, int32_t n, const float* R, const int32_t* t,
+                                    float* out7);
+
 typedef struct {
   int32_t device;            /* HIP device ordinal */
   uint64_t hbm_budget_bytes; /* device memory the server may hold */
   int32_t max_slots;         /* queries per launch group (1 .. 256) */
   int32_t queue_depth;       /* queued queries before ga_submit returns GA_EAGAIN */
   uint32_t mode;             /* GA_SERVE_LOCAL or GA_SERVE_SPECTRAL; both give the same values */
+  ga_mock_query_fn mock_fn;  /* test executor; null for the GPU */
+  void* mock_user;           /* passed to mock_fn */
+  uint32_t mock_launch_us;   /* simulated duration of one launch group */
 } ga_server_cfg;
 
 typedef struct {

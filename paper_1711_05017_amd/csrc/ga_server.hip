@@ -17,6 +17,9 @@
 // plane's share of the 7 sums against the pair's resident AX), the sum over
 // planes, one copy of the results to pinned host memory. Local mode:
 // k_local_query and the sum over sample blocks.
+// Test executor (ga_server_cfg.mock_fn): the same scheduling with no device
+// memory and no launches; a group's results come from the callback at
+// launch and its completion is reported mock_launch_us later.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -88,6 +91,11 @@ struct Group {
   std::vector<Pending> batch;
   uint64_t t_start = 0;
   bool busy = false;
+  // test executor: results computed at launch, reported at ready_ns
+  bool mock = false;
+  std::vector<float> mock_out;
+  uint64_t ready_ns = 0;
+  bool mock_failed = false;
 };
 
 struct SizeClass {
@@ -118,6 +126,10 @@ size_t group_bytes(uint32_t mode, int n, int slots, int64_t max_pts) {
 }
 
 void free_group(Group& g) {
+  if (g.mock) {
+    g = Group{};
+    return;
+  }
   if (g.stream) (void)hipStreamSynchronize(g.stream);
   if (g.h_items) (void)hipHostFree(g.h_items);
   if (g.h_out) (void)hipHostFree(g.h_out);
@@ -128,7 +140,12 @@ void free_group(Group& g) {
   g = Group{};
 }
 
-bool alloc_group(Group& g, hipStream_t stream, uint32_t mode, int n, int slots, int64_t max_pts) {
+bool alloc_group(Group& g, hipStream_t stream, uint32_t mode, int n, int slots, int64_t max_pts, bool mock) {
+  if (mock) {
+    g.mock = true;
+    g.mock_out.assign((size_t)slots * 7, 0.f);
+    return true;
+  }
   g.stream = stream;
   bool ok = hipEventCreateWithFlags(&g.done, hipEventDisableTiming) == hipSuccess &&
             hipHostMalloc((void**)&g.h_items, sizeof(QueryItem) * slots, hipHostMallocDefault) == hipSuccess &&
@@ -183,6 +200,11 @@ struct ga_server {
   bool stop = false;
   ga_status sticky = GA_OK;
   std::thread worker;
+  // test executor (ga_server_cfg.mock_fn)
+  ga_mock_query_fn mock_fn = nullptr;
+  void* mock_user = nullptr;
+  uint32_t mock_launch_us = 0;
+  bool mock() const { return mock_fn != nullptr; }
 
   SizeClass* find_class(int n, float sigma) {
     for (auto& c : classes)
@@ -191,7 +213,7 @@ struct ga_server {
   }
   void free_pair_locked(Pair& p) {
     for (void* q : {(void*)p.d_xyzr, (void*)p.d_w, (void*)p.d_AX, (void*)p.d_FA})
-      if (q) (void)hipFree(q);
+      if (q) (void)hipFree(q);  // all null under the test executor
     bytes -= p.bytes;
   }
   // After a sticky error nothing is launched any more: every queued query
@@ -213,6 +235,7 @@ struct ga_server {
   }
   void run();
   void launch(SizeClass& c, Group& g);
+  void launch_mock(SizeClass& c, Group& g);
   void harvest_locked(Group& g, bool ok, uint64_t t_done);
 };
 
@@ -270,6 +293,17 @@ void ga_server::launch(SizeClass& c, Group& g) {
   (void)hipEventRecord(g.done, g.stream);
 }
 
+// Test executor: the group's results from mock_fn now (scheduler thread,
+// server lock not held), its completion mock_launch_us later.
+void ga_server::launch_mock(SizeClass& c, Group& g) {
+  g.mock_failed = false;
+  for (size_t i = 0; i < g.batch.size(); ++i) {
+    const Pending& q = g.batch[i];
+    if (mock_fn(mock_user, q.pair, c.n, q.R, q.t, g.mock_out.data() + 7 * i) != 0) g.mock_failed = true;
+  }
+  g.ready_ns = g.t_start + (uint64_t)mock_launch_us * 1000u;
+}
+
 // Results of a finished group to its tickets; frees released pairs whose
 // last query this was (caller holds mu).
 void ga_server::harvest_locked(Group& g, bool ok, uint64_t t_done) {
@@ -278,7 +312,7 @@ void ga_server::harvest_locked(Group& g, bool ok, uint64_t t_done) {
     auto it = tickets.find(q.ticket);
     if (it != tickets.end() && ok) {
       ga_result& r = it->second.r;
-      const float* o = g.h_out + 7 * i;
+      const float* o = (g.mock ? g.mock_out.data() : g.h_out) + 7 * i;
       r.E = o[0];
       r.F[0] = o[1];
       r.F[1] = o[2];
@@ -304,7 +338,7 @@ void ga_server::harvest_locked(Group& g, bool ok, uint64_t t_done) {
 }
 
 void ga_server::run() {
-  (void)hipSetDevice(device);
+  if (!mock()) (void)hipSetDevice(device);
   (void)prctl(PR_SET_TIMERSLACK, 1000UL);  // 1 us: the short waits below stay short
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
@@ -315,6 +349,14 @@ void ga_server::run() {
       for (int gi = 0; gi < cp->ngroups; ++gi) {
         Group& g = cp->groups[gi];
         if (!g.busy) continue;
+        if (g.mock) {
+          const uint64_t t = now_ns();
+          if (t < g.ready_ns) continue;
+          if (g.mock_failed) sticky = GA_EDEVICE;
+          harvest_locked(g, !g.mock_failed, t);
+          progress = true;
+          continue;
+        }
         const hipError_t e = hipEventQuery(g.done);
         if (e == hipErrorNotReady) continue;
         if (e != hipSuccess) sticky = GA_EDEVICE;
@@ -332,7 +374,7 @@ void ga_server::run() {
         g.batch.assign(c.queue.begin(), c.queue.begin() + k);
         c.queue.erase(c.queue.begin(), c.queue.begin() + k);
         queued -= k;
-        fill_items(this, c, g);
+        if (!g.mock) fill_items(this, c, g);
         g.busy = true;
         g.t_start = now_ns();
         ++busy_groups;
@@ -342,7 +384,10 @@ void ga_server::run() {
     }
     if (!to_launch.empty()) {
       lk.unlock();
-      for (auto& [c, g] : to_launch) launch(*c, *g);
+      for (auto& [c, g] : to_launch) {
+        if (g->mock) launch_mock(*c, *g);
+        else launch(*c, *g);
+      }
       lk.lock();
       continue;
     }
@@ -363,10 +408,15 @@ ga_status ga_server_create(ga_server** server, const ga_server_cfg* cfg) {
   if (cfg->max_slots < 1 || cfg->max_slots > 256 || cfg->queue_depth < 1 || cfg->hbm_budget_bytes == 0 ||
       (cfg->mode != GA_SERVE_LOCAL && cfg->mode != GA_SERVE_SPECTRAL))
     return GA_EINVAL;
-  int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) return GA_EINVAL;
+  if (!cfg->mock_fn) {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) return GA_EINVAL;
+  }
   ga_server* s = new (std::nothrow) ga_server();
   if (!s) return GA_ENOMEM;
+  s->mock_fn = cfg->mock_fn;
+  s->mock_user = cfg->mock_user;
+  s->mock_launch_us = cfg->mock_launch_us;
   s->device = cfg->device;
   s->mode = cfg->mode;
   s->budget = cfg->hbm_budget_bytes;
@@ -385,7 +435,7 @@ ga_status ga_server_destroy(ga_server* s) {
   }
   s->cv.notify_all();
   s->worker.join();
-  (void)hipSetDevice(s->device);
+  if (!s->mock()) (void)hipSetDevice(s->device);
   for (auto& cp : s->classes) {
     for (int gi = 0; gi < cp->ngroups; ++gi) free_group(cp->groups[gi]);
     if (cp->stream) (void)hipStreamDestroy(cp->stream);
@@ -402,7 +452,8 @@ ga_status ga_pair_register(ga_server* s, const ga_part* A, const ga_part* B, con
   if (!plane_edge(n)) return GA_EUNSUPPORTED;  // served sizes use the plane path
   if (!host_part_ok(A, n, true) || !host_part_ok(B, n, false)) return GA_EINVAL;
   if (!(std::isfinite(cB[0]) && std::isfinite(cB[1]) && std::isfinite(cB[2]))) return GA_EINVAL;
-  if (hipSetDevice(s->device) != hipSuccess) return GA_EDEVICE;
+  const bool mock = s->mock();
+  if (!mock && hipSetDevice(s->device) != hipSuccess) return GA_EDEVICE;
   const size_t spec_bytes = spectrum_elems(n) * sizeof(float2);
   const size_t n3 = (size_t)n * n * n;
   const size_t pair_bytes = (size_t)B->n_pts * 5 * sizeof(float) + (s->mode == GA_SERVE_LOCAL ? 16 * n3 : 2 * spec_bytes);
@@ -423,16 +474,18 @@ ga_status ga_pair_register(ga_server* s, const ga_part* A, const ga_part* B, con
         else if (ngroups > 1) ngroups = 1;
         else return GA_ENOMEM;
       }
-      if (ga_plan_create(&nc->plan, n, slots, 0) != GA_OK) return GA_EDEVICE;
-      if (hipStreamCreateWithFlags(&nc->stream, hipStreamNonBlocking) != hipSuccess) {
-        ga_plan_destroy(nc->plan);
-        return GA_EDEVICE;
+      if (!mock) {
+        if (ga_plan_create(&nc->plan, n, slots, 0) != GA_OK) return GA_EDEVICE;
+        if (hipStreamCreateWithFlags(&nc->stream, hipStreamNonBlocking) != hipSuccess) {
+          ga_plan_destroy(nc->plan);
+          return GA_EDEVICE;
+        }
       }
       for (int gi = 0; gi < ngroups; ++gi)
-        if (!alloc_group(nc->groups[gi], nc->stream, s->mode, n, slots, nc->max_pts)) {
+        if (!alloc_group(nc->groups[gi], nc->stream, s->mode, n, slots, nc->max_pts, mock)) {
           for (int gj = 0; gj < gi; ++gj) free_group(nc->groups[gj]);
-          (void)hipStreamDestroy(nc->stream);
-          ga_plan_destroy(nc->plan);
+          if (nc->stream) (void)hipStreamDestroy(nc->stream);
+          if (nc->plan) ga_plan_destroy(nc->plan);
           return GA_ENOMEM;
         }
       nc->slots = slots;
@@ -460,7 +513,7 @@ ga_status ga_pair_register(ga_server* s, const ga_part* A, const ga_part* B, con
       bool ok = !(fail && fail[0] == '1');
       for (int gi = 0; gi < c->ngroups; ++gi) {
         free_group(c->groups[gi]);
-        ok = ok && alloc_group(c->groups[gi], c->stream, s->mode, n, c->slots, B->n_pts);
+        ok = ok && alloc_group(c->groups[gi], c->stream, s->mode, n, c->slots, B->n_pts, mock);
       }
       if (!ok) {
         s->sticky = GA_ENOMEM;
@@ -482,6 +535,14 @@ ga_status ga_pair_register(ga_server* s, const ga_part* A, const ga_part* B, con
   std::memcpy(p.cB, cB, sizeof(p.cB));
   p.n_pts = B->n_pts;
   p.bytes = pair_bytes;
+  if (mock) {  // nothing resident: the test executor computes from the pair id
+    std::lock_guard<std::mutex> lk(s->mu);
+    p.id = s->next_pair++;
+    s->pairs[p.id] = p;
+    s->stats.pairs = (int32_t)s->pairs.size();
+    *pair_id = p.id;
+    return GA_OK;
+  }
   float* dA = nullptr;
   float* dAw = nullptr;
   hipStream_t st = nullptr;

@@ -46,9 +46,15 @@ KERNEL_KINDS = {"splat": 0, "plane_fwd": 1, "strip": 2, "plane_inv": 3, "readout
 _vp = ctypes.c_void_p
 
 
+MockQueryFn = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int32,
+                               ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int32),
+                               ctypes.POINTER(ctypes.c_float))
+
+
 class ServerCfg(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int32),
-                ("queue_depth", ctypes.c_int32), ("mode", ctypes.c_uint32)]
+                ("queue_depth", ctypes.c_int32), ("mode", ctypes.c_uint32), ("mock_fn", MockQueryFn),
+                ("mock_user", ctypes.c_void_p), ("mock_launch_us", ctypes.c_uint32)]
 
 
 class PartDesc(ctypes.Structure):
@@ -707,9 +713,24 @@ class Server:
     query is evaluated (GA_SERVE_LOCAL or GA_SERVE_SPECTRAL, same values)."""
 
     def __init__(self, device: int = 0, hbm_budget_bytes: int = 8 << 30, max_slots: int = 8, queue_depth: int = 4096,
-                 mode: int = GA_SERVE_LOCAL):
+                 mode: int = GA_SERVE_LOCAL, mock=None, mock_launch_us: int = 0):
+        """mock: a test executor, called as mock(pair_id, n, R (9 floats),
+        t (3 ints)) -> 7 floats on the server's scheduler thread (an
+        exception acts as a device error); the server then uses no device."""
         lib = load()
-        cfg = ServerCfg(device, hbm_budget_bytes, max_slots, queue_depth, mode)
+        self._mock = None
+        if mock is not None:
+            def call(user, pair_id, n, R, t, out7):
+                try:
+                    vals = mock(int(pair_id), int(n), [R[i] for i in range(9)], [t[i] for i in range(3)])
+                    for i in range(7):
+                        out7[i] = float(vals[i])
+                    return 0
+                except Exception:
+                    return 1
+            self._mock = MockQueryFn(call)
+        cfg = ServerCfg(device, hbm_budget_bytes, max_slots, queue_depth, mode,
+                        self._mock if self._mock is not None else MockQueryFn(), None, int(mock_launch_us))
         h = ctypes.c_void_p()
         _check("ga_server_create", lib.ga_server_create(ctypes.byref(h), ctypes.byref(cfg)))
         self._h = h
