@@ -198,8 +198,29 @@ template <int N, class SH> constexpr int tw_off(int s) {
 template <int N, class SH> constexpr int tw_count() { return tw_off<N, SH>(SH::NST); }
 
 template <int N, class SH = Shape<N>> struct Twiddles {
+  using Sched = SH;
   float2 v[tw_count<N, SH>()];
 };
+
+// The same twiddles read from a table tab[m] = exp(-2 pi i m / N), m < N
+// (typically in LDS), for kernels whose registers cannot hold them.
+template <int N, class SH = Shape<N>> struct TwiddlesTab {
+  using Sched = SH;
+  const float2* tab;
+};
+
+// Twiddle r of butterfly b at stage S for transform lane `lane`.
+template <int N, int S, class SH>
+__device__ __forceinline__ float2 tw_at(const Twiddles<N, SH>& tw, int lane, int b, int r) {
+  (void)lane;
+  return tw.v[tw_off<N, SH>(S) + b * (SH::R[S] - 1) + r - 1];
+}
+template <int N, int S, class SH>
+__device__ __forceinline__ float2 tw_at(const TwiddlesTab<N, SH>& tw, int lane, int b, int r) {
+  constexpr int L = N / SH::E, R = SH::R[S], NS = ns_before<N, SH>(S);
+  const int k = (lane + L * b) % NS;
+  return tw.tab[r * k * (N / (NS * R))];
+}
 
 // Per-lane twiddles: stage s > 0, butterfly b, element r uses
 // exp(-2 pi i r k / (NS R)) with k = j mod NS, j = lane + L b.
@@ -229,8 +250,9 @@ __device__ __forceinline__ void load_twiddles(Twiddles<N, SH>& tw, const float2*
 // bank conflicts). Stage 0 takes its inputs from ld(pos) and the last stage
 // hands its outputs to st(pos, v); positions are natural indices. The
 // schedule SH comes with the twiddles.
-template <int N, int S, int DIR, class SH, class At, class Ld, class St>
-__device__ __forceinline__ void fft_stage(int lane, const Twiddles<N, SH>& tw, At& at, Ld& ld, St& st) {
+template <int N, int S, int DIR, class TW, class At, class Ld, class St>
+__device__ __forceinline__ void fft_stage(int lane, const TW& tw, At& at, Ld& ld, St& st) {
+  using SH = typename TW::Sched;
   constexpr int E = SH::E, L = N / E, R = SH::R[S], NS = ns_before<N, SH>(S), NB = E / R;
   constexpr bool first = (S == 0), last = (S == SH::NST - 1);
   float2 v[E];
@@ -249,7 +271,7 @@ __device__ __forceinline__ void fft_stage(int lane, const Twiddles<N, SH>& tw, A
   for (int b = 0; b < NB; ++b) {
     if constexpr (S > 0) {
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[b * R + r] = twmul<DIR>(v[b * R + r], tw.v[tw_off<N, SH>(S) + b * (R - 1) + r - 1]);
+      for (int r = 1; r < R; ++r) v[b * R + r] = twmul<DIR>(v[b * R + r], tw_at<N, S>(tw, lane, b, r));
     }
     Bfly<R, DIR>::run(&v[b * R]);
   }
@@ -271,25 +293,25 @@ __device__ __forceinline__ void fft_stage(int lane, const Twiddles<N, SH>& tw, A
 
 // Transform of length N on the L lanes [0, L) of this transform (`lane` is
 // the index within the transform), element pos at at(pos).
-template <int N, int DIR, class SH, class At, class Ld, class St>
-__device__ __forceinline__ void fft_at(int lane, const Twiddles<N, SH>& tw, At at, Ld ld, St st) {
+template <int N, int DIR, class TW, class At, class Ld, class St>
+__device__ __forceinline__ void fft_at(int lane, const TW& tw, At at, Ld ld, St st) {
   fft_stage<N, 0, DIR>(lane, tw, at, ld, st);
 }
-template <int N, int DIR, class SH, class At>
-__device__ __forceinline__ void fft_inplace_at(int lane, const Twiddles<N, SH>& tw, At at) {
+template <int N, int DIR, class TW, class At>
+__device__ __forceinline__ void fft_inplace_at(int lane, const TW& tw, At at) {
   auto ld = [&](int pos) { return *at(pos); };
   auto st = [&](int pos, float2 v) { *at(pos) = v; };
   fft_stage<N, 0, DIR>(lane, tw, at, ld, st);
 }
 
 // The same with data in buf[pos * es].
-template <int N, int DIR, class SH, class Ld, class St>
-__device__ __forceinline__ void fft_lanes(int lane, const Twiddles<N, SH>& tw, float2* buf, int es, Ld ld, St st) {
+template <int N, int DIR, class TW, class Ld, class St>
+__device__ __forceinline__ void fft_lanes(int lane, const TW& tw, float2* buf, int es, Ld ld, St st) {
   auto at = [=](int pos) { return buf + pos * es; };
   fft_stage<N, 0, DIR>(lane, tw, at, ld, st);
 }
-template <int N, int DIR, class SH>
-__device__ __forceinline__ void fft_inplace(int lane, const Twiddles<N, SH>& tw, float2* buf, int es) {
+template <int N, int DIR, class TW>
+__device__ __forceinline__ void fft_inplace(int lane, const TW& tw, float2* buf, int es) {
   auto at = [=](int pos) { return buf + pos * es; };
   fft_inplace_at<N, DIR>(lane, tw, at);
 }

@@ -78,12 +78,32 @@ template <int N, bool INV = false> struct Plane {
   __device__ __forceinline__ static int zs(int t, int p) { return t * PAIR + (p ^ ((p >> Z::ZS) & Z::ZM)); }
   static constexpr int L = lanes_per_fft<N>();
   static constexpr int TPW = ffts_per_wave<N>();
-  static constexpr int WAVES = (N >= 128) ? 8 : 4;
+  // 192: 12 waves, one round of the 96 row-pair and column transforms (the
+  // plane's 149 KB of LDS admits one workgroup per CU; its twiddles are read
+  // from an LDS table so that 12 waves fit the register file)
+  static constexpr int WAVES = (N == 192) ? 12 : (N >= 128) ? 8 : 4;
   static constexpr int THREADS = 64 * WAVES;
   // waves per SIMD the register budget must allow: two 8-wave workgroups per
   // CU at n = 128 (the plane's LDS admits two)
   static constexpr int MINW = (N == 128) ? 4 : 1;
 };
+
+// Twiddles of the generic plane kernels: in registers, or (192) read from a
+// table the workgroup copies to LDS (plane_twiddles).
+template <int N> constexpr bool kPlaneTwTab = (N == 192);
+template <int N> using PlaneTw = std::conditional_t<kPlaneTwTab<N>, TwiddlesTab<N>, Twiddles<N>>;
+// Sets up the twiddles of transform lane `l`: registers from the table, or
+// the LDS copy tab[N] (filled by the whole workgroup; the caller's next
+// workgroup barrier orders it before the first transform).
+template <int N>
+__device__ __forceinline__ void plane_twiddles(PlaneTw<N>& tw, const float2* __restrict__ table, float2* tab, int l) {
+  if constexpr (kPlaneTwTab<N>) {
+    for (int i = threadIdx.x; i < N; i += blockDim.x) tab[i] = table[i];
+    tw.tab = tab;
+  } else {
+    load_twiddles<N>(tw, table, l);
+  }
+}
 
 constexpr int kChunk = 256;  // records examined per round; bounds the LDS hit list
 
@@ -463,9 +483,9 @@ __device__ void splat_plane(const SplatParams& p, const double* R, int b, int x,
 // and written after. DIRECT = false: the spectrum stays in W (layout
 // yc) and dst0, dst1 are not used; the caller copies it out (edges whose
 // transforms leave no registers for the direct stores).
-template <int N, bool DIRECT>
-__device__ void plane_forward_out(float2* W, const Twiddles<N>& tw, float2* __restrict__ dst0,
-                                  float2* __restrict__ dst1, float s1) {
+template <int N, bool DIRECT, class TW>
+__device__ __forceinline__ void plane_forward_out(float2* W, const TW& tw, float2* __restrict__ dst0,
+                                                  float2* __restrict__ dst1, float s1) {
   using P = Plane<N>;
   constexpr int L = P::L, TPW = P::TPW, H = P::H;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -718,9 +738,12 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_fwd
                                                                                const float2* __restrict__ table) {
   using P = Plane<N>;
   __shared__ __attribute__((aligned(16))) float2 W[P::SIZE];
+  __shared__ float2 tw_tab[kPlaneTwTab<N> ? N : 1];
   const int x = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
   float* Wf = reinterpret_cast<float*>(W);
   const size_t plane_sz = (size_t)N * P::H;
+  PlaneTw<N> tw;
+  plane_twiddles<N>(tw, table, tw_tab, (tid & 63) % P::L);
   // the y transforms store the spectrum straight to global memory up to
   // edge 128; the 192 transforms need their registers (copy-out from LDS)
   constexpr bool kDirect = N <= 128;
@@ -762,11 +785,7 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_fwd
     }
   }
   __syncthreads();
-  {
-    Twiddles<N> tw;
-    load_twiddles<N>(tw, table, (tid & 63) % P::L);
-    plane_forward_out<N, kDirect>(W, tw, dst0, nullptr, 1.0f);
-  }
+  plane_forward_out<N, kDirect>(W, tw, dst0, nullptr, 1.0f);
   if constexpr (!kDirect) plane_to_global<N>(dst0, W, 1.0f);
 }
 
@@ -1176,8 +1195,9 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_sin
   const size_t plane_sz = (size_t)N * H;
   const float2* AXp = it.AX + (size_t)((x + it.t[0]) % N) * plane_sz;
   const int ty = it.t[1], tz = it.t[2];
-  Twiddles<N> tw;  // first: their loads overlap the splat
-  load_twiddles<N>(tw, table, (tid & 63) % P::L);
+  __shared__ float2 tw_tab[kPlaneTwTab<N> ? N : 1];
+  PlaneTw<N> tw;  // first: their loads overlap the splat
+  plane_twiddles<N>(tw, table, tw_tab, (tid & 63) % P::L);
   for (int i = tid; i < N; i += P::THREADS) tabc[i] = make_float2(table[i].x, -table[i].y);
   // splat: as the binned branch of k_plane_fwd
   const int4 rg = p.cand[(size_t)b * N + x];
@@ -1306,9 +1326,10 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_inv
   __shared__ __attribute__((aligned(16))) float2 W[P::SIZE];
   const int x = blockIdx.x, b = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l = lane % L;
+  __shared__ float2 tw_tab[kPlaneTwTab<N> ? N : 1];
   plane_from_global<N>(W, in + ((size_t)b * N + x) * (size_t)N * H);
-  Twiddles<N> tw;
-  load_twiddles<N>(tw, table, l);
+  PlaneTw<N> tw;
+  plane_twiddles<N>(tw, table, tw_tab, l);
   __syncthreads();
   // y: columns 1 .. N/2-1 in place. The z C2R below keeps only the real part
   // of columns kz = 0 and kz = N/2, so both go through one transform of
