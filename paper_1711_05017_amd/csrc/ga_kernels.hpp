@@ -80,8 +80,11 @@ template <int N, bool INV = false> struct Plane {
   static constexpr int TPW = ffts_per_wave<N>();
   // 192: 12 waves, one round of the 96 row-pair and column transforms (the
   // plane's 149 KB of LDS admits one workgroup per CU; its twiddles are read
-  // from an LDS table so that 12 waves fit the register file)
-  static constexpr int WAVES = (N == 192) ? 12 : (N >= 128) ? 8 : 4;
+  // from an LDS table so that 12 waves fit the register file). 64: 8 waves
+  // (the splat's hits spread over more waves: pass 1 8% and a single query's
+  // fused pass 28% faster than with 4). 96 keeps 4 (its inverse pass and
+  // batched single-pose launches measured slower with 8).
+  static constexpr int WAVES = (N == 192) ? 12 : (N == 128 || N == 64) ? 8 : 4;
   static constexpr int THREADS = 64 * WAVES;
   // waves per SIMD the register budget must allow: two 8-wave workgroups per
   // CU at n = 128 (the plane's LDS admits two)
