@@ -533,7 +533,7 @@ def main():
                          "kernel that scales the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the field path would shard by rotation "
+        print(json.dumps({"error": "the benchmark and library run on one GPU only; the field path would shard by rotation "
                                    "(independent fields) or by x-slab with two all-to-alls, not implemented"}))
         sys.exit(2)
 

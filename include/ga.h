@@ -81,7 +81,7 @@ typedef int32_t ga_status;
 #define GA_EAGAIN (-3)      /* queue full, try again */
 #define GA_EDEVICE (-4)     /* HIP runtime or launch error */
 #define GA_ENOTFOUND (-5)   /* unknown ticket or pair */
-#define GA_EUNSUPPORTED (-6) /* grid edge not supported by this build */
+#define GA_EUNSUPPORTED (-6) /* grid edge not compiled into the library */
 
 /* Transform directions for ga_fft3d. */
 #define GA_R2C (-1)
@@ -113,7 +113,7 @@ const char* ga_status_str(ga_status s);
 /* Library version string (static storage). */
 const char* ga_version(void);
 
-/* Whether grid edge n is supported by this build (1) or not (0). */
+/* Whether grid edge n is compiled into the library (1) or not (0). */
 int32_t ga_supported_n(int32_t n);
 
 /*

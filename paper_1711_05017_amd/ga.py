@@ -166,7 +166,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
-        raise RuntimeError(f"libga.so not found at {path}: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+        raise RuntimeError(f"libga.so not found at {path}: build it first (python -m paper_1711_05017_amd._build)")
     lib = ctypes.CDLL(path)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)
