@@ -667,7 +667,10 @@ __device__ __forceinline__ bool wave_hit(const SplatParams& p, const Placed& q, 
   h.w = __int_as_float(q.b.w);
   const float rho = q.a.w;
   if (!(fabsf(dx) < rho) || h.w == 0.0f) return false;
-  const float rd = sqrtf(fmaxf(rho * rho - dx * dx, 0.0f));
+  // disk radius from the hardware square root (within an ulp), widened by
+  // 2^-20 so that the square never misses a voxel of the disk: voxels it
+  // adds fail the d < rho test of the splat
+  const float rd = __builtin_amdgcn_sqrtf(fmaxf(rho * rho - dx * dx, 0.0f)) * (1.0f + 0x1p-20f);
   const int ylo = (int)ceilf(q.a.y - rd), yhi = (int)floorf(q.a.y + rd);
   const int zlo = (int)ceilf(q.a.z - rd), zhi = (int)floorf(q.a.z + rd);
   const int sy = yhi - ylo + 1, sz = zhi - zlo + 1;
@@ -678,52 +681,176 @@ __device__ __forceinline__ bool wave_hit(const SplatParams& p, const Placed& q, 
   h.offy = (float)ylo - q.a.y;
   h.offz = (float)zlo - q.a.z;
   h.dx2 = dx * dx;
-  h.c2s = p.sig_c / (rho * rho);
+  h.c2s = p.sig_c * __builtin_amdgcn_rcpf(rho * rho);  // within an ulp or so: moves K(d) by ~1e-7 at most
   return true;
 }
 
-// Splat of the hits one wavefront found (flag `hit`, parameters `h` in each
-// lane): the wave takes them one at a time, broadcast from their lanes, and
-// its 64 lanes cover 8 x 8 blocks of the hit's bounding square (lane = row
-// offset lane / 8, column offset lane % 8), adding w K(d) (times yhat_y or
-// yhat_z for channel 2 or 3) with LDS float atomics at Wf[idx(y, z)]. The
-// lanes of one atomic instruction never share an address, and no search or
-// workgroup barrier is involved.
 template <int N>
 __device__ __forceinline__ int wrap_axis(int v) {  // v in [-N, 2N)
   if constexpr ((N & (N - 1)) == 0) return v & (N - 1);
   else return wrapn(v, N);
 }
-template <int N, class Idx>
-__device__ __forceinline__ void wave_splat(const SplatParams& p, bool hit, const WaveHit& h, int chan, float* Wf,
-                                           Idx idx) {
-  const int lane = threadIdx.x & 63, ly = lane >> 3, lz = lane & 7;
-  const float fly = (float)ly, flz = (float)lz;
-  unsigned long long mask = __ballot(hit);
-  while (mask) {
-    const int i = __ffsll(mask) - 1;
-    mask &= mask - 1;
-    const int yb = __builtin_amdgcn_readlane(h.ybase, i), zb = __builtin_amdgcn_readlane(h.zbase, i);
-    const int syz = __builtin_amdgcn_readlane(h.syz, i);
-    const int sy = syz & 0xffff, sz = syz >> 16;
-    const float oy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h.offy), i));
-    const float oz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h.offz), i));
-    const float d2x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h.dx2), i));
-    const float cs = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h.c2s), i));
-    const float wk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h.w), i)) * p.inv1me0;
-    for (int by0 = 0; by0 < sy; by0 += 8) {
-      const float dy = fly + (oy + (float)by0);
-      const float dyy = fmaf(dy, dy, d2x);
-      const bool rowok = ly + by0 < sy;
-      for (int bz0 = 0; bz0 < sz; bz0 += 8) {
-        const float dz = flz + (oz + (float)bz0);
-        const float e = fmaf(dz, dz, dyy) * cs;  // d^2 / (2 s^2)
-        if (rowok && lz + bz0 < sz && e < p.sig_c) {  // inside the square and d < rho
-          const int yy = wrap_axis<N>(yb + by0 + ly), zz = wrap_axis<N>(zb + bz0 + lz);
-          float val = wk * (__expf(-e) - p.e0);
-          if (chan == 2) val *= yhat(yy, N);
-          if (chan == 3) val *= yhat(zz, N);
-          atomicAdd(&Wf[idx(yy, zz)], val);
+
+// Number of set bits of m below this lane.
+__device__ __forceinline__ int lanes_below(unsigned long long m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+// Inclusive prefix sum over the 64 lanes of a wavefront (all lanes active):
+// within each row of 16 lanes by DPP row shifts (lanes shifted in from
+// outside the row read 0), then the totals of the rows below added.
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);  // row_shr:8
+  const int t0 = __builtin_amdgcn_readlane(v, 15), t1 = __builtin_amdgcn_readlane(v, 31);
+  const int t2 = __builtin_amdgcn_readlane(v, 47);
+  const int row = (int)(threadIdx.x & 63) >> 4;
+  return v + (row >= 1 ? t0 : 0) + (row >= 2 ? t1 : 0) + (row >= 3 ? t2 : 0);
+}
+
+// The splat sums in LDS are fixed point: LDS float atomics complete at a
+// small fraction of the rate of integer ones on this hardware, so each value
+// is scaled by a power of two S, rounded to an integer and added with an
+// integer atomic (exact and order-independent), and the plane is converted
+// back (times 1/S) before its transforms. S comes from a bound on the
+// magnitude of any voxel's sum in the plane: each sample adds at most |w|
+// (times |yhat| <= N/2 for the channel multipliers) to a voxel, and a plane
+// receives only its candidates, so sum |w| over the candidates bounds it.
+// With bound * S < 2^30 no sum overflows and each add is rounded to
+// bound * 2^-30 at most, a relative error of the order of float32's for the
+// sums of a plane.
+struct PlaneBound {
+  float wsum;  // sum of |w| over the plane's candidates
+  bool any;    // some candidate of the first round hits the plane
+};
+
+// All threads of the workgroup: w0 = |w| of this thread's first-round
+// candidate (0 if none), hit = its hit flag; candidates beyond the first
+// round (64 WAVES) are read here. red: 2 WAVES floats of LDS. Ends with a
+// workgroup barrier.
+template <int WAVES, int THREADS>
+__device__ __forceinline__ PlaneBound plane_bound(const Placed* rb, int4 rg, int ncand, float w0, bool hit,
+                                                  float* red) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  float sum = w0;
+  for (int c = 64 * WAVES + tid; c < ncand; c += THREADS)
+    sum += fabsf(__int_as_float(rb[c < rg.y ? rg.x + c : rg.z + (c - rg.y)].b.w));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+  const bool wany = __ballot(hit) != 0;
+  if (lane == 0) {
+    red[wave] = sum;
+    red[WAVES + wave] = wany ? 1.f : 0.f;
+  }
+  __syncthreads();
+  PlaneBound r{0.f, false};
+#pragma unroll
+  for (int i = 0; i < WAVES; ++i) {
+    r.wsum += red[i];
+    r.any = r.any || red[WAVES + i] != 0.f;
+  }
+  return r;
+}
+
+// Power of two S with bound * S < 2^30 (bound >= 0; exponent clamped).
+__device__ __forceinline__ float splat_scale(float bound) {
+  int e = (bound > 0.f) ? __builtin_amdgcn_frexp_expf(bound) - 1 : 0;  // floor(log2 bound)
+  e = min(max(e, -96), 96);
+  return ldexpf(1.0f, 29 - e);
+}
+
+// Integer sums of a plane back to float: n4 int4 of W, times inv_s, each
+// element by the thread that reads it (no barrier inside).
+template <int THREADS>
+__device__ __forceinline__ void plane_fix_to_float(float2* W, int n4, float inv_s) {
+  float4* W4 = reinterpret_cast<float4*>(W);
+  const int4* I4 = reinterpret_cast<const int4*>(W);
+  for (int i = threadIdx.x; i < n4; i += THREADS) {
+    const int4 v = I4[i];
+    W4[i] = make_float4((float)v.x * inv_s, (float)v.y * inv_s, (float)v.z * inv_s, (float)v.w * inv_s);
+  }
+}
+
+// Hits one wavefront splats at a time, by plane edge (LDS per wave:
+// 32 bytes a hit and 64 bytes of start flags).
+template <int N>
+constexpr int kSplatCap = (N > 128) ? 16 : 32;
+
+// Per-wavefront LDS of the splat below: a batch of hits, compacted, and one
+// flag byte per lane marking where a hit's first row falls.
+template <int CAP>
+struct WaveSplatLds {
+  int4 hi[CAP];    // (ybase | zbase << 16, sz | first row << 8, offy bits, offz bits)
+  float4 hf[CAP];  // (dx^2, 1/(2 s^2), S w / (1 - e0), unused)
+  int flag[16];
+};
+
+// Splat of the hits one wavefront found (flag `hit`, parameters `h` in each
+// lane), adding w K(d) (times yhat_y or yhat_z for channel 2 or 3) in fixed
+// point, times S (splat_scale), with LDS integer atomics at Wf[idx(y, z)]. The rows of the hits' bounding squares are
+// enumerated as one sequence (hit by hit in lane order) and each lane takes
+// one row, 64 consecutive rows per step, walking the row's sz voxels: a
+// small disk does not leave lanes idle as a one-hit-per-step layout would.
+// A batch of up to CAP hits is compacted into the wave's LDS with the index
+// of its first row (a prefix sum over the wave); each step flags the lanes
+// at which a hit's rows start, and the hit of a lane is the number of starts
+// at or below it (a ballot and a masked bit count) plus those of earlier
+// steps. No search and no workgroup barrier is involved.
+template <int N, int CAP, class Idx>
+__device__ __forceinline__ void wave_splat(const SplatParams& p, bool hit, const WaveHit& h, int chan, float S,
+                                           float* Wf, Idx idx, WaveSplatLds<CAP>& ws) {
+  static_assert(N < 256 && CAP * N < (1 << 23), "packed square sizes and starts");
+  const int lane = threadIdx.x & 63;
+  const unsigned long long hm = __ballot(hit);
+  const int nh = __popcll(hm);  // uniform
+  const int rank = lanes_below(hm);
+  const int sy = h.syz & 0xffff, sz = h.syz >> 16;
+  unsigned char* flag8 = reinterpret_cast<unsigned char*>(ws.flag);
+  for (int r0 = 0; r0 < nh; r0 += CAP) {
+    const bool mine = hit && rank >= r0 && rank < r0 + CAP;
+    const int cnt = mine ? sy : 0;
+    const int incl = wave_incl_scan(cnt);
+    const int total = __builtin_amdgcn_readlane(incl, 63);
+    const int start = incl - cnt;
+    wave_sync();  // the previous batch's reads of ws are done
+    if (mine) {
+      ws.hi[rank - r0] = make_int4((h.ybase & 0xffff) | (h.zbase << 16), sz | (start << 8), __float_as_int(h.offy),
+                                   __float_as_int(h.offz));
+      ws.hf[rank - r0] = make_float4(h.dx2, h.c2s, h.w * p.inv1me0 * S, 0.f);
+    }
+    int before = 0;  // hits whose rows start before this step's first row
+    for (int base = 0; base < total; base += 64) {
+      wave_sync();
+      if (lane < 16) ws.flag[lane] = 0;
+      wave_sync();
+      if (mine && start >= base && start < base + 64) flag8[start - base] = 1;
+      wave_sync();
+      const bool f = flag8[lane] != 0;
+      const unsigned long long fm = __ballot(f);
+      const int j = before + lanes_below(fm) + (f ? 1 : 0) - 1;
+      before += __popcll(fm);
+      if (base + lane < total) {
+        const int4 a = ws.hi[j];
+        const float4 c = ws.hf[j];
+        const int row = base + lane - (a.y >> 8), szj = a.y & 0xff, zb = a.x >> 16;
+        const int yy = wrap_axis<N>((int)(short)(a.x & 0xffff) + row);
+        const float dy = __int_as_float(a.z) + (float)row;
+        const float dyy = fmaf(dy, dy, c.x);
+        const float ym = (chan == 2) ? c.z * yhat(yy, N) : c.z;
+        float dz = __int_as_float(a.w);
+        // the hit's LDS reads complete here, not at the loop head, where the
+        // wait would also hold each step until the previous atomic is done
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+        for (int k = 0; k < szj; ++k, dz += 1.0f) {
+          const float e = fmaf(dz, dz, dyy) * c.y;  // d^2 / (2 s^2)
+          if (e < p.sig_c) {                       // d < rho
+            const int zz = wrap_axis<N>(zb + k);
+            float val = ym * (__expf(-e) - p.e0);
+            if (chan == 3) val *= yhat(zz, N);
+            atomicAdd(reinterpret_cast<int*>(&Wf[idx(yy, zz)]), __float2int_rn(val));
+          }
         }
       }
     }
@@ -751,6 +878,7 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_fwd
   // edge 128; the 192 transforms need their registers (copy-out from LDS)
   constexpr bool kDirect = N <= 128;
   float2* dst0 = out + ((size_t)b * N + x) * plane_sz;
+  float S = 1.0f;  // fixed-point scale of the splat sums
   if constexpr (GRID) {
     const float2* src = reinterpret_cast<const float2*>(grid + ((size_t)b * N + x) * N * N);
     // two adjacent z values of one row land in one pair-region entry each
@@ -772,15 +900,20 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_fwd
     const bool is_cand = wave_cand(rb, rg, lane * P::WAVES + wave, q);
     float4* W4 = reinterpret_cast<float4*>(W);
     for (int i = tid; i < P::SIZE / 2; i += P::THREADS) W4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-    WaveHit h;
+    __shared__ WaveSplatLds<kSplatCap<N>> wsl[P::WAVES];
+    __shared__ float bnd[2 * P::WAVES];
+    WaveHit h{};
     bool hit = is_cand && wave_hit<N>(p, q, x, h);
-    if (!__syncthreads_or(hit) && ncand <= 64 * P::WAVES) {
+    const PlaneBound pb =
+        plane_bound<P::WAVES, P::THREADS>(rb, rg, ncand, is_cand ? fabsf(__int_as_float(q.b.w)) : 0.f, hit, bnd);
+    if (!pb.any && ncand <= 64 * P::WAVES) {
       float4* d0 = reinterpret_cast<float4*>(dst0);
       for (int i = tid; i < (int)(plane_sz / 2); i += P::THREADS) d0[i] = make_float4(0.f, 0.f, 0.f, 0.f);
       return;
     }
+    S = splat_scale(pb.wsum);
     for (int c0 = 0;;) {
-      wave_splat<N>(p, hit, h, 0, Wf, pidx);
+      wave_splat<N>(p, hit, h, 0, S, Wf, pidx, wsl[wave]);
       c0 += 64 * P::WAVES;
       if (c0 >= ncand) break;  // uniform
       const bool more = wave_cand(rb, rg, c0 + lane * P::WAVES + wave, q);
@@ -788,6 +921,10 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_fwd
     }
   }
   __syncthreads();
+  if constexpr (!GRID) {
+    plane_fix_to_float<P::THREADS>(W, P::SIZE / 2, 1.0f / S);
+    __syncthreads();
+  }
   plane_forward_out<N, kDirect>(W, tw, dst0, nullptr, 1.0f);
   if constexpr (!kDirect) plane_to_global<N>(dst0, W, 1.0f);
 }
@@ -982,11 +1119,15 @@ __device__ __forceinline__ void plane_splat_body(const SplatParams& p, float2* _
   const bool is_cand = wave_cand(rb, rg, lane * P::WAVES + wave, q);
   float4* W4 = reinterpret_cast<float4*>(W);
   for (int i = tid; i < P::SIZE / 2; i += P::THREADS) W4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-  WaveHit h;
+  __shared__ WaveSplatLds<kSplatCap<N>> wsl[P::WAVES];
+  __shared__ float bnd[2 * P::WAVES];
+  WaveHit h{};
   bool hit = is_cand && wave_hit<N>(sp, q, x, h);
+  const PlaneBound pb =
+      plane_bound<P::WAVES, P::THREADS>(rb, rg, ncand, is_cand ? fabsf(__int_as_float(q.b.w)) : 0.f, hit, bnd);
   // A plane that no sample reaches is zero, and so is its spectrum: it is
   // written directly (or adds nothing), without the transforms.
-  if (!__syncthreads_or(hit) && ncand <= 64 * P::WAVES) {
+  if (!pb.any && ncand <= 64 * P::WAVES) {
     if constexpr (SINGLE) {
       if (tid < 7) dstp[tid] = 0.0;
     } else {
@@ -996,8 +1137,9 @@ __device__ __forceinline__ void plane_splat_body(const SplatParams& p, float2* _
     return;
   }
   float* Wf = reinterpret_cast<float*>(W);
+  const float S = splat_scale(chan ? pb.wsum * (0.5f * N) : pb.wsum), inv_s = 1.0f / S;
   for (int c0 = 0;;) {
-    wave_splat<N>(sp, hit, h, chan, Wf, pidx);
+    wave_splat<N>(sp, hit, h, chan, S, Wf, pidx, wsl[wave]);
     c0 += 64 * P::WAVES;
     if (c0 >= ncand) break;  // uniform
     const bool more = wave_cand(rb, rg, c0 + lane * P::WAVES + wave, q);
@@ -1011,7 +1153,10 @@ __device__ __forceinline__ void plane_splat_body(const SplatParams& p, float2* _
     float2* zb = W + P::al(t) + l;  // position l + m (m a multiple of 8) at zb[be(m)]
     float2 v[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = zb[P::be(8 * r)];
+    for (int r = 0; r < 16; ++r) {  // the splat's fixed-point sums, back to float
+      const int2 iv = reinterpret_cast<const int2*>(zb)[P::be(8 * r)];
+      v[r] = make_float2((float)iv.x * inv_s, (float)iv.y * inv_s);
+    }
     Bfly<16, -1>::run(v);
     float2* zw = W + P::al(t) + 17 * l;  // position 16 l + r at be(16 l + r) = 17 l + r
     wave_sync();
@@ -1213,14 +1358,19 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_sin
   const bool is_cand = wave_cand(rb, rg, lane * P::WAVES + wave, q);
   float4* W4 = reinterpret_cast<float4*>(W);
   for (int i = tid; i < P::SIZE / 2; i += P::THREADS) W4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-  WaveHit h;
+  __shared__ WaveSplatLds<kSplatCap<N>> wsl[P::WAVES];
+  __shared__ float bnd[2 * P::WAVES];
+  WaveHit h{};
   bool hit = is_cand && wave_hit<N>(p, q, x, h);
-  if (!__syncthreads_or(hit) && ncand <= 64 * P::WAVES) {
+  const PlaneBound pb =
+      plane_bound<P::WAVES, P::THREADS>(rb, rg, ncand, is_cand ? fabsf(__int_as_float(q.b.w)) : 0.f, hit, bnd);
+  if (!pb.any && ncand <= 64 * P::WAVES) {
     if (tid < 7) dstp[tid] = 0.0;
     return;
   }
+  const float S = splat_scale(chan ? pb.wsum * (0.5f * N) : pb.wsum);
   for (int c0 = 0;;) {
-    wave_splat<N>(p, hit, h, chan, Wf, pidx);
+    wave_splat<N>(p, hit, h, chan, S, Wf, pidx, wsl[wave]);
     c0 += 64 * P::WAVES;
     if (c0 >= ncand) break;  // uniform
     const bool more = wave_cand(rb, rg, c0 + lane * P::WAVES + wave, q);
@@ -1241,6 +1391,8 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_sin
     rd[j] = in ? AXp[plane_sz * N + ky * H + kz] : make_float2(0.f, 0.f);
   }
   __syncthreads();  // every wave's splat atomics land before any transform reads the plane
+  plane_fix_to_float<P::THREADS>(W, P::SIZE / 2, 1.0f / S);
+  __syncthreads();
   plane_forward_out<N, false>(W, tw, nullptr, nullptr, 0.f);  // spectrum stays in W
   SingleAcc acc;
   if (active) {
