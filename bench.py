@@ -40,32 +40,32 @@ HBM_PEAK_GBPS = 8000.0
 # grid). Valid only for the kernel sources they were taken on: reported as
 # null once those change.
 COUNTER_TRAFFIC = {
-    "sources_sha256": "b62ac4e58fc0543d19c3becadf3e4eb2a93680ad43d70d9ddf0078fd2f9a3dde",
-    "bytes": {"bin": (193.0 * 2 + 4164.0) * 1024, "plane_fwd": (18079.3 * 2 + 532824.8) * 1024,
-              "plane_inv": (266319.2 * 2 + 525968.0) * 1024,
-              "strip/g4k1r0": (487730.2 * 2 + 532480.0) * 1024,
-              "strip/g4k1r1": (488161.9 * 2 + 532480.0) * 1024,
-              "strip/g4k2r0": (395867.2 * 2 + 532480.0) * 1024,
-              "strip/g4k2r1": (396010.5 * 2 + 532480.0) * 1024,
-              "strip/g4k4r0": (329851.9 * 2 + 532480.0) * 1024,
-              "strip/g4k4r1": (329717.9 * 2 + 532480.0) * 1024,
-              "strip/g4k8r0": (296544.2 * 2 + 532480.0) * 1024,
-              "strip/g4k8r1": (296412.6 * 2 + 532480.0) * 1024,
-              "strip/g8k1r0": (531886.2 * 2 + 532480.0) * 1024,
-              "strip/g8k1r1": (531973.9 * 2 + 532480.0) * 1024,
-              "strip/g8k2r0": (399457.5 * 2 + 532480.0) * 1024,
-              "strip/g8k2r1": (399458.4 * 2 + 532480.0) * 1024,
-              "strip/g8k4r0": (332900.6 * 2 + 532480.0) * 1024,
-              "strip/g8k4r1": (332899.8 * 2 + 532480.0) * 1024,
-              "strip/g8k8r0": (299606.6 * 2 + 532480.1) * 1024,
+    "sources_sha256": "21dd86b50baa69560c7656e7fd235345a87fccb267b82dda89358d5ad3f68bed",
+    "bytes": {"bin": (193.0 * 2 + 4164.0) * 1024, "plane_fwd": (16965.4 * 2 + 533236.4) * 1024,
+              "plane_inv": (266319.9 * 2 + 526120.2) * 1024,
+              "strip/g4k1r0": (487942.5 * 2 + 532480.0) * 1024,
+              "strip/g4k1r1": (487452.7 * 2 + 532480.0) * 1024,
+              "strip/g4k2r0": (396223.9 * 2 + 532480.0) * 1024,
+              "strip/g4k2r1": (396174.7 * 2 + 532480.0) * 1024,
+              "strip/g4k4r0": (329927.3 * 2 + 532480.0) * 1024,
+              "strip/g4k4r1": (329980.6 * 2 + 532480.0) * 1024,
+              "strip/g4k8r0": (296740.0 * 2 + 532480.0) * 1024,
+              "strip/g4k8r1": (296740.9 * 2 + 532480.0) * 1024,
+              "strip/g8k1r0": (531281.1 * 2 + 532480.0) * 1024,
+              "strip/g8k1r1": (531417.3 * 2 + 532480.0) * 1024,
+              "strip/g8k2r0": (399454.0 * 2 + 532480.0) * 1024,
+              "strip/g8k2r1": (399458.3 * 2 + 532480.0) * 1024,
+              "strip/g8k4r0": (332900.5 * 2 + 532480.0) * 1024,
+              "strip/g8k4r1": (332899.5 * 2 + 532480.0) * 1024,
+              "strip/g8k8r0": (299606.0 * 2 + 532480.0) * 1024,
               "strip/g8k8r1": (299605.6 * 2 + 532480.0) * 1024},
 }
 # Wavefront VALU instructions per launch at 128^3 x 64 (rocprofv3
 # SQ_INSTS_VALU, same validity rule): against the issue rate of one VALU
 # instruction per CU per cycle they give each kernel's instruction-issue floor.
 COUNTER_VALU = {
-    "sources_sha256": "b62ac4e58fc0543d19c3becadf3e4eb2a93680ad43d70d9ddf0078fd2f9a3dde",
-    "insts": {"bin": 359552, "plane_fwd": 62331723, "plane_inv": 58425344,
+    "sources_sha256": "21dd86b50baa69560c7656e7fd235345a87fccb267b82dda89358d5ad3f68bed",
+    "insts": {"bin": 359552, "plane_fwd": 48689349, "plane_inv": 58425344,
               "strip/g4k1r0": 77675520,
               "strip/g4k1r1": 76277760,
               "strip/g4k2r0": 68556800,
