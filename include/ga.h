@@ -208,6 +208,11 @@ ga_status ga_score(const ga_plan* plan, const float* d_A2, int64_t a_stride, con
  * batch x 9 floats) about h_c, splatted, transformed, multiplied by
  * conj with the resident d_Ahat (one spectrum of the stationary part) and
  * transformed back into the energy field d_E[b] (batch x n^3 floats).
+ * The moving part's densities are accumulated in fixed point, each x-plane
+ * scaled by a power of two from the sum of |w| over the samples that reach
+ * it. That sum must lie within about 2^-96 .. 2^96, where the rounding per
+ * sample is at most 2^-31 of that sum; scaling every weight by a power of
+ * two scales d_E by exactly that power.
  * Workspace: GA_OP_ENERGY with n_items = n_pts.
  */
 ga_status ga_energy_fields(const ga_plan* plan, const float* d_Ahat, const float* d_xyzr, const float* d_w,

@@ -157,6 +157,33 @@ def test_energy_fields_fused_path(G, n, npts, nrot):
         assert O.rel_l2(E[r], O.energy_field(uA_ref, uB_ref)) < FIELD_TOL, r
 
 
+@pytest.mark.parametrize("n,npts,nrot", [(64, 500, 2), (96, 800, 2), (128, 1500, 2)])
+def test_energy_fields_fixed_point_splat(G, n, npts, nrot):
+    """The batched path splats the moving part in fixed point with a per-plane
+    power-of-two scale (sum of |w| over the plane's candidates): weights over
+    six decades still match the oracle, scaling every weight by 2^40 or 2^-40
+    scales the field by exactly that power (the integer sums are unchanged),
+    and repeated calls give the same bits."""
+    A = _part(n, 7100 + n, npts, 1.0, 3.0)
+    B = _part(n, 7200 + n, npts, 1.0, 3.0, conf=n / 6)
+    wB = (B.w * 10.0 ** np.random.default_rng(7300 + n).uniform(-3, 3, B.n)).astype(np.float32)
+    R = synth.shoemake_rotations(7400 + n, nrot)
+    cB = B.ref_point()
+    plan = G.Plan(n, max_batch=nrot)
+    Ahat = G.ga_fft3d(plan, G.GA_R2C, G.ga_splat(plan, _dev(A.xyzr), _dev(A.w)))[0].contiguous()
+    xb, Rd = _dev(B.xyzr), _dev(R)
+    E = G.ga_energy_fields(plan, Ahat, xb, _dev(wB), Rd, cB).cpu().numpy()
+    uA_ref = O.splat(A.xyzr[:, :3].astype(np.float64), A.xyzr[:, 3], A.w, n)
+    for r in range(nrot):
+        uB_ref = O.splat(O.place(B.xyzr[:, :3], R[r], cB), B.xyzr[:, 3], wB.astype(np.float64), n)
+        assert O.rel_l2(E[r], O.energy_field(uA_ref, uB_ref)) < FIELD_TOL, r
+    again = G.ga_energy_fields(plan, Ahat, xb, _dev(wB), Rd, cB).cpu().numpy()
+    assert np.array_equal(again, E)
+    for k in (40, -40):
+        Ek = G.ga_energy_fields(plan, Ahat, xb, _dev(np.ldexp(wB, k).astype(np.float32)), Rd, cB).cpu().numpy()
+        assert np.array_equal(Ek, np.ldexp(E, k)), k
+
+
 def test_c1_workload_end_to_end(G):
     a = synth.config_c1()
     n = a.n
