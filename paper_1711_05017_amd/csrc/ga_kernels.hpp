@@ -136,7 +136,16 @@ struct SplatParams {
   // records whose x bin lies within reach of plane x (two runs when the range
   // wraps around the torus); null where the kernels do not use it
   const int4* cand;
+  // per batch member, kPlaneMaskWords<N> words: bit x set when plane x of
+  // the member's spectrum was written. With it, pass 1 stores no plane that
+  // no sample reaches (its spectrum is zero) and readers of the spectra
+  // treat unset planes as zero. Cleared by the binning kernel; null: every
+  // plane is stored.
+  unsigned* pmask;
 };
+
+template <int N>
+constexpr int kPlaneMaskWords = (N + 31) / 32;
 
 // A sample that reaches the current plane, with the bounding square of its
 // disk in the plane: rows ylo .. ylo + sy - 1, columns zlo .. zlo + sz - 1
@@ -282,11 +291,13 @@ __device__ void bin_block(const SplatParams& p, const double* R, Placed* __restr
 }
 
 // Per batch member b: the moving part rotated by R_b, binned into
-// rec[b*n_pts ...], off[b*(N+1) ...], rmax[b]. grid = batch, block = 1024.
+// rec[b*n_pts ...], off[b*(N+1) ...], rmax[b]; the member's plane mask
+// (p.pmask, if set) cleared for pass 1. grid = batch, block = 1024.
 template <int N>
 __global__ void __launch_bounds__(1024) k_bin_samples(SplatParams p, Placed* __restrict__ rec, int* __restrict__ off,
                                                      float* __restrict__ rmax, int4* __restrict__ cand) {
   const int b = blockIdx.x;
+  if (p.pmask && (int)threadIdx.x < kPlaneMaskWords<N>) p.pmask[(size_t)b * kPlaneMaskWords<N> + threadIdx.x] = 0u;
   double R[9];
   load_rotation(p, b, R);
   bin_block<N>(p, R, rec + (size_t)b * p.n_pts, off + (size_t)b * (N + 1), rmax + b,
@@ -907,10 +918,12 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_fwd
     const PlaneBound pb =
         plane_bound<P::WAVES, P::THREADS>(rb, rg, ncand, is_cand ? fabsf(__int_as_float(q.b.w)) : 0.f, hit, bnd);
     if (!pb.any && ncand <= 64 * P::WAVES) {
+      if (p.pmask) return;  // not stored: its mask bit stays clear
       float4* d0 = reinterpret_cast<float4*>(dst0);
       for (int i = tid; i < (int)(plane_sz / 2); i += P::THREADS) d0[i] = make_float4(0.f, 0.f, 0.f, 0.f);
       return;
     }
+    if (p.pmask && tid == 0) atomicOr(&p.pmask[(size_t)b * kPlaneMaskWords<N> + (x >> 5)], 1u << (x & 31));
     S = splat_scale(pb.wsum);
     for (int c0 = 0;;) {
       wave_splat<N>(p, hit, h, 0, S, Wf, pidx, wsl[wave]);
@@ -1130,11 +1143,14 @@ __device__ __forceinline__ void plane_splat_body(const SplatParams& p, float2* _
   if (!pb.any && ncand <= 64 * P::WAVES) {
     if constexpr (SINGLE) {
       if (tid < 7) dstp[tid] = 0.0;
-    } else {
+    } else if (!p.pmask) {  // with a plane mask the plane is not stored (its bit stays clear)
       float4* d = reinterpret_cast<float4*>(dst0);
       for (int i = tid; i < (int)(plane_sz / 2); i += P::THREADS) d[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     return;
+  }
+  if constexpr (!SINGLE) {
+    if (p.pmask && tid == 0) atomicOr(&p.pmask[(size_t)b * kPlaneMaskWords<N> + (x >> 5)], 1u << (x & 31));
   }
   float* Wf = reinterpret_cast<float*>(W);
   const float S = splat_scale(chan ? pb.wsum * (0.5f * N) : pb.wsum), inv_s = 1.0f / S;
@@ -1587,15 +1603,57 @@ template <int N, int G, class SH = Shape<N>> struct Strip {
   __device__ __forceinline__ static int idx(int x, int g) { return x * LD + (g ^ (((x >> Z::SH) & Z::MASK) * Z::MUL)); }
 };
 
+// Loads in flight per thread: the largest divisor of it up to 16.
+constexpr int load_batch(int it) {
+  for (int b = 16; b > 1; --b)
+    if (it % b == 0) return b;
+  return 1;
+}
 template <int N, int G, class SH = Shape<N>>
-__device__ __forceinline__ void strip_load(float2* S, const float2* src, int c0) {
+__device__ __forceinline__ void strip_load(float2* S, const float2* src, int c0, const unsigned* rows = nullptr) {
   using T = Strip<N, G, SH>;
-  batched_copy<N * G, T::THREADS, float2>(
-      [&](int i) {
-        const int x = i / G, c = c0 + i % G;
-        return (c < T::C) ? src[(size_t)x * T::C + c] : make_float2(0.f, 0.f);
-      },
-      [&](int i, float2 v) { S[T::idx(i / G, i % G)] = v; });
+  // rows: a plane mask (kPlaneMaskWords<N> words) or null; rows whose bit is
+  // clear are zero and not read. Thread (x0, g) takes rows x0 + XS u of
+  // column g, so the word and bit offset of row x0 + XS u are compile-time
+  // for each u (XS divides 32 and x0 < XS).
+  constexpr int XS = T::THREADS / G, IT = N / XS, B = load_batch(IT), MW = kPlaneMaskWords<N>;
+  if constexpr (!(T::THREADS % G == 0 && N % XS == 0 && 32 % XS == 0)) {
+    batched_copy<N * G, T::THREADS, float2>(
+        [&](int i) {
+          const int x = i / G, c = c0 + i % G;
+          const bool live = !rows || ((rows[x >> 5] >> (x & 31)) & 1u);
+          return (c < T::C && live) ? src[(size_t)x * T::C + c] : make_float2(0.f, 0.f);
+        },
+        [&](int i, float2 v) { S[T::idx(i / G, i % G)] = v; });
+  } else {
+    // raw buffer loads: one per-lane offset for all rows, the row step a
+    // compile-time scalar offset; a row that is not read gets an offset
+    // beyond the buffer, for which the load returns zero without a memory
+    // access
+    static_assert((size_t)N * T::C * sizeof(float2) < 0x80000000u, "strip offsets below the skip offset");
+    constexpr unsigned kSkip = 0x80000000u;
+    unsigned rw[MW];
+#pragma unroll
+    for (int j = 0; j < MW; ++j) rw[j] = rows ? rows[j] : ~0u;
+    const int x0 = (int)threadIdx.x / G, g = (int)threadIdx.x % G, c = c0 + g;
+    const bool colok = c < T::C;
+    const auto rs = buffer_rsrc(const_cast<float2*>(src), (unsigned)((size_t)N * T::C * sizeof(float2)));
+    const unsigned vbase = (unsigned)(((size_t)x0 * T::C + c) * sizeof(float2));
+#pragma unroll
+    for (int u0 = 0; u0 < IT; u0 += B) {
+      float2 v[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int xr = XS * (u0 + u);  // row x0 + xr
+        const bool live = colok && ((rw[xr >> 5] >> ((xr & 31) + x0)) & 1u);
+        const u32x2 r = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)(live ? vbase : kSkip),
+                                                              (int)((size_t)xr * T::C * sizeof(float2)), 0);
+        v[u] = make_float2(__uint_as_float(r.x), __uint_as_float(r.y));
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u) S[T::idx(x0 + XS * (u0 + u), g)] = v[u];
+    }
+  }
 }
 template <int N, int G, class SH = Shape<N>>
 __device__ __forceinline__ void strip_store(const float2* S, float2* dst, int c0) {
@@ -1640,7 +1698,9 @@ __global__ void __launch_bounds__((Strip<N, G>::THREADS)) k_strip_fft(const floa
 // members in turn. With a shared stationary spectrum (a_stride = 0, FWD) each
 // thread keeps its elements of A in registers, so A is read once per K
 // members. B and out may be the same buffer (the fused path works in place),
-// so neither is declared __restrict__.
+// so neither is declared __restrict__. bmask (FWD, or null): the plane masks
+// of B's members (SplatParams::pmask); planes whose bit is clear are zero and
+// not read.
 // xcd_m > 0 selects a one-dimensional, XCD-aware grid: workgroups are
 // dispatched round-robin over the 8 XCDs (each with its own L2), so
 // workgroup id runs on XCD id % 8; the xcd_m member groups of one strip are
@@ -1650,7 +1710,8 @@ template <int N, int G, bool FWD, int K = 1, class SH = Shape<N>>
 __global__ void __launch_bounds__((Strip<N, G, SH>::THREADS)) k_strip_corr(const float2* __restrict__ A,
                                                                          long long a_stride, const float2* B,
                                                                          float2* out, int batch, int xcd_m,
-                                                                         const float2* __restrict__ table) {
+                                                                         const float2* __restrict__ table,
+                                                                         const unsigned* __restrict__ bmask) {
   using T = Strip<N, G, SH>;
   constexpr int IT = (N * G + T::THREADS - 1) / T::THREADS;  // strip elements per thread
   constexpr int NSTRIPS = (T::C + G - 1) / G;
@@ -1684,7 +1745,7 @@ __global__ void __launch_bounds__((Strip<N, G, SH>::THREADS)) k_strip_corr(const
     const size_t boff = (size_t)b * N * T::C;
     const float2* Ab = A + (size_t)b * (size_t)a_stride;
     if constexpr (FWD) {
-      strip_load<N, G, SH>(S, B + boff, c0);
+      strip_load<N, G, SH>(S, B + boff, c0, bmask ? bmask + (size_t)b * kPlaneMaskWords<N> : nullptr);
       __syncthreads();
       strip_fft<N, G, -1>(S, tw);
       __syncthreads();

@@ -138,26 +138,27 @@ template <int N> struct Launch {
   // the default radix schedule or its alternative (radix = 1); the
   // autotuner picks all three per plan.
   static constexpr int kCorrK = 4;
+  // bmask: the plane masks of buf's members from pass 1 (or null: dense)
   template <int GG, int K, class SH>
   static void corr_fwd(const float2* A, long long a_stride, float2* buf, int batch, bool xcd, const float2* tw,
-                       hipStream_t s) {
+                       hipStream_t s, const unsigned* bmask) {
     using TT = Strip<N, GG, SH>;
     const int ns = (TT::C + GG - 1) / GG, m = (batch + K - 1) / K;
     if (xcd)
       hipLaunchKernelGGL((k_strip_corr<N, GG, true, K, SH>), dim3((unsigned)(((ns + 7) / 8) * 8 * m)),
-                         dim3(TT::THREADS), 0, s, A, a_stride, buf, buf, batch, m, tw);
+                         dim3(TT::THREADS), 0, s, A, a_stride, buf, buf, batch, m, tw, bmask);
     else
       hipLaunchKernelGGL((k_strip_corr<N, GG, true, K, SH>), dim3(ns, m), dim3(TT::THREADS), 0, s, A, a_stride, buf,
-                         buf, batch, 0, tw);
+                         buf, batch, 0, tw, bmask);
   }
   template <int GG, class SH>
   static void corr_fwd_k(int k, const float2* A, long long a_stride, float2* buf, int batch, bool xcd,
-                         const float2* tw, hipStream_t s) {
+                         const float2* tw, hipStream_t s, const unsigned* bmask) {
     switch (k) {
-      case 1: corr_fwd<GG, 1, SH>(A, a_stride, buf, batch, xcd, tw, s); break;
-      case 2: corr_fwd<GG, 2, SH>(A, a_stride, buf, batch, xcd, tw, s); break;
-      case 8: corr_fwd<GG, 8, SH>(A, a_stride, buf, batch, xcd, tw, s); break;
-      default: corr_fwd<GG, 4, SH>(A, a_stride, buf, batch, xcd, tw, s); break;
+      case 1: corr_fwd<GG, 1, SH>(A, a_stride, buf, batch, xcd, tw, s, bmask); break;
+      case 2: corr_fwd<GG, 2, SH>(A, a_stride, buf, batch, xcd, tw, s, bmask); break;
+      case 8: corr_fwd<GG, 8, SH>(A, a_stride, buf, batch, xcd, tw, s, bmask); break;
+      default: corr_fwd<GG, 4, SH>(A, a_stride, buf, batch, xcd, tw, s, bmask); break;
     }
   }
   // groups in {4, 8}, k in {1, 2, 4, 8}; k > 1 only with a shared spectrum.
@@ -171,21 +172,21 @@ template <int N> struct Launch {
   // whether the alternative radix schedule exists for this edge
   static constexpr bool kAltRadix = ShapeAlt<N>::kDistinct && tunable<ShapeAlt<N>>();
   static void corr_fwd_tuned(int groups, int k, bool xcd, int radix, const float2* A, long long a_stride, float2* buf,
-                             int batch, const float2* tw, hipStream_t s) {
+                             int batch, const float2* tw, hipStream_t s, const unsigned* bmask = nullptr) {
     if (a_stride != 0 || batch == 1) k = 1;
     if constexpr (!kTunable) {
-      corr_fwd<G, 1, Shape<N>>(A, a_stride, buf, batch, xcd, tw, s);
+      corr_fwd<G, 1, Shape<N>>(A, a_stride, buf, batch, xcd, tw, s, bmask);
     } else {
       if constexpr (kAltRadix) {
         if (radix == 1) {
           using SA = ShapeAlt<N>;
-          if (groups == 8) corr_fwd_k<8 * ffts_per_wave<N, SA>(), SA>(k, A, a_stride, buf, batch, xcd, tw, s);
-          else corr_fwd_k<4 * ffts_per_wave<N, SA>(), SA>(k, A, a_stride, buf, batch, xcd, tw, s);
+          if (groups == 8) corr_fwd_k<8 * ffts_per_wave<N, SA>(), SA>(k, A, a_stride, buf, batch, xcd, tw, s, bmask);
+          else corr_fwd_k<4 * ffts_per_wave<N, SA>(), SA>(k, A, a_stride, buf, batch, xcd, tw, s, bmask);
           return;
         }
       }
-      if (groups == 8) corr_fwd_k<8 * ffts_per_wave<N>(), Shape<N>>(k, A, a_stride, buf, batch, xcd, tw, s);
-      else corr_fwd_k<4 * ffts_per_wave<N>(), Shape<N>>(k, A, a_stride, buf, batch, xcd, tw, s);
+      if (groups == 8) corr_fwd_k<8 * ffts_per_wave<N>(), Shape<N>>(k, A, a_stride, buf, batch, xcd, tw, s, bmask);
+      else corr_fwd_k<4 * ffts_per_wave<N>(), Shape<N>>(k, A, a_stride, buf, batch, xcd, tw, s, bmask);
     }
   }
   static void strip_corr(bool fwd, const float2* A, long long a_stride, const float2* B, float2* out, int batch,
@@ -194,10 +195,10 @@ template <int N> struct Launch {
       corr_fwd_tuned(4, kCorrK, false, 0, A, a_stride, out, batch, tw, s);
     } else if (fwd) {
       hipLaunchKernelGGL((k_strip_corr<N, G, true, 1>), dim3(nstrips(), batch), dim3(T::THREADS), 0, s, A, a_stride, B,
-                         out, batch, 0, tw);
+                         out, batch, 0, tw, nullptr);
     } else {
       hipLaunchKernelGGL((k_strip_corr<N, G, false, 1>), dim3(nstrips(), batch), dim3(T::THREADS), 0, s, A, a_stride,
-                         B, out, batch, 0, tw);
+                         B, out, batch, 0, tw, nullptr);
     }
   }
   // complex score: nparts = 1 or 2 product spectra per member from part `first`
@@ -352,18 +353,19 @@ inline int nlocal_of(int64_t n_pts) { return (int)((n_pts + kLocalSPB - 1) / kLo
 inline bool valid_sigma(float s) { return std::isfinite(s) && s > 0.0f; }
 
 // Workspace of the fused field path: batch spectra, then the binned samples
-// (records, bin offsets, largest radius and per-plane candidate runs per
-// batch member), each part 16-byte aligned.
+// (records, bin offsets, largest radius, per-plane candidate runs and the
+// plane mask of pass 1 per batch member), each part 16-byte aligned.
 inline size_t bin_offset(int n, int batch) { return (size_t)batch * spectrum_elems(n) * sizeof(float2); }
 struct BinLayout {
-  size_t rec, off, rmax, cand, total;  // byte offsets from the start of the binned part
+  size_t rec, off, rmax, cand, pmask, total;  // byte offsets from the start of the binned part
   BinLayout(int n, int batch, int64_t n_pts) {
     auto up = [](size_t v) { return (v + 15) / 16 * 16; };
     rec = 0;
     off = up((size_t)batch * (size_t)n_pts * sizeof(Placed));
     rmax = off + up((size_t)batch * (n + 1) * sizeof(int));
     cand = rmax + up((size_t)batch * sizeof(float));
-    total = cand + (size_t)batch * n * sizeof(int4);
+    pmask = cand + up((size_t)batch * n * sizeof(int4));
+    total = pmask + (size_t)batch * ((n + 31) / 32) * sizeof(unsigned);
   }
 };
 inline size_t bin_bytes(int n, int batch, int64_t n_pts) { return BinLayout(n, batch, n_pts).total; }

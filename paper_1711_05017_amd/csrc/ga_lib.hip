@@ -433,6 +433,7 @@ ga_status ga_energy_fields(const ga_plan* plan, const float* d_Ahat, const float
   int* off = reinterpret_cast<int*>(bins + bl.off);
   float* rmax = reinterpret_cast<float*>(bins + bl.rmax);
   int4* cand = reinterpret_cast<int4*>(bins + bl.cand);
+  unsigned* pmask = reinterpret_cast<unsigned*>(bins + bl.pmask);
   // chunked, two-stream execution (ga_plan_set_overlap); one stream under
   // graph capture
   int chunks = std::min(plan->chunks, (int)batch);
@@ -460,6 +461,8 @@ ga_status ga_energy_fields(const ga_plan* plan, const float* d_Ahat, const float
       float* mc = rmax + c0;
       int4* cc = cand + (size_t)c0 * N;
       float2* tc = tmp + (size_t)c0 * spectrum_elems(n);
+      unsigned* pc = pmask + (size_t)c0 * kPlaneMaskWords<N>;
+      spc.pmask = pc;  // cleared by the binning, set by pass 1, read by the x pass
       {
         ProfScope pb(plan, GA_K_BIN, sc);
         Launch<N>::bin_samples(spc, rc, oc, mc, cc, nb, sc);
@@ -475,7 +478,7 @@ ga_status ga_energy_fields(const ga_plan* plan, const float* d_Ahat, const float
       {
         ProfScope ps(plan, GA_K_STRIP, sc);
         Launch<N>::corr_fwd_tuned(groups, k, plan->tune_xcd == 1, plan->tune_radix,
-                                  reinterpret_cast<const float2*>(d_Ahat), 0, tc, nb, plan->d_tw, sc);
+                                  reinterpret_cast<const float2*>(d_Ahat), 0, tc, nb, plan->d_tw, sc, pc);
       }
       ProfScope ps(plan, GA_K_PLANE_INV, sc);
       Launch<N>::plane_inv(tc, d_E + (size_t)c0 * n * n * n, scale, nb, plan->d_tw, sc);

@@ -184,6 +184,27 @@ def test_energy_fields_fixed_point_splat(G, n, npts, nrot):
         assert np.array_equal(Ek, np.ldexp(E, k)), k
 
 
+@pytest.mark.parametrize("n,npts,nrot", [(64, 400, 3), (128, 1200, 5), (192, 1500, 2)])
+def test_energy_fields_skip_empty_planes(G, n, npts, nrot):
+    """Pass 1 stores no x-plane that no sample reaches and the x pass reads
+    only the planes pass 1 marked: a workspace full of NaN bits beforehand
+    (stale spectra in every plane) must not reach the fields."""
+    A = _part(n, 7600 + n, npts, 1.0, 3.0)
+    B = _part(n, 7700 + n, npts, 1.0, 3.0, conf=n / 6)  # most x-planes of B stay empty
+    R = synth.shoemake_rotations(7800 + n, nrot)
+    cB = B.ref_point()
+    plan = G.Plan(n, max_batch=nrot)
+    Ahat = G.ga_fft3d(plan, G.GA_R2C, G.ga_splat(plan, _dev(A.xyzr), _dev(A.w)))[0].contiguous()
+    work = plan.workspace(G.ga.GA_OP_ENERGY, nrot, B.n)
+    work.fill_(255)
+    E = G.ga_energy_fields(plan, Ahat, _dev(B.xyzr), _dev(B.w), _dev(R), cB, work=work).cpu().numpy()
+    assert np.isfinite(E).all()
+    uA_ref = O.splat(A.xyzr[:, :3].astype(np.float64), A.xyzr[:, 3], A.w, n)
+    for r in range(nrot):
+        uB_ref = O.splat(O.place(B.xyzr[:, :3], R[r], cB), B.xyzr[:, 3], B.w, n)
+        assert O.rel_l2(E[r], O.energy_field(uA_ref, uB_ref)) < FIELD_TOL, r
+
+
 def test_c1_workload_end_to_end(G):
     a = synth.config_c1()
     n = a.n
