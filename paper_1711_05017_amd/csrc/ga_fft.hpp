@@ -15,6 +15,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace ga {
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
@@ -248,8 +250,9 @@ __device__ __forceinline__ void load_twiddles(Twiddles<N, SH>& tw, const float2*
 // One Stockham stage, in place in LDS: element `pos` of the transform lives
 // at at(pos) (a float2 pointer; any layout, e.g. strided or swizzled against
 // bank conflicts). Stage 0 takes its inputs from ld(pos) and the last stage
-// hands its outputs to st(pos, v); positions are natural indices. The
-// schedule SH comes with the twiddles.
+// hands its outputs to st(pos, v), or st(pos, v, e) with e the output's
+// element index in the lane (fft_out_pos); positions are natural indices.
+// The schedule SH comes with the twiddles.
 template <int N, int S, int DIR, class TW, class At, class Ld, class St>
 __device__ __forceinline__ void fft_stage(int lane, const TW& tw, At& at, Ld& ld, St& st) {
   using SH = typename TW::Sched;
@@ -283,12 +286,24 @@ __device__ __forceinline__ void fft_stage(int lane, const TW& tw, At& at, Ld& ld
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int pos = base + r * NS;
-      if constexpr (last) st(pos, v[b * R + r]);
+      if constexpr (last) {
+        if constexpr (std::is_invocable_v<St&, int, float2, int>) st(pos, v[b * R + r], b * R + r);
+        else st(pos, v[b * R + r]);
+      }
       else *at(pos) = v[b * R + r];
     }
   }
   wave_sync();
   if constexpr (!last) fft_stage<N, S + 1, DIR>(lane, tw, at, ld, st);
+}
+
+// Natural position of output element e of transform lane `lane` (as the
+// last stage of fft_stage stores it) under schedule SH.
+template <int N, class SH>
+__device__ __forceinline__ int fft_out_pos(int lane, int e) {
+  constexpr int S = SH::NST - 1, E = SH::E, L = N / E, R = SH::R[S], NS = ns_before<N, SH>(S);
+  const int b = e / R, r = e % R, j = lane + L * b, k = j % NS;
+  return (j - k) * R + k + r * NS;
 }
 
 // Transform of length N on the L lanes [0, L) of this transform (`lane` is

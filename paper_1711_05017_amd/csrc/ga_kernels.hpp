@@ -1724,19 +1724,25 @@ __global__ void __launch_bounds__((Strip<N, G, SH>::THREADS)) k_strip_corr(const
   }
   __shared__ float2 S[T::SIZE];
   Twiddles<N, SH> tw;
-  load_twiddles<N>(tw, table, (threadIdx.x & 63) % T::L);
+  const int lane = (int)threadIdx.x & 63, tl = lane % T::L, g = ((int)threadIdx.x >> 6) * T::TPW + lane / T::L;
+  load_twiddles<N>(tw, table, tl);  // this thread: lane tl of the x transform of column g
   const int c0 = sx * G;
   auto a_at = [&](const float2* Ab, int i) {
     const int x = i / G, c = c0 + i % G;
     return (c < T::C) ? Ab[(size_t)x * T::C + c] : make_float2(0.f, 0.f);
   };
-  float2 areg[(FWD && K > 1) ? IT : 1];
+  // FWD with a shared stationary spectrum (K > 1): that spectrum, held in
+  // registers for the K members, in the order the forward x transform hands
+  // out its results (element e of this lane is row fft_out_pos(tl, e) of
+  // column g), so that the conjugate product is taken in the transform's
+  // last stage instead of a pass of its own over the strip
+  static_assert(SH::E == IT, "one transform's elements per thread");
+  float2 aout[(FWD && K > 1) ? IT : 1];
   if constexpr (FWD && K > 1) {
+    const bool colok = c0 + g < T::C;
 #pragma unroll
-    for (int u = 0; u < IT; ++u) {
-      const int i = threadIdx.x + u * T::THREADS;
-      areg[u] = (i < N * G) ? a_at(A, i) : make_float2(0.f, 0.f);
-    }
+    for (int e = 0; e < IT; ++e)
+      aout[e] = colok ? A[(size_t)fft_out_pos<N, SH>(tl, e) * T::C + c0 + g] : make_float2(0.f, 0.f);
   }
 #pragma unroll 1
   for (int kk = 0; kk < K; ++kk) {
@@ -1747,18 +1753,13 @@ __global__ void __launch_bounds__((Strip<N, G, SH>::THREADS)) k_strip_corr(const
     if constexpr (FWD) {
       strip_load<N, G, SH>(S, B + boff, c0, bmask ? bmask + (size_t)b * kPlaneMaskWords<N> : nullptr);
       __syncthreads();
-      strip_fft<N, G, -1>(S, tw);
-      __syncthreads();
       if constexpr (K > 1) {
-#pragma unroll
-        for (int u = 0; u < IT; ++u) {
-          const int i = threadIdx.x + u * T::THREADS;
-          if (i < N * G) {
-            float2* e = &S[T::idx(i / G, i % G)];
-            *e = cmulc(areg[u], *e);
-          }
-        }
+        auto at = [=](int x) { return S + T::idx(x, g); };
+        fft_at<N, -1>(tl, tw, at, [&](int pos) { return *at(pos); },
+                      [&](int pos, float2 v, int e) { *at(pos) = cmulc(aout[e], v); });
       } else {
+        strip_fft<N, G, -1>(S, tw);
+        __syncthreads();
         batched_copy<N * G, T::THREADS, float2>([&](int i) { return a_at(Ab, i); }, [&](int i, float2 a) {
           float2* e = &S[T::idx(i / G, i % G)];
           *e = cmulc(a, *e);
