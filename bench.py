@@ -40,48 +40,48 @@ HBM_PEAK_GBPS = 8000.0
 # grid). Valid only for the kernel sources they were taken on: reported as
 # null once those change.
 COUNTER_TRAFFIC = {
-    "sources_sha256": "21dd86b50baa69560c7656e7fd235345a87fccb267b82dda89358d5ad3f68bed",
-    "bytes": {"bin": (193.0 * 2 + 4164.0) * 1024, "plane_fwd": (16965.4 * 2 + 533236.4) * 1024,
-              "plane_inv": (266319.9 * 2 + 526120.2) * 1024,
-              "strip/g4k1r0": (487942.5 * 2 + 532480.0) * 1024,
-              "strip/g4k1r1": (487452.7 * 2 + 532480.0) * 1024,
-              "strip/g4k2r0": (396223.9 * 2 + 532480.0) * 1024,
-              "strip/g4k2r1": (396174.7 * 2 + 532480.0) * 1024,
-              "strip/g4k4r0": (329927.3 * 2 + 532480.0) * 1024,
-              "strip/g4k4r1": (329980.6 * 2 + 532480.0) * 1024,
-              "strip/g4k8r0": (296740.0 * 2 + 532480.0) * 1024,
-              "strip/g4k8r1": (296740.9 * 2 + 532480.0) * 1024,
-              "strip/g8k1r0": (531281.1 * 2 + 532480.0) * 1024,
-              "strip/g8k1r1": (531417.3 * 2 + 532480.0) * 1024,
-              "strip/g8k2r0": (399454.0 * 2 + 532480.0) * 1024,
-              "strip/g8k2r1": (399458.3 * 2 + 532480.0) * 1024,
-              "strip/g8k4r0": (332900.5 * 2 + 532480.0) * 1024,
-              "strip/g8k4r1": (332899.5 * 2 + 532480.0) * 1024,
-              "strip/g8k8r0": (299606.0 * 2 + 532480.0) * 1024,
-              "strip/g8k8r1": (299605.6 * 2 + 532480.0) * 1024},
+    "sources_sha256": "8fbe75d5a364bbb8c254f40084a85a87b2b4dc28e832f9a6901b42f043de97de",
+    "bytes": {"bin": (193.0 * 2 + 4166.0) * 1024, "plane_fwd": (16616.2 * 2 + 246273.4) * 1024,
+              "plane_inv": (266319.8 * 2 + 525878.2) * 1024,
+              "strip/g4k1r0": (297385.6 * 2 + 532480.0) * 1024,
+              "strip/g4k1r1": (296407.1 * 2 + 532480.0) * 1024,
+              "strip/g4k2r0": (249519.6 * 2 + 532480.0) * 1024,
+              "strip/g4k2r1": (249490.2 * 2 + 532480.0) * 1024,
+              "strip/g4k4r0": (182611.2 * 2 + 532480.0) * 1024,
+              "strip/g4k4r1": (182573.0 * 2 + 532480.0) * 1024,
+              "strip/g4k8r0": (150663.5 * 2 + 532480.0) * 1024,
+              "strip/g4k8r1": (150746.5 * 2 + 532480.0) * 1024,
+              "strip/g8k1r0": (387578.8 * 2 + 532480.0) * 1024,
+              "strip/g8k1r1": (387264.6 * 2 + 532480.0) * 1024,
+              "strip/g8k2r0": (256224.4 * 2 + 532480.0) * 1024,
+              "strip/g8k2r1": (256223.1 * 2 + 532480.0) * 1024,
+              "strip/g8k4r0": (189642.6 * 2 + 532480.0) * 1024,
+              "strip/g8k4r1": (189637.7 * 2 + 532480.0) * 1024,
+              "strip/g8k8r0": (156345.8 * 2 + 532480.0) * 1024,
+              "strip/g8k8r1": (156348.5 * 2 + 532480.0) * 1024},
 }
 # Wavefront VALU instructions per launch at 128^3 x 64 (rocprofv3
 # SQ_INSTS_VALU, same validity rule): against the issue rate of one VALU
 # instruction per CU per cycle they give each kernel's instruction-issue floor.
 COUNTER_VALU = {
-    "sources_sha256": "21dd86b50baa69560c7656e7fd235345a87fccb267b82dda89358d5ad3f68bed",
-    "insts": {"bin": 359552, "plane_fwd": 48689349, "plane_inv": 58425344,
-              "strip/g4k1r0": 77675520,
-              "strip/g4k1r1": 76277760,
-              "strip/g4k2r0": 68556800,
-              "strip/g4k2r1": 67624960,
-              "strip/g4k4r0": 63914240,
-              "strip/g4k4r1": 63182080,
-              "strip/g4k8r0": 61543040,
-              "strip/g4k8r1": 60910720,
-              "strip/g8k1r0": 76876800,
-              "strip/g8k1r1": 75479040,
-              "strip/g8k2r0": 68224000,
-              "strip/g8k2r1": 67292160,
-              "strip/g8k4r0": 63747840,
-              "strip/g8k4r1": 63015680,
-              "strip/g8k8r0": 61459840,
-              "strip/g8k8r1": 60827520},
+    "sources_sha256": "8fbe75d5a364bbb8c254f40084a85a87b2b4dc28e832f9a6901b42f043de97de",
+    "insts": {"bin": 360704, "plane_fwd": 47631848, "plane_inv": 58425344,
+              "strip/g4k1r0": 76677120,
+              "strip/g4k1r1": 75412480,
+              "strip/g4k2r0": 66460160,
+              "strip/g4k2r1": 65594880,
+              "strip/g4k4r0": 62699520,
+              "strip/g4k4r1": 62000640,
+              "strip/g4k8r0": 60602880,
+              "strip/g4k8r1": 59987200,
+              "strip/g8k1r0": 76078080,
+              "strip/g8k1r1": 74613760,
+              "strip/g8k2r0": 66593280,
+              "strip/g8k2r1": 65694720,
+              "strip/g8k4r0": 62766080,
+              "strip/g8k4r1": 62050560,
+              "strip/g8k8r0": 60636160,
+              "strip/g8k8r1": 60012160},
 }
 VALU_ISSUE_PER_S = 256 * 2.4e9  # CUs x clock: one wave64 VALU instruction per CU per cycle
 COPY_GBPS = 5390.0  # plain 512 MiB device copy, read + write (rocprofv3 calibration on the MI355X)
@@ -528,6 +528,9 @@ def main():
                          "legs in turn")
     ap.add_argument("--spectral-queries", type=int, default=40000, help="queries of the spectral serving leg")
     ap.add_argument("--no-batch256", action="store_true")
+    ap.add_argument("--strip-sweep", type=int, default=0,
+                    help="counter runs: instead of autotuning, run this many whole calls in every configuration of "
+                         "the fused x pass (one stream)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB, three times (the known-size "
                          "kernel that scales the HBM byte counters)")
@@ -565,10 +568,26 @@ def main():
     E = torch.empty((batch, n, n, n), dtype=torch.float32, device=dev)
     work = plan.workspace(G.ga.GA_OP_ENERGY, batch, a.B.n, device=dev)
 
-    tuned, tune_us = plan.autotune(Ahat, batch, work)  # before the timed region
-
     def step():
         G.ga_energy_fields(plan, Ahat, xb, wb, R, a.cB, a.sigma, out=E, work=work)
+
+    if args.strip_sweep:
+        # counter runs: every configuration of the fused x pass on the real
+        # calls (plane masks included), one stream, then the default one
+        plan.set_overlap(1)
+        for g, k, x, r in plan.AUTOTUNE_CANDIDATES:
+            if r == 1 and not plan.has_alt_radix():
+                continue
+            plan.set_tuning(g, k, x)
+            plan.set_radix(r)
+            for _ in range(args.strip_sweep):
+                step()
+        torch.cuda.synchronize()
+        plan.set_tuning(4, 4, 2)
+        plan.set_radix(1 if plan.has_alt_radix() else 0)
+        tuned, tune_us = plan.tuning() + (plan.radix(),), {}
+    else:
+        tuned, tune_us = plan.autotune(Ahat, batch, work)  # before the timed region
 
     def kernel_times():
         kt = {}
