@@ -904,6 +904,12 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_fwd
     // spectrum, written directly
     const int4 rg = p.cand[(size_t)b * N + x];
     const int ncand = rg.y + rg.w;
+    if (ncand == 0) {  // no sample within reach: a zero plane, known before any load or fill
+      if (p.pmask) return;
+      float4* d0 = reinterpret_cast<float4*>(dst0);
+      for (int i = tid; i < (int)(plane_sz / 2); i += P::THREADS) d0[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+      return;
+    }
     const Placed* rb = p.rec + (size_t)b * p.n_pts;
     const int lane = tid & 63, wave = tid >> 6;
     auto pidx = [](int yy, int zz) { return P::zs(yy >> 1, zz) * 2 + (yy & 1); };
@@ -1126,6 +1132,15 @@ __device__ __forceinline__ void plane_splat_body(const SplatParams& p, float2* _
   sp.inv1me0 *= 0.5f;  // the 1/2 of the two-for-one split
   const int4 rg = p.cand[(size_t)b * N + x];
   const int ncand = rg.y + rg.w;
+  if (ncand == 0) {  // no sample within reach: a zero plane, known before any load or fill
+    if constexpr (SINGLE) {
+      if (tid < 7) dstp[tid] = 0.0;
+    } else if (!p.pmask) {
+      float4* d = reinterpret_cast<float4*>(dst0);
+      for (int i = tid; i < (int)(plane_sz / 2); i += P::THREADS) d[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    return;
+  }
   const Placed* rb = p.rec + (size_t)b * p.n_pts;
   auto pidx = [](int yy, int zz) { return 2 * (P::al(yy & (T - 1)) + P::be(zz)) + (yy >= T ? 1 : 0); };
   Placed q;
@@ -1366,6 +1381,10 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_sin
   // splat: as the binned branch of k_plane_fwd
   const int4 rg = p.cand[(size_t)b * N + x];
   const int ncand = rg.y + rg.w;
+  if (ncand == 0) {  // no sample within reach: a zero plane, known before any load or fill
+    if (tid < 7) dstp[tid] = 0.0;
+    return;
+  }
   const Placed* rb = p.rec + (size_t)b * p.n_pts;
   const int lane = tid & 63, wave = tid >> 6;
   auto pidx = [](int yy, int zz) { return P::zs(yy >> 1, zz) * 2 + (yy & 1); };
