@@ -40,32 +40,32 @@ HBM_PEAK_GBPS = 8000.0
 # grid). Valid only for the kernel sources they were taken on: reported as
 # null once those change.
 COUNTER_TRAFFIC = {
-    "sources_sha256": "8fbe75d5a364bbb8c254f40084a85a87b2b4dc28e832f9a6901b42f043de97de",
-    "bytes": {"bin": (193.0 * 2 + 4166.0) * 1024, "plane_fwd": (16616.2 * 2 + 246273.4) * 1024,
-              "plane_inv": (266319.8 * 2 + 525878.2) * 1024,
-              "strip/g4k1r0": (297385.6 * 2 + 532480.0) * 1024,
-              "strip/g4k1r1": (296407.1 * 2 + 532480.0) * 1024,
-              "strip/g4k2r0": (249519.6 * 2 + 532480.0) * 1024,
-              "strip/g4k2r1": (249490.2 * 2 + 532480.0) * 1024,
-              "strip/g4k4r0": (182611.2 * 2 + 532480.0) * 1024,
-              "strip/g4k4r1": (182573.0 * 2 + 532480.0) * 1024,
-              "strip/g4k8r0": (150663.5 * 2 + 532480.0) * 1024,
-              "strip/g4k8r1": (150746.5 * 2 + 532480.0) * 1024,
-              "strip/g8k1r0": (387578.8 * 2 + 532480.0) * 1024,
-              "strip/g8k1r1": (387264.6 * 2 + 532480.0) * 1024,
-              "strip/g8k2r0": (256224.4 * 2 + 532480.0) * 1024,
-              "strip/g8k2r1": (256223.1 * 2 + 532480.0) * 1024,
-              "strip/g8k4r0": (189642.6 * 2 + 532480.0) * 1024,
-              "strip/g8k4r1": (189637.7 * 2 + 532480.0) * 1024,
-              "strip/g8k8r0": (156345.8 * 2 + 532480.0) * 1024,
-              "strip/g8k8r1": (156348.5 * 2 + 532480.0) * 1024},
+    "sources_sha256": "d47243be48d6491650d599345854d74bdc4ac973ef385e16042a482952ad211b",
+    "bytes": {"bin": (186.0 * 2 + 4166.2) * 1024, "plane_fwd": (16650.1 * 2 + 246446.0) * 1024,
+              "plane_inv": (266319.6 * 2 + 525968.3) * 1024,
+              "strip/g4k1r0": (297627.3 * 2 + 532480.0) * 1024,
+              "strip/g4k1r1": (295464.5 * 2 + 532480.0) * 1024,
+              "strip/g4k2r0": (249820.8 * 2 + 532480.0) * 1024,
+              "strip/g4k2r1": (249596.8 * 2 + 532480.0) * 1024,
+              "strip/g4k4r0": (182504.9 * 2 + 532480.0) * 1024,
+              "strip/g4k4r1": (182593.6 * 2 + 532480.0) * 1024,
+              "strip/g4k8r0": (150413.7 * 2 + 532480.0) * 1024,
+              "strip/g4k8r1": (150578.5 * 2 + 532480.0) * 1024,
+              "strip/g8k1r0": (387540.7 * 2 + 532480.0) * 1024,
+              "strip/g8k1r1": (387336.4 * 2 + 532480.0) * 1024,
+              "strip/g8k2r0": (256229.3 * 2 + 532480.0) * 1024,
+              "strip/g8k2r1": (256226.8 * 2 + 532480.0) * 1024,
+              "strip/g8k4r0": (189635.7 * 2 + 532480.0) * 1024,
+              "strip/g8k4r1": (189642.5 * 2 + 532480.0) * 1024,
+              "strip/g8k8r0": (156348.9 * 2 + 532480.0) * 1024,
+              "strip/g8k8r1": (156348.6 * 2 + 532480.0) * 1024},
 }
 # Wavefront VALU instructions per launch at 128^3 x 64 (rocprofv3
 # SQ_INSTS_VALU, same validity rule): against the issue rate of one VALU
 # instruction per CU per cycle they give each kernel's instruction-issue floor.
 COUNTER_VALU = {
-    "sources_sha256": "8fbe75d5a364bbb8c254f40084a85a87b2b4dc28e832f9a6901b42f043de97de",
-    "insts": {"bin": 360704, "plane_fwd": 47631848, "plane_inv": 58425344,
+    "sources_sha256": "d47243be48d6491650d599345854d74bdc4ac973ef385e16042a482952ad211b",
+    "insts": {"bin": 360704, "plane_fwd": 43650793, "plane_inv": 58425344,
               "strip/g4k1r0": 76677120,
               "strip/g4k1r1": 75412480,
               "strip/g4k2r0": 66460160,
