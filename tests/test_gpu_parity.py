@@ -205,6 +205,25 @@ def test_energy_fields_skip_empty_planes(G, n, npts, nrot):
         assert O.rel_l2(E[r], O.energy_field(uA_ref, uB_ref)) < FIELD_TOL, r
 
 
+@pytest.mark.parametrize("n,npts,nrot", [(32, 6000, 2), (64, 12000, 2), (128, 25000, 2)])
+def test_energy_fields_dense_part_many_candidate_rounds(G, n, npts, nrot):
+    """A dense moving part: every x-plane has several rounds of candidates
+    (more than one per lane of the workgroup) and wavefronts hold more hits
+    than their LDS batch, so the splat's later rounds, its batches and the
+    plane bound over all rounds are exercised against the oracle."""
+    A = _part(n, 8000 + n, 400, 1.0, 3.0)
+    B = _part(n, 8100 + n, npts, 1.0, 3.0, conf=n / 6)
+    R = synth.shoemake_rotations(8200 + n, nrot)
+    cB = B.ref_point()
+    plan = G.Plan(n, max_batch=nrot)
+    Ahat = G.ga_fft3d(plan, G.GA_R2C, G.ga_splat(plan, _dev(A.xyzr), _dev(A.w)))[0].contiguous()
+    E = G.ga_energy_fields(plan, Ahat, _dev(B.xyzr), _dev(B.w), _dev(R), cB).cpu().numpy()
+    uA_ref = O.splat(A.xyzr[:, :3].astype(np.float64), A.xyzr[:, 3], A.w, n)
+    for r in range(nrot):
+        uB_ref = O.splat(O.place(B.xyzr[:, :3], R[r], cB), B.xyzr[:, 3], B.w, n)
+        assert O.rel_l2(E[r], O.energy_field(uA_ref, uB_ref)) < FIELD_TOL, r
+
+
 def test_c1_workload_end_to_end(G):
     a = synth.config_c1()
     n = a.n
