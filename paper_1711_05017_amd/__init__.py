@@ -40,6 +40,7 @@ from .ga import (  # noqa: F401
     ga_splat,
     ga_supported_n,
 )
+from .spectra import load_spectrum, save_spectrum, skeleton_key  # noqa: F401
 
 
 def lib():
