@@ -40,32 +40,32 @@ HBM_PEAK_GBPS = 8000.0
 # grid). Valid only for the kernel sources they were taken on: reported as
 # null once those change.
 COUNTER_TRAFFIC = {
-    "sources_sha256": "d47243be48d6491650d599345854d74bdc4ac973ef385e16042a482952ad211b",
-    "bytes": {"bin": (186.0 * 2 + 4166.2) * 1024, "plane_fwd": (16650.1 * 2 + 246446.0) * 1024,
-              "plane_inv": (266319.6 * 2 + 525968.3) * 1024,
-              "strip/g4k1r0": (297627.3 * 2 + 532480.0) * 1024,
-              "strip/g4k1r1": (295464.5 * 2 + 532480.0) * 1024,
-              "strip/g4k2r0": (249820.8 * 2 + 532480.0) * 1024,
-              "strip/g4k2r1": (249596.8 * 2 + 532480.0) * 1024,
-              "strip/g4k4r0": (182504.9 * 2 + 532480.0) * 1024,
-              "strip/g4k4r1": (182593.6 * 2 + 532480.0) * 1024,
-              "strip/g4k8r0": (150413.7 * 2 + 532480.0) * 1024,
-              "strip/g4k8r1": (150578.5 * 2 + 532480.0) * 1024,
-              "strip/g8k1r0": (387540.7 * 2 + 532480.0) * 1024,
-              "strip/g8k1r1": (387336.4 * 2 + 532480.0) * 1024,
-              "strip/g8k2r0": (256229.3 * 2 + 532480.0) * 1024,
-              "strip/g8k2r1": (256226.8 * 2 + 532480.0) * 1024,
-              "strip/g8k4r0": (189635.7 * 2 + 532480.0) * 1024,
-              "strip/g8k4r1": (189642.5 * 2 + 532480.0) * 1024,
-              "strip/g8k8r0": (156348.9 * 2 + 532480.0) * 1024,
-              "strip/g8k8r1": (156348.6 * 2 + 532480.0) * 1024},
+    "sources_sha256": "d61db16b11038243e6218f35f668d3d67eb776084cf7d51d80732136f7089944",
+    "bytes": {"bin": (193.0 * 2 + 4166.0) * 1024, "plane_fwd": (16646.8 * 2 + 246460.4) * 1024,
+              "plane_inv": (266299.2 * 2 + 526652.5) * 1024,
+              "strip/g4k1r0": (296598.4 * 2 + 532480.0) * 1024,
+              "strip/g4k1r1": (295090.0 * 2 + 532480.0) * 1024,
+              "strip/g4k2r0": (249551.9 * 2 + 532480.0) * 1024,
+              "strip/g4k2r1": (249420.5 * 2 + 532480.0) * 1024,
+              "strip/g4k4r0": (182620.8 * 2 + 532480.0) * 1024,
+              "strip/g4k4r1": (182533.7 * 2 + 532480.0) * 1024,
+              "strip/g4k8r0": (150348.5 * 2 + 532480.0) * 1024,
+              "strip/g4k8r1": (150453.3 * 2 + 532480.0) * 1024,
+              "strip/g8k1r0": (387642.6 * 2 + 532480.0) * 1024,
+              "strip/g8k1r1": (387318.1 * 2 + 532480.0) * 1024,
+              "strip/g8k2r0": (256224.7 * 2 + 532480.0) * 1024,
+              "strip/g8k2r1": (256216.2 * 2 + 532480.0) * 1024,
+              "strip/g8k4r0": (189642.6 * 2 + 532480.0) * 1024,
+              "strip/g8k4r1": (189642.4 * 2 + 532480.0) * 1024,
+              "strip/g8k8r0": (156348.5 * 2 + 532480.0) * 1024,
+              "strip/g8k8r1": (156348.5 * 2 + 532480.0) * 1024},
 }
 # Wavefront VALU instructions per launch at 128^3 x 64 (rocprofv3
 # SQ_INSTS_VALU, same validity rule): against the issue rate of one VALU
 # instruction per CU per cycle they give each kernel's instruction-issue floor.
 COUNTER_VALU = {
-    "sources_sha256": "d47243be48d6491650d599345854d74bdc4ac973ef385e16042a482952ad211b",
-    "insts": {"bin": 360704, "plane_fwd": 43650793, "plane_inv": 58425344,
+    "sources_sha256": "d61db16b11038243e6218f35f668d3d67eb776084cf7d51d80732136f7089944",
+    "insts": {"bin": 360704, "plane_fwd": 43651549, "plane_inv": 54525952,
               "strip/g4k1r0": 76677120,
               "strip/g4k1r1": 75412480,
               "strip/g4k2r0": 66460160,

@@ -1521,33 +1521,31 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_inv
   PlaneTw<N> tw;
   plane_twiddles<N>(tw, table, tw_tab, l);
   __syncthreads();
-  // y: columns 1 .. N/2-1 in place. The z C2R below keeps only the real part
-  // of columns kz = 0 and kz = N/2, so both go through one transform of
-  // c = h(col0) + i h(colN/2), h(a)(k) = (a(k) + conj a(-k))/2, whose
-  // inverse is Re IFFT(col0) + i Re IFFT(colN/2).
+  // Columns kz = 0 and kz = N/2: the z C2R below keeps only the real part of
+  // both, so they go through one transform of c = h(col0) + i h(colN/2),
+  // h(a)(k) = (a(k) + conj a(-k))/2, whose inverse is Re IFFT(col0) +
+  // i Re IFFT(colN/2). c is formed in place in column 0 before the y
+  // transforms (read, barrier, write, barrier), so that every y transform
+  // loads and stores its own column alike.
+  static_assert(P::THREADS >= N, "one thread per position of column 0");
+  {
+    float2 cv = make_float2(0.f, 0.f);
+    if (tid < N) {
+      const int m = (N - tid) % N;
+      const float2 a0 = W[P::yc(tid, 0)], a1 = W[P::yc(m, 0)];
+      const float2 b0 = W[P::yc(tid, N / 2)], b1 = W[P::yc(m, N / 2)];
+      const float2 ha = make_float2(0.5f * (a0.x + a1.x), 0.5f * (a0.y - a1.y));
+      const float2 hb = make_float2(0.5f * (b0.x + b1.x), 0.5f * (b0.y - b1.y));
+      cv = make_float2(ha.x - hb.y, ha.y + hb.x);
+    }
+    __syncthreads();
+    if (tid < N) W[P::yc(tid, 0)] = cv;
+    __syncthreads();
+  }
+  // y: columns 0 .. N/2-1 in place (column 0 holds c)
   for (int it = 0; it * P::WAVES * TPW < N / 2; ++it) {
     const int t = (it * P::WAVES + wave) * TPW + lane / L;
-    if (t < N / 2) {
-      auto col = [=](int pos) { return W + P::yc(pos, t); };
-      auto ld = [&](int pos) -> float2 {
-        if (t != 0) return *col(pos);
-        const int m = (N - pos) % N;
-        const float2 a0 = W[P::yc(pos, 0)], a1 = W[P::yc(m, 0)];
-        const float2 b0 = W[P::yc(pos, N / 2)], b1 = W[P::yc(m, N / 2)];
-        const float2 ha = make_float2(0.5f * (a0.x + a1.x), 0.5f * (a0.y - a1.y));
-        const float2 hb = make_float2(0.5f * (b0.x + b1.x), 0.5f * (b0.y - b1.y));
-        return make_float2(ha.x - hb.y, ha.y + hb.x);
-      };
-      auto st = [&](int pos, float2 v) {
-        if (t != 0) {
-          *col(pos) = v;
-        } else {
-          W[P::yc(pos, 0)] = make_float2(v.x, 0.f);
-          W[P::yc(pos, N / 2)] = make_float2(v.y, 0.f);
-        }
-      };
-      fft_at<N, +1>(l, tw, col, ld, st);
-    }
+    if (t < N / 2) fft_inplace_at<N, +1>(l, tw, [=](int pos) { return W + P::yc(pos, t); });
   }
   __syncthreads();
   float* dst = out + ((size_t)b * N + x) * (size_t)N * N;
@@ -1561,7 +1559,13 @@ __global__ void __launch_bounds__(Plane<N>::THREADS, Plane<N>::MINW) k_plane_inv
       // region in the transform's own layout.
       auto ld = [&](int k) -> float2 {
         if (k < H) {
-          float2 a = W[P::yc(2 * t, k)], bb = W[P::yc(2 * t + 1, k)];
+          // k = N/2 is the imaginary part of column 0 (see above)
+          const int kk = (k == N / 2) ? 0 : k;
+          float2 a = W[P::yc(2 * t, kk)], bb = W[P::yc(2 * t + 1, kk)];
+          if (k == N / 2) {
+            a.x = a.y;
+            bb.x = bb.y;
+          }
           if (k == 0 || k == N / 2) {
             a.y = 0.f;
             bb.y = 0.f;
