@@ -40,32 +40,32 @@ HBM_PEAK_GBPS = 8000.0
 # grid). Valid only for the kernel sources they were taken on: reported as
 # null once those change.
 COUNTER_TRAFFIC = {
-    "sources_sha256": "d61db16b11038243e6218f35f668d3d67eb776084cf7d51d80732136f7089944",
-    "bytes": {"bin": (193.0 * 2 + 4166.0) * 1024, "plane_fwd": (16646.8 * 2 + 246460.4) * 1024,
-              "plane_inv": (266299.2 * 2 + 526652.5) * 1024,
-              "strip/g4k1r0": (296598.4 * 2 + 532480.0) * 1024,
-              "strip/g4k1r1": (295090.0 * 2 + 532480.0) * 1024,
-              "strip/g4k2r0": (249551.9 * 2 + 532480.0) * 1024,
-              "strip/g4k2r1": (249420.5 * 2 + 532480.0) * 1024,
-              "strip/g4k4r0": (182620.8 * 2 + 532480.0) * 1024,
-              "strip/g4k4r1": (182533.7 * 2 + 532480.0) * 1024,
-              "strip/g4k8r0": (150348.5 * 2 + 532480.0) * 1024,
-              "strip/g4k8r1": (150453.3 * 2 + 532480.0) * 1024,
-              "strip/g8k1r0": (387642.6 * 2 + 532480.0) * 1024,
-              "strip/g8k1r1": (387318.1 * 2 + 532480.0) * 1024,
-              "strip/g8k2r0": (256224.7 * 2 + 532480.0) * 1024,
-              "strip/g8k2r1": (256216.2 * 2 + 532480.0) * 1024,
-              "strip/g8k4r0": (189642.6 * 2 + 532480.0) * 1024,
+    "sources_sha256": "d376be4ec7ef4e8bfdd99d0dc9136a7802ea55d24cecb138e87c699f8565607e",
+    "bytes": {"bin": (190.0 * 2 + 4166.0) * 1024, "plane_fwd": (16634.6 * 2 + 246298.1) * 1024,
+              "plane_inv": (266299.3 * 2 + 526867.6) * 1024,
+              "strip/g4k1r0": (296647.1 * 2 + 532480.0) * 1024,
+              "strip/g4k1r1": (295175.9 * 2 + 532480.0) * 1024,
+              "strip/g4k2r0": (249645.5 * 2 + 532480.0) * 1024,
+              "strip/g4k2r1": (249616.1 * 2 + 532480.0) * 1024,
+              "strip/g4k4r0": (182556.1 * 2 + 532480.0) * 1024,
+              "strip/g4k4r1": (182550.0 * 2 + 532480.0) * 1024,
+              "strip/g4k8r0": (150590.3 * 2 + 532480.0) * 1024,
+              "strip/g4k8r1": (150712.3 * 2 + 532480.0) * 1024,
+              "strip/g8k1r0": (387539.0 * 2 + 532480.0) * 1024,
+              "strip/g8k1r1": (387453.9 * 2 + 532480.0) * 1024,
+              "strip/g8k2r0": (256224.6 * 2 + 532480.0) * 1024,
+              "strip/g8k2r1": (256222.5 * 2 + 532480.0) * 1024,
+              "strip/g8k4r0": (189639.6 * 2 + 532480.0) * 1024,
               "strip/g8k4r1": (189642.4 * 2 + 532480.0) * 1024,
-              "strip/g8k8r0": (156348.5 * 2 + 532480.0) * 1024,
-              "strip/g8k8r1": (156348.5 * 2 + 532480.0) * 1024},
+              "strip/g8k8r0": (156348.6 * 2 + 532480.0) * 1024,
+              "strip/g8k8r1": (156348.4 * 2 + 532480.0) * 1024},
 }
 # Wavefront VALU instructions per launch at 128^3 x 64 (rocprofv3
 # SQ_INSTS_VALU, same validity rule): against the issue rate of one VALU
 # instruction per CU per cycle they give each kernel's instruction-issue floor.
 COUNTER_VALU = {
-    "sources_sha256": "d61db16b11038243e6218f35f668d3d67eb776084cf7d51d80732136f7089944",
-    "insts": {"bin": 360704, "plane_fwd": 43651549, "plane_inv": 54525952,
+    "sources_sha256": "d376be4ec7ef4e8bfdd99d0dc9136a7802ea55d24cecb138e87c699f8565607e",
+    "insts": {"bin": 360704, "plane_fwd": 42674747, "plane_inv": 54525952,
               "strip/g4k1r0": 76677120,
               "strip/g4k1r1": 75412480,
               "strip/g4k2r0": 66460160,

@@ -1295,38 +1295,53 @@ __device__ __forceinline__ void plane_splat_body(const SplatParams& p, float2* _
       }
     } else {
       // C = P + i Q with P, Q the spectra of the real columns kz = 0 and N/2:
-      // P(k) = (C(k) + conj C(N-k))/2, Q(k) = -i (C(k) - conj C(N-k))/2
+      // P(k) = (C(k) + conj C(N-k))/2, Q(k) = -i (C(k) - conj C(N-k))/2.
+      // C(k) goes back to the column's slots; the split reads it there
+      // (single-translation sums: at once; spectra: after the barrier below,
+      // one thread per k, so that this wavefront does not also store the
+      // column while the others have finished).
       wave_sync();
 #pragma unroll
       for (int r = 0; r < R1; ++r) {
         r1[P::al(8 * r)] = u[0][r];
         r2[P::al(8 * r)] = u[1][r];
       }
-      wave_sync();
+      if constexpr (SINGLE) {
+        wave_sync();
 #pragma unroll
-      for (int bb = 0; bb < NB1; ++bb)
+        for (int bb = 0; bb < NB1; ++bb)
 #pragma unroll
-        for (int r = 0; r < R1; ++r) {
-          const int k = l + 8 * bb + 16 * r, m = (N - k) & (N - 1);
-          const float2 a = u[bb][r];
-          const float2 z = W[P::al((m & 7) | ((m >> 4) << 3)) + (((m >> 3) & 1) ? b2 : b1)];
-          const float2 pk = make_float2(0.5f * (a.x + z.x), 0.5f * (a.y - z.y));
-          const float2 qk = make_float2(0.5f * (a.y + z.y), -0.5f * (a.x - z.x));
-          if constexpr (SINGLE) {
+          for (int r = 0; r < R1; ++r) {
+            const int k = l + 8 * bb + 16 * r, m = (N - k) & (N - 1);
+            const float2 a = u[bb][r];
+            const float2 z = W[P::al((m & 7) | ((m >> 4) << 3)) + (((m >> 3) & 1) ? b2 : b1)];
+            const float2 pk = make_float2(0.5f * (a.x + z.x), 0.5f * (a.y - z.y));
+            const float2 qk = make_float2(0.5f * (a.y + z.y), -0.5f * (a.x - z.x));
             // (k, kz = 0) and (k, kz = N/2), weight 1, omega_z = 0
             const float2* ap = AXp + (size_t)k * H;
             const float2 ph0 = tabc[(k * ty) & (N - 1)], ph1 = tabc[(k * ty + T * tz) & (N - 1)];
             acc.add(pk, cmul(ap[0], ph0), cmul(ap[plane_sz * N], ph0), omega_of<N>(k));
             acc.add(qk, cmul(ap[T], ph1), cmul(ap[plane_sz * N + T], ph1), omega_of<N>(k));
-          } else {
-            dst0[(size_t)k * H] = pk;
-            dst0[(size_t)k * H + T] = qk;
           }
-        }
-      if constexpr (SINGLE) acc.fold(pass, 1.f, 0.f, s1);
+        acc.fold(pass, 1.f, 0.f, s1);
+      }
     }
   }
-  if constexpr (SINGLE) block_sum7<P::THREADS>(acc, red, dstp);
+  if constexpr (SINGLE) {
+    block_sum7<P::THREADS>(acc, red, dstp);
+  } else {
+    static_assert(P::THREADS >= N, "one thread per k of column 0");
+    __syncthreads();
+    if (tid < N) {
+      // C(q) of column 0 sits at row (q & 7) | ((q >> 4) << 3) of the slots
+      // of kz = 0 (bit 3 of q clear) or kz = N/2 (set)
+      auto slot = [](int q) { return P::al((q & 7) | ((q >> 4) << 3)) + (((q >> 3) & 1) ? P::be(T) : P::be(0)); };
+      const int k = tid, m = (N - k) & (N - 1);
+      const float2 a = W[slot(k)], z = W[slot(m)];
+      dst0[(size_t)k * H] = make_float2(0.5f * (a.x + z.x), 0.5f * (a.y - z.y));
+      dst0[(size_t)k * H + T] = make_float2(0.5f * (a.y + z.y), -0.5f * (a.x - z.x));
+    }
+  }
 }
 
 // grid = (N planes, batch); block = 512. Pass 1 from binned samples: the

@@ -91,3 +91,24 @@ def test_y_transforms_read_exactly_the_z_outputs_they_own():
         k1, k2 = c, (T if c == 0 else N - c)
         got = {z_out[al(l) + al(8 * r) + be(k)] for l in range(L) for r in range(8) for k in (k1, k2)}
         assert got == {(t, k) for t in range(T) for k in (k1, k2)}
+
+
+def test_column_zero_split_after_the_barrier_reads_what_the_transform_stored():
+    """Spectra path: the column-0 transform stores C(q), q = l + 8 bb + 16 r,
+    back in its slots; after the workgroup barrier thread k < N splits the
+    packed column from C(k) and C(N - k), read at slot(q). Every such read is
+    in bounds and finds the C(q) it wants, and each q has a slot of its own."""
+    stored = {}
+    for l in range(L):
+        for bb in range(2):
+            for r in range(8):
+                q = l + 8 * bb + 16 * r
+                stored[al(l) + al(8 * r) + (be(T) if bb else be(0))] = q
+    assert len(stored) == N
+
+    def slot(q):
+        return al((q & 7) | ((q >> 4) << 3)) + (be(T) if (q >> 3) & 1 else be(0))
+
+    for k in range(N):
+        for q in (k, (N - k) & (N - 1)):
+            assert 0 <= slot(q) < SIZE and stored[slot(q)] == q
