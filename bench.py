@@ -40,32 +40,32 @@ HBM_PEAK_GBPS = 8000.0
 # grid). Valid only for the kernel sources they were taken on: reported as
 # null once those change.
 COUNTER_TRAFFIC = {
-    "sources_sha256": "d376be4ec7ef4e8bfdd99d0dc9136a7802ea55d24cecb138e87c699f8565607e",
-    "bytes": {"bin": (190.0 * 2 + 4166.0) * 1024, "plane_fwd": (16634.6 * 2 + 246298.1) * 1024,
-              "plane_inv": (266299.3 * 2 + 526867.6) * 1024,
-              "strip/g4k1r0": (296647.1 * 2 + 532480.0) * 1024,
-              "strip/g4k1r1": (295175.9 * 2 + 532480.0) * 1024,
-              "strip/g4k2r0": (249645.5 * 2 + 532480.0) * 1024,
-              "strip/g4k2r1": (249616.1 * 2 + 532480.0) * 1024,
-              "strip/g4k4r0": (182556.1 * 2 + 532480.0) * 1024,
-              "strip/g4k4r1": (182550.0 * 2 + 532480.0) * 1024,
-              "strip/g4k8r0": (150590.3 * 2 + 532480.0) * 1024,
-              "strip/g4k8r1": (150712.3 * 2 + 532480.0) * 1024,
-              "strip/g8k1r0": (387539.0 * 2 + 532480.0) * 1024,
-              "strip/g8k1r1": (387453.9 * 2 + 532480.0) * 1024,
-              "strip/g8k2r0": (256224.6 * 2 + 532480.0) * 1024,
-              "strip/g8k2r1": (256222.5 * 2 + 532480.0) * 1024,
-              "strip/g8k4r0": (189639.6 * 2 + 532480.0) * 1024,
-              "strip/g8k4r1": (189642.4 * 2 + 532480.0) * 1024,
-              "strip/g8k8r0": (156348.6 * 2 + 532480.0) * 1024,
-              "strip/g8k8r1": (156348.4 * 2 + 532480.0) * 1024},
+    "sources_sha256": "bb7813aa8059a70a539d26695cd2846d7692e8ee9bd76e952819c542b05ff951",
+    "bytes": {"bin": (193.0 * 2 + 4166.0) * 1024, "plane_fwd": (16631.4 * 2 + 246299.3) * 1024,
+              "plane_inv": (266292.7 * 2 + 526589.1) * 1024,
+              "strip/g4k1r0": (297388.3 * 2 + 532480.0) * 1024,
+              "strip/g4k1r1": (295405.9 * 2 + 532480.0) * 1024,
+              "strip/g4k2r0": (249437.3 * 2 + 532480.0) * 1024,
+              "strip/g4k2r1": (249530.7 * 2 + 532480.0) * 1024,
+              "strip/g4k4r0": (182527.1 * 2 + 532480.0) * 1024,
+              "strip/g4k4r1": (182555.1 * 2 + 532480.0) * 1024,
+              "strip/g4k8r0": (150374.1 * 2 + 532480.0) * 1024,
+              "strip/g4k8r1": (150584.4 * 2 + 532480.0) * 1024,
+              "strip/g8k1r0": (387597.9 * 2 + 532480.0) * 1024,
+              "strip/g8k1r1": (387389.7 * 2 + 532480.0) * 1024,
+              "strip/g8k2r0": (256227.0 * 2 + 532480.0) * 1024,
+              "strip/g8k2r1": (256224.9 * 2 + 532480.0) * 1024,
+              "strip/g8k4r0": (189642.5 * 2 + 532480.0) * 1024,
+              "strip/g8k4r1": (189635.5 * 2 + 532480.0) * 1024,
+              "strip/g8k8r0": (156343.9 * 2 + 532480.0) * 1024,
+              "strip/g8k8r1": (156348.5 * 2 + 532480.0) * 1024},
 }
 # Wavefront VALU instructions per launch at 128^3 x 64 (rocprofv3
 # SQ_INSTS_VALU, same validity rule): against the issue rate of one VALU
 # instruction per CU per cycle they give each kernel's instruction-issue floor.
 COUNTER_VALU = {
-    "sources_sha256": "d376be4ec7ef4e8bfdd99d0dc9136a7802ea55d24cecb138e87c699f8565607e",
-    "insts": {"bin": 360704, "plane_fwd": 42674747, "plane_inv": 54525952,
+    "sources_sha256": "bb7813aa8059a70a539d26695cd2846d7692e8ee9bd76e952819c542b05ff951",
+    "insts": {"bin": 360704, "plane_fwd": 42674710, "plane_inv": 54525952,
               "strip/g4k1r0": 76677120,
               "strip/g4k1r1": 75412480,
               "strip/g4k2r0": 66460160,

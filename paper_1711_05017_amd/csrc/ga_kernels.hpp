@@ -538,17 +538,20 @@ __device__ __forceinline__ void plane_forward_out(float2* W, const TW& tw, float
     }
   }
   __syncthreads();
-  // y: columns 1 .. N/2-1 in place; column 0 carries the real columns kz = 0
-  // (real part) and kz = N/2 (imaginary part) and is split afterwards.
+  // Column 0 carries the real columns kz = 0 (real part) and kz = N/2
+  // (imaginary part) through one y transform. It is packed here, one thread
+  // per row (each touches only its own row's slots), and split after all y
+  // transforms, so that no wavefront runs the packed column's loads and its
+  // split beside a plain column under its execution mask.
+  static_assert(P::THREADS >= N, "one thread per row of column 0");
+  if (tid < N) W[P::yc(tid, 0)].y = W[P::yc(tid, N / 2)].x;
+  __syncthreads();
+  // y: columns 0 .. N/2-1 in place
   for (int it = 0; it * P::WAVES * TPW < N / 2; ++it) {
     const int t = (it * P::WAVES + wave) * TPW + lane / L;
     if (t < N / 2) {
       auto col = [=](int pos) { return W + P::yc(pos, t); };
-      auto ld = [&](int pos) -> float2 {
-        float2 v = *col(pos);
-        if (t == 0) v.y = W[P::yc(pos, N / 2)].x;
-        return v;
-      };
+      auto ld = [&](int pos) -> float2 { return *col(pos); };
       auto st = [&](int pos, float2 v) {
         if (!DIRECT || t == 0) {
           *col(pos) = v;
@@ -558,33 +561,32 @@ __device__ __forceinline__ void plane_forward_out(float2* W, const TW& tw, float
         if (dst1) dst1[(size_t)pos * H + t] = make_float2(v.x * s1, v.y * s1);
       };
       fft_at<N, -1>(l, tw, col, ld, st);
-      if (t == 0) {
-        // C = A + i B with A, B the spectra of the real columns kz = 0 and
-        // kz = N/2: B(k) = (C(k) - conj C(N-k))/(2i) to column N/2 (not read
-        // here), then A(k) = C(k) - i B(k), position by position.
-        for (int k = l; k < N; k += L) {
-          const float2 a = W[P::yc(k, 0)];
-          const float2 z = W[P::yc((N - k) % N, 0)];
-          W[P::yc(k, N / 2)] = make_float2(0.5f * (a.y + z.y), -0.5f * (a.x - z.x));
-        }
-        wave_sync();
-        for (int k = l; k < N; k += L) {
-          const float2 c = W[P::yc(k, 0)];
-          const float2 bb = W[P::yc(k, N / 2)];
-          const float2 a = make_float2(c.x + bb.y, c.y - bb.x);
-          if constexpr (DIRECT) {
-            dst0[(size_t)k * H] = a;
-            dst0[(size_t)k * H + N / 2] = bb;
-            if (dst1) {
-              dst1[(size_t)k * H] = make_float2(a.x * s1, a.y * s1);
-              dst1[(size_t)k * H + N / 2] = make_float2(bb.x * s1, bb.y * s1);
-            }
-          } else {
-            W[P::yc(k, 0)] = a;
-          }
-        }
-        wave_sync();
+    }
+  }
+  __syncthreads();
+  // C = A + i B with A, B the spectra of the real columns kz = 0 and kz = N/2:
+  // B(k) = (C(k) - conj C(N-k))/(2i), A(k) = C(k) - i B(k), one thread per k
+  float2 a = make_float2(0.f, 0.f), bb = a;
+  if (tid < N) {
+    const int k = tid;
+    const float2 c = W[P::yc(k, 0)];
+    const float2 z = W[P::yc((N - k) % N, 0)];
+    bb = make_float2(0.5f * (c.y + z.y), -0.5f * (c.x - z.x));
+    a = make_float2(c.x + bb.y, c.y - bb.x);
+    if constexpr (DIRECT) {
+      dst0[(size_t)k * H] = a;
+      dst0[(size_t)k * H + N / 2] = bb;
+      if (dst1) {
+        dst1[(size_t)k * H] = make_float2(a.x * s1, a.y * s1);
+        dst1[(size_t)k * H + N / 2] = make_float2(bb.x * s1, bb.y * s1);
       }
+    }
+  }
+  if constexpr (!DIRECT) {
+    __syncthreads();  // every C(N-k) is read before column 0 is overwritten
+    if (tid < N) {
+      W[P::yc(tid, 0)] = a;
+      W[P::yc(tid, N / 2)] = bb;
     }
   }
   __syncthreads();
